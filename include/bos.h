@@ -1,0 +1,191 @@
+/*
+ * bos.h — C ABI of libbos, bucket oblivious random permutation (ORP) and bucket
+ * oblivious sort on AMD MI355X (gfx950).
+ *
+ * Method: Asharov, Chan, Nayak, Pass, Ren, Shi, "Bucket Oblivious Sort: An
+ * Extremely Simple Oblivious Sort" (SOSA 2020).  The problem statement is that
+ * of Section 1 and Section 2 (functionalities "oblivious sort" and "oblivious
+ * permutation"): sort or permute n records held in untrusted memory so that the
+ * sequence of memory addresses touched reveals nothing beyond n.  Here HBM and
+ * LDS play the untrusted memory; every HBM and LDS address of the routing
+ * phase is a function of (n, Z, levels per pass) only.  The strip of dummies
+ * reveals the bin loads, as Lemma 3.3 allows, and the final comparison sort of
+ * bos_sort reveals only what a comparison sort of a uniformly permuted array
+ * reveals (Section 3.3).
+ *
+ * Records: little-endian array-of-structs {key, payload}, both unsigned, of
+ * 4 + 4 bytes (BOS_REC_U32U32) or 8 + 8 bytes (BOS_REC_U64U64).  Record order is
+ * unsigned lexicographic on (key, payload).
+ *
+ * Ownership: the caller owns every buffer.  `in`, `out` and `ws` are device
+ * pointers (hipMalloc'd or torch CUDA tensors), at least 16-byte aligned;
+ * `in` and `out` must not overlap each other or `ws`.  The library allocates no
+ * device memory on these calls; it keeps only small host-side caches (captured
+ * graphs of the batched path), released by bos_release_cache().
+ *
+ * Streams: `stream` is a hipStream_t (NULL = legacy default stream).  Work is
+ * stream-ordered.  With BOS_SYNC (the default when params is NULL) the call
+ * synchronizes `stream` after each attempt to read the overflow status and
+ * retries on overflow; without it the call enqueues one attempt and returns,
+ * leaving the status on the device.
+ *
+ * Errors: every entry point returns a bos_status; no exception crosses the ABI.
+ * On any status other than BOS_OK the content of `out` is unspecified.
+ */
+#ifndef BOS_H
+#define BOS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BOS_OK = 0,
+  BOS_ERR_INVALID_ARG = 1, /* bad record type, null pointer, Z not supported, n too large */
+  BOS_ERR_OVERFLOW = 2,    /* a bucket overflowed in every attempt (Algorithm 3.1 abort) */
+  BOS_ERR_WORKSPACE = 3,   /* ws NULL or smaller than bos_workspace_bytes() */
+  BOS_ERR_HIP = 4,         /* a HIP runtime call failed */
+  BOS_ERR_INSECURE_Z = 5,  /* log2 of the Lemma 3.2 failure bound exceeds -min_security_bits */
+  BOS_ERR_UNSUPPORTED = 6  /* no GPU, or a parameter combination the kernels do not cover */
+} bos_status;
+
+typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
+
+/* flags */
+#define BOS_SYNC 1u        /* synchronize and retry on overflow inside the call */
+
+typedef struct {
+  uint64_t seed;              /* Philox key: labels and per-bin permutation keys */
+  uint32_t z;                 /* bucket capacity Z (Algorithm 3.1); power of two in
+                                 [8, 2048]; 0 = 512, the paper's choice */
+  uint32_t k;                 /* butterfly levels fused per pass; 0 = planner's choice */
+  uint32_t tile;              /* records per tile of the final sort; 0 = default */
+  uint32_t max_retries;       /* extra attempts after an overflow (default 3) */
+  uint32_t min_security_bits; /* reject Z when log2(B log2 B e^(-Z/6)) > -bits;
+                                 0 disables the check (default 80) */
+  uint32_t flags;             /* BOS_SYNC */
+} bos_params;
+
+typedef struct {
+  uint32_t attempts;              /* attempts run (1 = no overflow) */
+  uint32_t z, k, tile;            /* parameters used */
+  uint32_t levels;                /* L = log2 B */
+  uint32_t passes;                /* HBM passes of the routing phase */
+  int32_t first_overflow_level;   /* first overflowing MergeSplit (level i, pair j)
+                                     of the last failed attempt; -1 if none */
+  int32_t reserved;
+  int64_t first_overflow_pair;
+  uint64_t buckets;               /* B */
+  uint64_t algorithmic_bytes;     /* HBM bytes the method must move in the last attempt */
+} bos_report;
+
+typedef struct {
+  const void* in;   /* device, n records */
+  void* out;        /* device, n records */
+  uint64_t n;
+  uint64_t seed;
+} bos_instance;
+
+/* Fill *p with the defaults listed above. */
+void bos_default_params(bos_params* p);
+
+/* Device workspace (bytes) that bos_orp / bos_sort need for n records.
+ * Returns 0 when the arguments are invalid. */
+size_t bos_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p);
+
+/* Bucket ORP (Algorithm 3.1 followed by Section 3.2): out = in permuted by a
+ * uniformly random permutation drawn from `seed`.  The output is a deterministic
+ * function of (in, n, seed, Z) and does not depend on k or tile.  n may be 0. */
+bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
+                   void* ws, size_t ws_bytes, void* stream, bos_report* rep /* host, nullable */);
+
+/* Bucket oblivious sort (Section 3.3): the ORP's bin assignment, a per-bin
+ * oblivious sort, then a non-oblivious comparison (merge) sort.  out = in sorted
+ * by (key, payload); the output does not depend on seed, Z, k or tile. */
+bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
+                    void* ws, size_t ws_bytes, void* stream, bos_report* rep);
+
+/* Workspace for bos_sort_batched over `count` instances of the given sizes. */
+size_t bos_batched_workspace_bytes(const uint64_t* n, uint32_t count, bos_rec rec,
+                                   const bos_params* p);
+
+/* Many independent bucket oblivious sorts (Section 3.3) of uneven sizes in one
+ * pass-major launch sequence, captured once into a hipGraph per batch shape and
+ * replayed afterwards.  inst: host array of `count` descriptors (device in/out
+ * pointers, n, seed).  d_status: device array of `count` uint32 receiving
+ * BOS_OK or BOS_ERR_OVERFLOW per instance of the last attempt.  With BOS_SYNC
+ * the call retries overflowing instances (one at a time) and returns the worst
+ * status; rep (nullable) receives totals. */
+bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec rec,
+                            const bos_params* p, void* ws, size_t ws_bytes, void* stream,
+                            uint32_t* d_status, bos_report* rep);
+
+/* Oblivious bitonic sort (Batcher) of the same records by (key, payload): the
+ * GPU baseline the bucket sort is measured against.  ws: bos_bitonic_workspace_bytes. */
+size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec);
+bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Drop cached graphs and plans. */
+void bos_release_cache(void);
+
+/* Static text for a status code. */
+const char* bos_status_string(bos_status s);
+
+/* ---- test and measurement hooks (not part of the method) ---------------- */
+
+/* Run one attempt of the routing phase only (Algorithm 3.1) and copy the slot
+ * arrays at every pass boundary to host memory: recs_host[(P+1) * B * Z * rec],
+ * tags_host[(P+1) * B * Z] (tag = label or 0xFFFFFFFF for a dummy), and the
+ * level index of every boundary to levels_host[P+1].  Bucket contents are
+ * sets: the order of slots inside a bucket is the network's, not the paper's.
+ * Synchronizes `stream`.  Returns BOS_ERR_OVERFLOW with *ovf_level / *ovf_pair
+ * set when the attempt overflows. */
+bos_status bos_debug_levels(const void* in, uint64_t n, bos_rec rec, const bos_params* p,
+                            uint32_t attempt, void* ws, size_t ws_bytes, void* stream,
+                            void* recs_host, uint32_t* tags_host, uint32_t* levels_host,
+                            int32_t* ovf_level, int64_t* ovf_pair);
+
+/* Labels of attempt `attempt` for elements 0..n-1 computed by the device
+ * generator, written to labels_dev (device, n uint32). */
+bos_status bos_debug_labels(uint64_t n, uint32_t levels, uint64_t seed, uint32_t attempt,
+                            uint32_t* labels_dev, void* stream);
+
+/* Per-launch timing.  When enabled, every kernel launch of bos_orp, bos_sort,
+ * bos_sort_batched and bos_bitonic_sort is bracketed by two HIP events on the
+ * launch's stream.  bos_profile_read() waits for the recorded events, copies
+ * up to `cap` records (oldest first) and clears the log; it returns the number
+ * of records that were logged.  Not thread-safe; meant for benchmarks. */
+typedef enum {
+  BOS_K_ROUTE_FIRST = 1,  /* first routing pass: input read, labels, levels */
+  BOS_K_ROUTE_MID = 2,    /* middle routing pass: slot arrays in and out */
+  BOS_K_ROUTE_LAST = 3,   /* last routing pass: levels, per-bin finish, strip */
+  BOS_K_ROUTE_SINGLE = 4, /* first and last pass at once (L <= k) */
+  BOS_K_SORT_TILE = 5,    /* comparison sort: tile sort */
+  BOS_K_SORT_MERGE = 6,   /* comparison sort: one merge pass */
+  BOS_K_BITONIC_TILE = 7, /* bitonic baseline: local phases */
+  BOS_K_BITONIC_GLOBAL = 8,
+  BOS_K_BITONIC_TAIL = 9,
+  BOS_K_OTHER = 10
+} bos_kernel_kind;
+typedef struct {
+  uint32_t kind;     /* bos_kernel_kind */
+  uint32_t index;    /* pass index within its phase */
+  float ms;          /* elapsed time between the two events */
+  uint32_t reserved;
+  uint64_t bytes;    /* algorithmic HBM bytes of the launch */
+} bos_launch_time;
+void bos_profile_enable(int on);
+uint32_t bos_profile_read(bos_launch_time* out, uint32_t cap);
+
+/* Number of passes and levels per pass the planner picks (passes_out[0] =
+ * P, passes_out[1 + t] = levels of pass t, up to 32 passes). */
+bos_status bos_plan(uint64_t n, bos_rec rec, const bos_params* p, uint64_t* buckets,
+                    uint32_t* levels, uint32_t* passes_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

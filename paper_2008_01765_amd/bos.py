@@ -1,0 +1,304 @@
+"""Python binding of libbos (include/bos.h): argument marshalling only.
+
+Every step of the method runs in the gfx950 kernels of libbos.so; this module
+turns torch CUDA tensors into device pointers, sizes workspaces and maps status
+codes to exceptions.  There is no CPU fallback: if libbos.so is missing or no
+GPU is present the calls raise.
+
+Record tensors have shape (n, 2) on a CUDA device: int32 columns for 8-byte
+records {u32 key, u32 payload}, int64 columns for 16-byte records
+{u64 key, u64 payload}; the bits are taken as unsigned.
+"""
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbos.so")
+
+OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED = range(7)
+SYNC = 1
+
+
+class BosError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("z", C.c_uint32), ("k", C.c_uint32), ("tile", C.c_uint32),
+                ("max_retries", C.c_uint32), ("min_security_bits", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("attempts", C.c_uint32), ("z", C.c_uint32), ("k", C.c_uint32), ("tile", C.c_uint32),
+                ("levels", C.c_uint32), ("passes", C.c_uint32), ("first_overflow_level", C.c_int32),
+                ("reserved", C.c_int32), ("first_overflow_pair", C.c_int64), ("buckets", C.c_uint64),
+                ("algorithmic_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Instance(C.Structure):
+    _fields_ = [("in_", C.c_void_p), ("out", C.c_void_p), ("n", C.c_uint64), ("seed", C.c_uint64)]
+
+
+class LaunchTime(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("index", C.c_uint32), ("ms", C.c_float), ("reserved", C.c_uint32),
+                ("bytes", C.c_uint64)]
+
+
+KERNEL_KINDS = {1: "route_first", 2: "route_mid", 3: "route_last", 4: "route_single", 5: "sort_tile",
+                6: "sort_merge", 7: "bitonic_tile", 8: "bitonic_global", 9: "bitonic_tail", 10: "other"}
+
+EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "bos_batched_workspace_bytes",
+           "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
+           "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
+           "bos_profile_read"]
+
+_lib = None
+
+
+def lib():
+    """Load libbos.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbos.so is not built; run python -m paper_2008_01765_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, R = C.POINTER(Params), C.POINTER(Report)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        L.bos_default_params.argtypes = [P]
+        L.bos_default_params.restype = None
+        L.bos_workspace_bytes.argtypes = [u64, C.c_int, P]
+        L.bos_workspace_bytes.restype = C.c_size_t
+        for fn in (L.bos_orp, L.bos_sort):
+            fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, R]
+            fn.restype = C.c_int
+        L.bos_batched_workspace_bytes.argtypes = [C.POINTER(u64), u32, C.c_int, P]
+        L.bos_batched_workspace_bytes.restype = C.c_size_t
+        L.bos_sort_batched.argtypes = [C.POINTER(Instance), u32, C.c_int, P, vp, C.c_size_t, vp, vp, R]
+        L.bos_sort_batched.restype = C.c_int
+        L.bos_bitonic_workspace_bytes.argtypes = [u64, C.c_int]
+        L.bos_bitonic_workspace_bytes.restype = C.c_size_t
+        L.bos_bitonic_sort.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
+        L.bos_bitonic_sort.restype = C.c_int
+        L.bos_release_cache.argtypes = []
+        L.bos_release_cache.restype = None
+        L.bos_status_string.argtypes = [C.c_int]
+        L.bos_status_string.restype = C.c_char_p
+        L.bos_debug_levels.argtypes = [vp, u64, C.c_int, P, u32, vp, C.c_size_t, vp, vp, vp, vp,
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.bos_debug_levels.restype = C.c_int
+        L.bos_debug_labels.argtypes = [u64, u32, u64, u32, vp, vp]
+        L.bos_debug_labels.restype = C.c_int
+        L.bos_plan.argtypes = [u64, C.c_int, P, C.POINTER(u64), C.POINTER(u32), C.POINTER(u32)]
+        L.bos_plan.restype = C.c_int
+        L.bos_profile_enable.argtypes = [C.c_int]
+        L.bos_profile_enable.restype = None
+        L.bos_profile_read.argtypes = [C.POINTER(LaunchTime), u32]
+        L.bos_profile_read.restype = u32
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        raise BosError(st, "libbos: " + lib().bos_status_string(st).decode())
+
+
+def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True):
+    p = Params()
+    lib().bos_default_params(C.byref(p))
+    p.seed = seed & 0xFFFFFFFFFFFFFFFF
+    p.z, p.k, p.tile = z, k, tile
+    p.max_retries = max_retries
+    p.min_security_bits = min_security_bits
+    p.flags = SYNC if sync else 0
+    return p
+
+
+def rec_bytes(t):
+    if t.dim() != 2 or t.shape[1] != 2 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("records must be a contiguous (n, 2) CUDA tensor")
+    if t.dtype == torch.int32:
+        return 8
+    if t.dtype == torch.int64:
+        return 16
+    raise ValueError("records must be int32 (8-byte) or int64 (16-byte) pairs")
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+_ws_cache = {}
+
+
+def workspace(nbytes, device=None):
+    """A cached device byte buffer of at least nbytes."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    buf = _ws_cache.get(dev)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(dev, None)
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        _ws_cache[dev] = buf
+    return buf
+
+
+def release_workspaces():
+    _ws_cache.clear()
+    lib().bos_release_cache()
+
+
+def workspace_bytes(n, rec, p):
+    nb = lib().bos_workspace_bytes(n, rec, C.byref(p))
+    if nb == 0:
+        raise BosError(INVALID_ARG, "libbos: no workspace size for these arguments")
+    return nb
+
+
+def _run(fn, t, p, out, stream):
+    rec = rec_bytes(t)
+    n = t.shape[0]
+    if out is None:
+        out = torch.empty_like(t)
+    ws = workspace(workspace_bytes(n, rec, p), t.device)
+    rep = Report()
+    st = fn(C.c_void_p(t.data_ptr()), C.c_void_p(out.data_ptr()), n, rec, C.byref(p),
+            C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream), C.byref(rep))
+    _check(st)
+    return out, rep.as_dict()
+
+
+def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stream=None, report=False):
+    """Bucket ORP of the records in t (Section 3.2)."""
+    p = params(seed, z, k, 0, max_retries, min_security_bits)
+    o, rep = _run(lib().bos_orp, t, p, out, stream)
+    return (o, rep) if report else o
+
+
+def sort(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
+         report=False):
+    """Bucket oblivious sort of the records in t (Section 3.3)."""
+    p = params(seed, z, k, tile, max_retries, min_security_bits)
+    o, rep = _run(lib().bos_sort, t, p, out, stream)
+    return (o, rep) if report else o
+
+
+def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, outs=None,
+                 stream=None, report=False):
+    """Bucket oblivious sort of every tensor in `tensors` (same record type)."""
+    if not tensors:
+        return []
+    rec = rec_bytes(tensors[0])
+    for t in tensors:
+        if rec_bytes(t) != rec:
+            raise ValueError("all instances must use the same record type")
+    if outs is None:
+        outs = [torch.empty_like(t) for t in tensors]
+    p = params(0, z, k, tile, max_retries, min_security_bits)
+    cnt = len(tensors)
+    arr = (Instance * cnt)()
+    ns = (C.c_uint64 * cnt)()
+    for i, (t, o, s) in enumerate(zip(tensors, outs, seeds)):
+        arr[i].in_ = t.data_ptr()
+        arr[i].out = o.data_ptr()
+        arr[i].n = t.shape[0]
+        arr[i].seed = s & 0xFFFFFFFFFFFFFFFF
+        ns[i] = t.shape[0]
+    nb = lib().bos_batched_workspace_bytes(ns, cnt, rec, C.byref(p))
+    ws = workspace(nb, tensors[0].device)
+    dstat = torch.zeros(cnt, dtype=torch.int32, device=tensors[0].device)
+    rep = Report()
+    st = lib().bos_sort_batched(arr, cnt, rec, C.byref(p), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream(stream), C.c_void_p(dstat.data_ptr()), C.byref(rep))
+    _check(st)
+    return (outs, rep.as_dict()) if report else outs
+
+
+def bitonic_sort(t, out=None, stream=None):
+    """Oblivious bitonic sort of the records in t (the GPU baseline)."""
+    rec = rec_bytes(t)
+    n = t.shape[0]
+    if out is None:
+        out = torch.empty_like(t)
+    nb = lib().bos_bitonic_workspace_bytes(n, rec)
+    ws = workspace(nb, t.device)
+    _check(lib().bos_bitonic_sort(C.c_void_p(t.data_ptr()), C.c_void_p(out.data_ptr()), n, rec,
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return out
+
+
+def profile_enable(on=True):
+    """Bracket every kernel launch with HIP events (see profile_read)."""
+    lib().bos_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """Per-launch records logged since the last read: list of dicts with kind,
+    index, ms and algorithmic bytes."""
+    cap = 1 << 16
+    buf = (LaunchTime * cap)()
+    cnt = lib().bos_profile_read(buf, cap)
+    return [{"kind": KERNEL_KINDS.get(buf[i].kind, str(buf[i].kind)), "index": buf[i].index,
+             "ms": buf[i].ms, "bytes": buf[i].bytes} for i in range(min(cnt, cap))]
+
+
+def plan(n, rec, z=0, k=0, tile=0, min_security_bits=80):
+    p = params(0, z, k, tile, 3, min_security_bits)
+    b, l = C.c_uint64(), C.c_uint32()
+    passes = (C.c_uint32 * 33)()
+    _check(lib().bos_plan(n, rec, C.byref(p), C.byref(b), C.byref(l), passes))
+    return {"buckets": b.value, "levels": l.value, "passes": list(passes[1:1 + passes[0]])}
+
+
+def debug_labels(n, levels, seed, attempt=0, device="cuda"):
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    _check(lib().bos_debug_labels(n, levels, seed & 0xFFFFFFFFFFFFFFFF, attempt, C.c_void_p(out.data_ptr()),
+                                  _stream(None)))
+    torch.cuda.synchronize()
+    return out[:n]
+
+
+def debug_levels(t, seed=0, z=0, k=0, attempt=0, min_security_bits=0):
+    """Slot arrays at every pass boundary of one attempt (host numpy arrays)."""
+    import numpy as np
+    rec = rec_bytes(t)
+    n = t.shape[0]
+    p = params(seed, z, k, 0, 0, min_security_bits)
+    pl = plan(n, rec, z=z, k=k, min_security_bits=min_security_bits)
+    B, Z = pl["buckets"], (z or 512)
+    P = len(pl["passes"])
+    dt = np.uint32 if rec == 8 else np.uint64
+    recs = np.zeros((P + 1, B, Z, 2), dtype=dt)
+    tags = np.zeros((P + 1, B, Z), dtype=np.uint32)
+    lv = np.zeros(P + 1, dtype=np.uint32)
+    ws = workspace(workspace_bytes(n, rec, p), t.device)
+    ol, op = C.c_int32(), C.c_int64()
+    st = lib().bos_debug_levels(C.c_void_p(t.data_ptr()), n, rec, C.byref(p), attempt, C.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream(None), recs.ctypes.data, tags.ctypes.data, lv.ctypes.data,
+                                C.byref(ol), C.byref(op))
+    if st not in (OK, OVERFLOW):
+        _check(st)
+    # boundaries 1..P-1 follow passes 0..P-2 (the last pass strips instead)
+    return {"rc": st, "recs": recs[:P], "tags": tags[:P], "levels": lv[:P], "overflow": (ol.value, op.value)}
+
+
+def to_numpy(t):
+    """Records of a CUDA tensor as an unsigned numpy array (n, 2)."""
+    import numpy as np
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a.view(np.uint64)
+
+
+def from_numpy(a, device="cuda"):
+    """An unsigned numpy record array (n, 2) as a CUDA tensor."""
+    import numpy as np
+    a = np.ascontiguousarray(a)
+    v = a.view(np.int32) if a.dtype == np.uint32 else a.view(np.int64)
+    return torch.from_numpy(v).to(device)

@@ -1,0 +1,108 @@
+// bos_common.h — device-side building blocks shared by the gfx950 kernels of
+// libbos: record types and comparisons, the Philox4x64-10 generator, and the
+// argument blocks of the routing kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bos {
+
+constexpr uint32_t kDummyTag = 0xFFFFFFFFu;  // tag of a dummy slot; real tags are labels < 2^31
+constexpr uint64_t kNoOverflow = ~0ull;      // status word when no MergeSplit overflowed
+constexpr int kMaxThreads = 512;             // threads per routing block
+
+// Record of BOS_REC_U32U32 (8 bytes) or BOS_REC_U64U64 (16 bytes).
+template <int R> struct RecOf;
+template <> struct RecOf<8> { using T = uint2; };
+template <> struct RecOf<16> { using T = uint4; };
+
+__device__ __forceinline__ uint64_t key_of(uint2 r) { return r.x; }
+__device__ __forceinline__ uint64_t pay_of(uint2 r) { return r.y; }
+__device__ __forceinline__ uint64_t key_of(uint4 r) { return uint64_t(r.x) | (uint64_t(r.y) << 32); }
+__device__ __forceinline__ uint64_t pay_of(uint4 r) { return uint64_t(r.z) | (uint64_t(r.w) << 32); }
+
+// Unsigned lexicographic order on (key, payload).
+__device__ __forceinline__ bool rec_less(uint2 a, uint2 b) {
+  const uint64_t ka = (uint64_t(a.x) << 32) | a.y, kb = (uint64_t(b.x) << 32) | b.y;
+  return ka < kb;
+}
+__device__ __forceinline__ bool rec_less(uint4 a, uint4 b) {
+  const uint64_t ka = key_of(a), kb = key_of(b);
+  return ka < kb || (ka == kb && pay_of(a) < pay_of(b));
+}
+
+template <typename T> __device__ __forceinline__ T zero_rec();
+template <> __device__ __forceinline__ uint2 zero_rec<uint2>() { return make_uint2(0, 0); }
+template <> __device__ __forceinline__ uint4 zero_rec<uint4>() { return make_uint4(0, 0, 0, 0); }
+template <typename T> __device__ __forceinline__ T max_rec();
+template <> __device__ __forceinline__ uint2 max_rec<uint2>() { return make_uint2(~0u, ~0u); }
+template <> __device__ __forceinline__ uint4 max_rec<uint4>() { return make_uint4(~0u, ~0u, ~0u, ~0u); }
+
+template <typename T> __device__ __forceinline__ T sel(bool c, T a, T b) { return c ? a : b; }
+template <> __device__ __forceinline__ uint2 sel<uint2>(bool c, uint2 a, uint2 b) {
+  return make_uint2(c ? a.x : b.x, c ? a.y : b.y);
+}
+template <> __device__ __forceinline__ uint4 sel<uint4>(bool c, uint4 a, uint4 b) {
+  return make_uint4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128
+// bit multiplications with the published multipliers and Weyl key increments.
+struct Philox4 {
+  uint64_t v[4];
+};
+__device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t lo0 = M0 * x0, hi0 = __umul64hi(M0, x0);
+    const uint64_t lo1 = M1 * x2, hi1 = __umul64hi(M1, x2);
+    const uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  Philox4 r;
+  r.v[0] = x0;
+  r.v[1] = x1;
+  r.v[2] = x2;
+  r.v[3] = x3;
+  return r;
+}
+
+// Arguments of one routing pass (levels [level0, level0 + klev) of Algorithm 3.1).
+struct PassArgs {
+  const void* x_in;           // first pass: the n input records
+  void* out;                  // last pass: n output records
+  const void* rec_in;         // slot records of level level0 (not first pass)
+  const uint32_t* tag_in;     // slot tags of level level0
+  void* rec_out;              // slot records of level level0 + klev (not last pass)
+  uint32_t* tag_out;
+  unsigned long long* status; // first overflow: (level << 32) | pair, min over MergeSplits
+  unsigned long long* scan;   // last pass: per-block look-back words
+  uint32_t* ticket;           // last pass: dynamic block index counter
+  uint64_t n;
+  uint64_t buckets;           // B
+  uint64_t seed;
+  uint32_t z, lz;             // Z and log2 Z
+  uint32_t levels;            // L
+  uint32_t level0, klev;      // first level of this pass, levels in this pass
+  uint32_t attempt;
+  uint32_t fin;               // last pass: 0 = random permutation of each bin, 1 = sort each bin
+};
+
+// Dynamic LDS bytes of a routing block (must match the carve in the kernel).
+__host__ __device__ inline uint32_t pass_lds_bytes(int rec, uint32_t z, uint32_t klev, bool last_shuffle) {
+  const uint32_t m = z << klev;
+  const uint32_t mp = m + (m >> 4);
+  uint32_t b = mp * uint32_t(rec) + mp * 4u + (m >> 4) * 4u + (1u << klev) * 12u + 64u * 4u + 64u;
+  if (last_shuffle) b += mp * 4u + mp * 2u;
+  return (b + 15u) & ~15u;
+}
+
+}  // namespace bos
