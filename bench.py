@@ -42,13 +42,16 @@ def parse():
     ap.add_argument("--data-seed", type=int, default=42)
     ap.add_argument("--bitonic-steps", type=int, default=2, help="0 skips the bitonic baseline")
     ap.add_argument("--cpu-log2n", type=int, default=24, help="oracle sample size; 0 skips it")
-    ap.add_argument("--mode", default="sort", choices=("sort", "orp"))
+    ap.add_argument("--mode", default="sort", choices=("sort", "orp", "copy"),
+                    help="copy: a plain device copy of the input (counter calibration)")
     return ap.parse_args()
 
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("bos_common.h", "orp_kernels.hip", "sort_kernels.hip"):
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2008_01765_amd", "csrc"))):
+        if not f.endswith((".h", ".hip")):
+            continue
         with open(os.path.join(ROOT, "paper_2008_01765_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -93,6 +96,13 @@ def main():
     out = torch.empty_like(x)
     del host
     stream = torch.cuda.current_stream()
+
+    if args.mode == "copy":
+        for _ in range(args.warmup + args.steps):
+            out.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_per_copy": 2 * n * args.rec, "copies": args.warmup + args.steps}))
+        return
 
     def step():
         if args.mode == "sort":

@@ -55,6 +55,8 @@ typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
 
 /* flags */
 #define BOS_SYNC 1u        /* synchronize and retry on overflow inside the call */
+#define BOS_GENERIC_ROUTING 2u /* test hook: route with the generic (non-specialised)
+                                  kernel; same results, slower */
 
 typedef struct {
   uint64_t seed;              /* Philox key: labels and per-bin permutation keys */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbos.so")
 
 OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED = range(7)
 SYNC = 1
+GENERIC_ROUTING = 2
 
 
 class BosError(RuntimeError):
@@ -110,14 +111,14 @@ def _check(st):
         raise BosError(st, "libbos: " + lib().bos_status_string(st).decode())
 
 
-def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True):
+def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True, generic=False):
     p = Params()
     lib().bos_default_params(C.byref(p))
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.z, p.k, p.tile = z, k, tile
     p.max_retries = max_retries
     p.min_security_bits = min_security_bits
-    p.flags = SYNC if sync else 0
+    p.flags = (SYNC if sync else 0) | (GENERIC_ROUTING if generic else 0)
     return p
 
 
@@ -175,17 +176,18 @@ def _run(fn, t, p, out, stream):
     return out, rep.as_dict()
 
 
-def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stream=None, report=False):
+def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stream=None, report=False,
+        generic=False):
     """Bucket ORP of the records in t (Section 3.2)."""
-    p = params(seed, z, k, 0, max_retries, min_security_bits)
+    p = params(seed, z, k, 0, max_retries, min_security_bits, generic=generic)
     o, rep = _run(lib().bos_orp, t, p, out, stream)
     return (o, rep) if report else o
 
 
 def sort(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
-         report=False):
+         report=False, generic=False):
     """Bucket oblivious sort of the records in t (Section 3.3)."""
-    p = params(seed, z, k, tile, max_retries, min_security_bits)
+    p = params(seed, z, k, tile, max_retries, min_security_bits, generic=generic)
     o, rep = _run(lib().bos_sort, t, p, out, stream)
     return (o, rep) if report else o
 
@@ -265,12 +267,12 @@ def debug_labels(n, levels, seed, attempt=0, device="cuda"):
     return out[:n]
 
 
-def debug_levels(t, seed=0, z=0, k=0, attempt=0, min_security_bits=0):
+def debug_levels(t, seed=0, z=0, k=0, attempt=0, min_security_bits=0, generic=False):
     """Slot arrays at every pass boundary of one attempt (host numpy arrays)."""
     import numpy as np
     rec = rec_bytes(t)
     n = t.shape[0]
-    p = params(seed, z, k, 0, 0, min_security_bits)
+    p = params(seed, z, k, 0, 0, min_security_bits, generic=generic)
     pl = plan(n, rec, z=z, k=k, min_security_bits=min_security_bits)
     B, Z = pl["buckets"], (z or 512)
     P = len(pl["passes"])

@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbos.so")
-SOURCES = ["orp_kernels.hip", "sort_kernels.hip", "bos_api.hip"]
+SOURCES = (["orp_kernels.hip", "route_kernels.hip", "sort_kernels.hip", "bos_api.hip"]
+           + ["route_r%d_z%d.hip" % (r, z) for r in (8, 16) for z in range(4, 12)])
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -23,8 +24,10 @@ def flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose=False, jobs=3):
+def build(verbose=False, jobs=None):
     """Compile every HIP source and link libbos.so.  Always recompiles."""
+    if jobs is None:
+        jobs = max(1, min(16, os.cpu_count() or 4))
     objs = []
     procs = []
     for src in SOURCES:

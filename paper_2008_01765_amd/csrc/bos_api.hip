@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -22,6 +23,8 @@ namespace bos {
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
 hipError_t launch_labels(uint32_t* out, uint64_t n, uint32_t L, uint64_t seed, uint32_t attempt, hipStream_t s);
 hipError_t launch_pass(int rec, const PassArgs& a, bool first, bool last, uint32_t nblocks, hipStream_t s);
+hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
+                        hipStream_t s);
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, hipStream_t s,
                                   void** result);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
@@ -93,6 +96,7 @@ struct Plan {
   uint32_t klev[kMaxPasses] = {0}, lev0[kMaxPasses] = {0};
   size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_scan = 0, total = 0;
   uint32_t nblocks_last = 1;
+  bool generic = false;
 };
 
 uint32_t g_lds_max = 0;
@@ -148,6 +152,7 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   pl->n = n;
   pl->rec = rec;
   pl->Z = Z;
+  pl->generic = (q.flags & BOS_GENERIC_ROUTING) != 0;
   pl->lz = 0;
   while ((1u << pl->lz) < Z) ++pl->lz;
   uint64_t B = 1;
@@ -222,6 +227,26 @@ uint64_t routing_bytes(const Plan& pl) {
 
 bos_status hip_status(hipError_t e) { return e == hipSuccess ? BOS_OK : BOS_ERR_HIP; }
 
+uint32_t g_num_cus = 0;
+uint32_t num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      g_num_cus = uint32_t(v);
+    else
+      g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+// The register-resident routing kernel covers Z in [16, 2048] with at least one
+// level per pass; Z = 8 and the single-bin case (L = 0) use the generic kernel,
+// as does every pass when the caller sets BOS_GENERIC_ROUTING.
+bool use_route_kernel(const Plan& pl, uint32_t t) {
+  return !pl.generic && pl.lz >= 4 && pl.lz <= 11 && pl.klev[t] >= 1;
+}
+
 // Enqueue one attempt of the routing phase; `out` receives the stripped bins.
 hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t seed, uint32_t attempt,
                            uint32_t fin, char* ws, hipStream_t s, int stop_after = -1) {
@@ -261,7 +286,11 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
                                         : BOS_K_ROUTE_MID;
     const uint64_t bytes = (first ? rec_bytes : slot_bytes) + (last ? rec_bytes : slot_bytes);
     prof_begin(kind, t, bytes, s);
-    e = launch_pass(pl.rec, a, first, last, uint32_t(pl.B >> pl.klev[t]), s);
+    const uint32_t nitems = uint32_t(pl.B >> pl.klev[t]);
+    if (use_route_kernel(pl, t))
+      e = launch_route(pl.rec, a, first, last, nitems, num_cus(), s);
+    else
+      e = launch_pass(pl.rec, a, first, last, nitems, s);
     prof_end(s);
     if (e != hipSuccess) return e;
   }

@@ -1,0 +1,836 @@
+// route_impl.h — register-resident routing passes of bucket ORP
+// (Algorithm 3.1 of Asharov et al., SOSA 2020) for gfx950.
+//
+// Same method and same results as orp_pass_kernel (orp_kernels.hip): one
+// launch runs `klev` fused butterfly levels over blocks of 2^klev buckets, every
+// MergeSplit a tight-compaction network over the 2Z slots of its two buckets
+// (marks = reals whose next label bit is 0 plus the first Z - x dummies, the
+// dummy tagging of Section 4.1; network = the offset-compaction recursion of
+// Sasy, Johnson and Goldberg, CCS 2022).  This version is specialised on
+// log2 Z so that every stage is unrolled with compile-time register pairs:
+//
+//   * A MergeSplit's 2Z slots live in the registers of 2Z/16 lanes, 16 slots
+//     per lane.  In layout A lane l holds positions q = 16 l + e (e = 0..15):
+//     stages over q bits 0..3 pair registers, stages over q bits 4 and 5 pair
+//     lanes l and l^1 / l^2 through DPP quad permutes.  In layout B a lane holds
+//     the 16 positions whose q bits LQ-4..LQ-1 vary (LQ = log2 2Z), so the
+//     remaining stages pair registers again.  Each level therefore moves the
+//     data through LDS twice: A -> B, and B -> next level's A (whose MergeSplits
+//     pair other buckets).
+//   * Blocks are persistent: a workgroup walks over several blocks of buckets
+//     and issues the HBM loads of its next block before computing the current
+//     one; barriers wait for LDS traffic only, so those loads stay in flight.
+//
+// Obliviousness: every HBM and LDS address is a function of (n, Z, klev,
+// level, block, lane, register) only; labels and records steer register
+// selects, never an address.
+#pragma once
+#include "bos_common.h"
+
+namespace bos {
+
+namespace route_detail {
+
+constexpr uint32_t kDppXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr uint32_t kDppXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr uint32_t kDppB0022 = 0xA0; // quad_perm [0,0,2,2]
+constexpr uint32_t kDppB1133 = 0xF5; // quad_perm [1,1,3,3]
+constexpr uint32_t kDppB0000 = 0x00; // quad_perm [0,0,0,0]
+constexpr uint32_t kDppB2222 = 0xAA; // quad_perm [2,2,2,2]
+
+// Barrier that waits for this wave's LDS operations only (global loads issued
+// earlier remain in flight).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+}
+
+template <uint32_t CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_mov_dpp(int(v), CTRL, 0xF, 0xF, false));
+}
+template <uint32_t CTRL>
+__device__ __forceinline__ uint2 dpp(uint2 v) {
+  return make_uint2(dpp<CTRL>(v.x), dpp<CTRL>(v.y));
+}
+template <uint32_t CTRL>
+__device__ __forceinline__ uint4 dpp(uint4 v) {
+  return make_uint4(dpp<CTRL>(v.x), dpp<CTRL>(v.y), dpp<CTRL>(v.z), dpp<CTRL>(v.w));
+}
+
+__device__ __forceinline__ uint32_t brev_k(uint32_t x, uint32_t k) { return k ? (__brev(x) >> (32u - k)) : 0u; }
+
+// Swap decision of the compaction network for the pair at offset i of a node
+// of 2*half slots whose marks prefix is P0 at its start and Ph at its middle.
+__device__ __forceinline__ bool swap_bit(uint32_t P0, uint32_t Ph, uint32_t half, uint32_t i) {
+  const uint32_t z = P0 & (2u * half - 1u), mm = Ph - P0;
+  const bool s = (((z & (half - 1u)) + mm) >= half) != (z >= half);
+  const uint32_t t = (z + mm) & (half - 1u);
+  return s != (i >= t);
+}
+
+// Exclusive scan over aligned segments of SEG lanes (SEG a power of two).
+template <uint32_t SEG>
+__device__ __forceinline__ uint32_t seg_scan(uint32_t v, uint32_t* swave, uint32_t* total) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  constexpr uint32_t W = SEG < 64u ? SEG : 64u;
+  uint32_t x = v;
+#pragma unroll
+  for (uint32_t off = 1; off < W; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if ((lane & (W - 1u)) >= off) x += y;
+  }
+  if constexpr (SEG <= 64u) {
+    *total = __shfl(x, int(lane | (W - 1u)), 64);
+    return x - v;
+  } else {
+    if (lane == 63u) swave[wave] = x;
+    lds_barrier();
+    constexpr uint32_t WPS = SEG / 64u;
+    const uint32_t w0 = wave & ~(WPS - 1u);
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < WPS; ++q) {
+      const uint32_t t = swave[w0 + q];
+      if (w0 + q < wave) pre += t;
+      tot += t;
+    }
+    *total = tot;
+    return pre + x - v;
+  }
+}
+
+}  // namespace route_detail
+using namespace route_detail;
+
+// ---- per-bin finish of the last pass (Section 3.2) ---------------------------
+//
+// Each final bin (Z slots in LDS, padded by one slot per 16) is sorted by a
+// bitonic network held in registers: lane lq of the bin's Z/16 lanes holds
+// slots 16 lq + e (layout P; stages on slot bits 0..3 pair registers, bits 4
+// and 5 pair lanes through DPP).  Stages on slot bits >= 6 run in layout Q,
+// where a lane holds the 16 slots whose top four bits vary.  Sort keys:
+// record order with dummies last (bos_sort, and the first half of the
+// random permutation of bos_orp), then (r, p) with dummies last, r the 64-bit
+// Philox key of the p-th real in record order (bos_orp).
+
+template <typename T>
+struct ElemRT {  // record + tag
+  T r;
+  uint32_t t;
+};
+template <typename T>
+struct ElemRK {  // record + 64-bit random key + (p | dummy << 15)
+  T r;
+  uint32_t klo, khi, aux;
+};
+
+template <typename T>
+__device__ __forceinline__ bool e_less(const ElemRT<T>& a, const ElemRT<T>& b) {
+  const bool da = a.t == kDummyTag, db = b.t == kDummyTag;
+  return !da && (db || rec_less(a.r, b.r));
+}
+template <typename T>
+__device__ __forceinline__ bool e_less(const ElemRK<T>& a, const ElemRK<T>& b) {
+  const bool da = (a.aux & 0x8000u) != 0, db = (b.aux & 0x8000u) != 0;
+  const uint64_t ka = (uint64_t(a.khi) << 32) | a.klo, kb = (uint64_t(b.khi) << 32) | b.klo;
+  return !da && (db || ka < kb || (ka == kb && a.aux < b.aux));
+}
+template <typename T>
+__device__ __forceinline__ ElemRT<T> e_sel(bool c, const ElemRT<T>& a, const ElemRT<T>& b) {
+  return ElemRT<T>{sel(c, a.r, b.r), c ? a.t : b.t};
+}
+template <typename T>
+__device__ __forceinline__ ElemRK<T> e_sel(bool c, const ElemRK<T>& a, const ElemRK<T>& b) {
+  return ElemRK<T>{sel(c, a.r, b.r), c ? a.klo : b.klo, c ? a.khi : b.khi, c ? a.aux : b.aux};
+}
+template <uint32_t CTRL, typename T>
+__device__ __forceinline__ ElemRT<T> e_dpp(const ElemRT<T>& a) {
+  return ElemRT<T>{dpp<CTRL>(a.r), dpp<CTRL>(a.t)};
+}
+template <uint32_t CTRL, typename T>
+__device__ __forceinline__ ElemRK<T> e_dpp(const ElemRK<T>& a) {
+  return ElemRK<T>{dpp<CTRL>(a.r), dpp<CTRL>(a.klo), dpp<CTRL>(a.khi), dpp<CTRL>(a.aux)};
+}
+
+// LDS views of the bins (padded slot index)
+template <typename T>
+struct LdsRT {
+  T* rec;
+  uint32_t* tag;
+  __device__ ElemRT<T> ld(uint32_t i) const { return ElemRT<T>{rec[i], tag[i]}; }
+  __device__ void st(uint32_t i, const ElemRT<T>& v) const {
+    rec[i] = v.r;
+    tag[i] = v.t;
+  }
+};
+template <typename T>
+struct LdsRK {
+  T* rec;
+  uint32_t* klo;
+  uint32_t* khi;
+  uint16_t* aux;
+  __device__ ElemRK<T> ld(uint32_t i) const { return ElemRK<T>{rec[i], klo[i], khi[i], aux[i]}; }
+  __device__ void st(uint32_t i, const ElemRK<T>& v) const {
+    rec[i] = v.r;
+    klo[i] = v.klo;
+    khi[i] = v.khi;
+    aux[i] = uint16_t(v.aux);
+  }
+};
+
+template <typename E>
+__device__ __forceinline__ void cx_reg(E& x, E& y, bool asc) {
+  const bool sw = asc ? e_less(y, x) : e_less(x, y);
+  const E nx = e_sel(sw, y, x), ny = e_sel(sw, x, y);
+  x = nx;
+  y = ny;
+}
+template <uint32_t CTRL, typename E>
+__device__ __forceinline__ void cx_lane(E& x, bool is_lo, bool asc) {
+  const E p = e_dpp<CTRL>(x);
+  const bool take = (is_lo == asc) ? e_less(p, x) : e_less(x, p);
+  x = e_sel(take, p, x);
+}
+
+// Bitonic sort (ascending) of every bin; v holds layout P on entry and exit.
+// bbase: padded LDS offset of this lane's bin; lq: lane within the bin.
+// Phases KK = 1..LZ (merges of 2^KK slots), stages JJ = KK-1..0 (slot bit JJ);
+// all indices are template parameters so every register index is static.
+struct BinLane {
+  uint32_t bbase, pbase, lq, lb0, lb1, lowQ;
+  bool active;  // lanes past the block's bins hold no bin and touch no LDS
+};
+
+template <int LZ, int KK>
+__device__ __forceinline__ bool asc_p(uint32_t e, const BinLane& bl) {
+  if constexpr (KK == LZ) return true;
+  else if constexpr (KK < 4) return ((e >> KK) & 1u) == 0u;
+  else return ((bl.lq >> (KK - 4)) & 1u) == 0u;
+}
+template <int LZ, int KK>
+__device__ __forceinline__ bool asc_q(uint32_t e) {
+  if constexpr (KK == LZ) return true;
+  else return ((e >> (KK - (LZ - 4))) & 1u) == 0u;
+}
+
+template <int LZ, int KK, int JJ, typename E>
+__device__ __forceinline__ void p_stages(E (&v)[16], const BinLane& bl) {
+  if constexpr (JJ >= 0) {
+    if constexpr (JJ < 4) {
+      constexpr uint32_t hb = 1u << JJ;
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        if (e & hb) continue;
+        cx_reg(v[e], v[e | hb], asc_p<LZ, KK>(e, bl));
+      }
+    } else if constexpr (JJ == 4) {
+      const bool asc = asc_p<LZ, KK>(0, bl);
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) cx_lane<kDppXor1>(v[e], bl.lb0 == 0u, asc);
+    } else {
+      const bool asc = asc_p<LZ, KK>(0, bl);
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) cx_lane<kDppXor2>(v[e], bl.lb1 == 0u, asc);
+    }
+    p_stages<LZ, KK, JJ - 1>(v, bl);
+  }
+}
+
+template <int LZ, int KK, int JJ, typename E>
+__device__ __forceinline__ void q_stages(E (&v)[16], const BinLane& bl) {
+  if constexpr (JJ >= 6) {
+    if constexpr (JJ >= LZ - 4) {
+      constexpr uint32_t hb = 1u << (JJ - (LZ - 4));
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        if (e & hb) continue;
+        cx_reg(v[e], v[e | hb], asc_q<LZ, KK>(e));
+      }
+    } else {  // slot bit LZ-5 = lane bit 1 of layout Q (Z = 2048)
+      static_assert(JJ == LZ - 5, "layout Q covers slot bits >= LZ-5");
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) cx_lane<kDppXor2>(v[e], bl.lb1 == 0u, asc_q<LZ, KK>(e));
+    }
+    q_stages<LZ, KK, JJ - 1>(v, bl);
+  }
+}
+
+template <int LZ, int KK, typename E, typename V>
+__device__ __forceinline__ void bitonic_phase(E (&v)[16], const V& lds, const BinLane& bl) {
+  if constexpr (KK <= LZ) {
+    if constexpr (KK - 1 >= 6) {
+      // layout Q for the stages on slot bits KK-1 .. 6
+      if (bl.active) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) lds.st(bl.pbase + e, v[e]);
+      }
+      lds_barrier();
+      if (bl.active) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t sl = (e << (LZ - 4)) | bl.lowQ;
+          v[e] = lds.ld(bl.bbase + sl + (sl >> 4));
+        }
+      }
+      q_stages<LZ, KK, KK - 1>(v, bl);
+      if (bl.active) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t sl = (e << (LZ - 4)) | bl.lowQ;
+          lds.st(bl.bbase + sl + (sl >> 4), v[e]);
+        }
+      }
+      lds_barrier();
+      if (bl.active) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) v[e] = lds.ld(bl.pbase + e);
+      }
+    }
+    p_stages<LZ, KK, (KK - 1 < 5 ? KK - 1 : 5)>(v, bl);
+    bitonic_phase<LZ, KK + 1>(v, lds, bl);
+  }
+}
+
+template <int LZ, typename E, typename V>
+__device__ __forceinline__ void bin_bitonic(E (&v)[16], const V& lds, uint32_t bbase, uint32_t lq, bool active) {
+  BinLane bl;
+  bl.active = active;
+  bl.bbase = bbase;
+  bl.pbase = bbase + 17u * lq;  // layout P: slots 16 lq .. 16 lq + 15
+  bl.lq = lq;
+  bl.lb0 = lq & 1u;
+  bl.lb1 = (lq >> 1) & 1u;
+  const uint32_t rest = lq >> 2;
+  bl.lowQ = LZ >= 6 ? ((bl.lb1 << (LZ >= 6 ? LZ - 5 : 0)) | (bl.lb0 << (LZ >= 6 ? LZ - 6 : 0)) | rest) : 0u;
+  bitonic_phase<LZ, 1>(v, lds, bl);
+}
+
+// Finish of the last pass: sort (or randomly permute) every bin, then strip
+// the dummies and write the bins' reals to their place in the output, found
+// with a decoupled look-back over the blocks (block index = ticket order).
+template <int R, int LZ>
+__device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uint32_t klev,
+                                            typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
+                                            uint16_t* saux, uint32_t* sload, uint32_t* soff) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t Z = 1u << LZ, ZP = Z + (Z >> 4), HL = Z >> 4;
+  const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
+  const bool active = tid < (m >> 4);
+  const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
+  const uint32_t bbase = S * ZP;
+  for (uint32_t b = tid; b < NB; b += blockDim.x) sload[b] = 0;
+  lds_barrier();
+
+  const LdsRT<T> lrt{srec, stag};
+  ElemRT<T> v[16];
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) v[e] = active ? lrt.ld(bbase + 17u * lq + e) : ElemRT<T>{zero_rec<T>(), kDummyTag};
+  bin_bitonic<LZ>(v, lrt, bbase, lq, active);
+
+  T outr[16];
+  bool real[16];
+  if (a.fin == 0) {
+    // random permutation: the p-th real (record order) of global bin gb gets
+    // key r(gb*Z + p), word (g mod 4) of Philox block g/4 with key (seed, 1)
+    const uint64_t gb = uint64_t(blk) * NB + brev_k(S, klev);
+    ElemRK<T> w[16];
+#pragma unroll
+    for (uint32_t e4 = 0; e4 < 4; ++e4) {
+      const uint32_t p0 = 16u * lq + 4u * e4;
+      const Philox4 ph = philox4x64_10((gb * Z + p0) >> 2, a.attempt, a.seed, 1);
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t e = 4u * e4 + q;
+        const bool dummy = v[e].t == kDummyTag;
+        w[e] = ElemRK<T>{v[e].r, uint32_t(ph.v[q]), uint32_t(ph.v[q] >> 32), (p0 + q) | (dummy ? 0x8000u : 0u)};
+      }
+    }
+    lds_barrier();  // the record sort's last LDS reads are done
+    const LdsRK<T> lrk{srec, stag, srhi, saux};
+    bin_bitonic<LZ>(w, lrk, bbase, lq, active);
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      outr[e] = w[e].r;
+      real[e] = (w[e].aux & 0x8000u) == 0u;
+    }
+  } else {
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      outr[e] = v[e].r;
+      real[e] = v[e].t != kDummyTag;
+    }
+  }
+  // bin loads: reals occupy the first slots of every sorted bin
+  uint32_t cnt = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) cnt += (active && real[e]) ? 1u : 0u;
+  if (active) atomicAdd(&sload[S], cnt);
+  lds_barrier();
+  if (tid == 0) {
+    uint64_t agg = 0;
+    for (uint32_t b = 0; b < NB; ++b) agg += sload[b];
+    uint64_t excl = 0;
+    const uint64_t kVal = (1ull << 62) - 1ull;
+    if (blk == 0) {
+      __hip_atomic_store(&a.scan[0], (2ull << 62) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&a.scan[blk], (1ull << 62) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t p = int64_t(blk) - 1;
+      while (p >= 0) {
+        const unsigned long long w = __hip_atomic_load(&a.scan[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t flag = uint32_t(w >> 62);
+        if (flag == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += w & kVal;
+        if (flag == 2) break;
+        --p;
+      }
+      __hip_atomic_store(&a.scan[blk], (2ull << 62) | (excl + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint64_t off = excl;
+    for (uint32_t u = 0; u < NB; ++u) {
+      const uint32_t b = brev_k(u, klev);
+      soff[2 * b] = uint32_t(off);
+      soff[2 * b + 1] = uint32_t(off >> 32);
+      off += sload[b];
+    }
+  }
+  lds_barrier();
+  if (active) {
+    T* OUT = static_cast<T*>(a.out);
+    const uint64_t off = (uint64_t(soff[2 * S + 1]) << 32) | soff[2 * S];
+    const uint32_t k = sload[S];
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint32_t p = 16u * lq + e;
+      if (p < k && off + p < a.n) OUT[off + p] = outr[e];
+    }
+  }
+}
+
+// R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last.
+template <int R, int LZ, int MODE>
+__global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t nitems) {
+  using T = typename RecOf<R>::T;
+  constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0;
+  constexpr uint32_t Z = 1u << LZ, LQ = LZ + 1, TPM = 1u << (LQ - 4), ZP = Z + (Z >> 4);
+  constexpr bool HAS_B = LQ > 6;
+  constexpr uint32_t HALF_LANES = TPM / 2;  // lanes per bucket in layout A
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t klev = a.klev, NB = 1u << klev, m = Z << klev, mp = NB * ZP;
+  T* srec = reinterpret_cast<T*>(smem);
+  uint32_t* stag = reinterpret_cast<uint32_t*>(smem + size_t(mp) * R);
+  uint32_t* spfx = stag + mp;          // m/16 marks-prefix entries (16-slot granularity)
+  uint32_t* sload = spfx + (m >> 4);   // NB bin loads (last pass)
+  uint32_t* soff = sload + NB;         // 2*NB words: output offsets (last pass)
+  uint32_t* swave = soff + 2 * NB;     // 64 scan words
+  uint32_t* smisc = swave + 64;        // 16 words
+  uint32_t* srhi = smisc + 16;         // last pass, shuffle
+  uint16_t* saux = reinterpret_cast<uint16_t*>(srhi + mp);
+
+  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint64_t n = a.n, B = a.buckets;
+  const uint32_t L = a.levels, i0 = a.level0;
+  const bool active = tid < (m >> 4);
+  const uint32_t ms = active ? tid / TPM : 0u, lt = active ? tid % TPM : 0u;
+  const T* RI = static_cast<const T*>(a.rec_in);
+  const T* X = static_cast<const T*>(a.x_in);
+  // first pass: all groups start on a multiple of 8 elements (labels come from
+  // whole Philox blocks); otherwise inputs are staged through LDS
+  const bool aligned = (n % (8 * B)) == 0;
+
+  // ---- load one block into layout-A registers of level 0 -------------------
+  // level 0 pairs LDS buckets 2ms and 2ms+1; lane lt holds slots 16*(lt mod
+  // TPM/2) .. +15 of bucket 2ms + lt / (TPM/2).
+  const uint32_t S_load = 2u * ms + (lt >= HALF_LANES ? 1u : 0u);
+  const uint32_t sb_load = 16u * (lt % HALF_LANES);
+  T rv[16];
+  uint32_t tv[16];
+  // 16-byte records leave no registers for a second block: no prefetch there
+  constexpr bool PREFETCH = R == 8;
+  T pf_rv[PREFETCH ? 16 : 1];
+  uint32_t pf_tv[PREFETCH ? 16 : 1];
+
+  auto issue_load = [&](uint32_t item, T* dr, uint32_t* dt) {
+    const uint64_t r = uint64_t(item) & ((1ull << i0) - 1ull), h = uint64_t(item) >> i0;
+    if constexpr (!FIRST) {
+      const uint64_t bucket = (h << (i0 + klev)) + (uint64_t(S_load) << i0) + r;
+      const uint64_t gi = (bucket << LZ) + sb_load;
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        dr[e] = active ? RI[gi + e] : zero_rec<T>();
+        dt[e] = active ? a.tag_in[gi + e] : kDummyTag;
+      }
+    } else {
+      // group j = h*NB + S_load holds X[floor(jn/B), floor((j+1)n/B))
+      const uint64_t j = h * NB + S_load;
+      const uint64_t gs = (j * n) / B, gz = ((j + 1) * n) / B - gs;
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        const bool real = active && (sb_load + e) < gz;
+        dr[e] = real ? X[gs + sb_load + e] : zero_rec<T>();
+        dt[e] = real ? 0u : kDummyTag;  // label filled in by finish_load
+      }
+    }
+  };
+  // first pass: labels of the loaded reals (word x mod 8 of Philox block x/8)
+  auto finish_load = [&](uint32_t item, uint32_t* dt) {
+    if constexpr (FIRST) {
+      const uint64_t h = uint64_t(item) >> i0;
+      const uint64_t j = h * NB + S_load;
+      const uint64_t gs = (j * n) / B;
+      const uint64_t x0 = gs + sb_load;  // multiple of 8
+      if (active && dt[0] != kDummyTag) {
+        const Philox4 p0 = philox4x64_10(x0 >> 3, a.attempt, a.seed, 0);
+#pragma unroll
+        for (uint32_t e = 0; e < 8; ++e) {
+          const uint32_t word = uint32_t(p0.v[e >> 1] >> (32u * (e & 1u)));
+          if (dt[e] != kDummyTag) dt[e] = L ? (word >> (32u - L)) : 0u;
+        }
+      }
+      if (active && dt[8] != kDummyTag) {
+        const Philox4 p1 = philox4x64_10((x0 >> 3) + 1, a.attempt, a.seed, 0);
+#pragma unroll
+        for (uint32_t e = 0; e < 8; ++e) {
+          const uint32_t word = uint32_t(p1.v[e >> 1] >> (32u * (e & 1u)));
+          if (dt[8 + e] != kDummyTag) dt[8 + e] = L ? (word >> (32u - L)) : 0u;
+        }
+      }
+    }
+  };
+  // first pass, groups not aligned to 8: stage the block through LDS and read
+  // layout A back (the generic placement of Algorithm 3.1)
+  auto staged_first_load = [&](uint32_t item) {
+    const uint64_t h = uint64_t(item) >> i0;
+    for (uint32_t t = tid; t < mp; t += nthr) {
+      srec[t] = zero_rec<T>();
+      stag[t] = kDummyTag;
+    }
+    lds_barrier();
+    const uint64_t j_lo = h * NB;
+    const uint64_t x_lo = (j_lo * n) / B, x_hi = ((j_lo + NB) * n) / B;
+    const uint64_t c_lo = x_lo >> 3, c_hi = (x_hi + 7) >> 3;
+    for (uint64_t c = c_lo + tid; c < c_hi; c += nthr) {
+      const Philox4 ph = philox4x64_10(c, a.attempt, a.seed, 0);
+#pragma unroll
+      for (uint32_t w = 0; w < 8; ++w) {
+        const uint64_t x = c * 8 + w;
+        if (x < x_lo || x >= x_hi) continue;
+        const uint32_t word = uint32_t(ph.v[w >> 1] >> (32u * (w & 1u)));
+        const uint64_t j = ((x + 1) * B - 1) / n;
+        const uint64_t gs = (j * n) / B;
+        const uint32_t S = uint32_t(j - j_lo), s = uint32_t(x - gs);
+        const uint32_t pi = S * ZP + s + (s >> 4);
+        srec[pi] = X[x];
+        stag[pi] = L ? (word >> (32u - L)) : 0u;
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint32_t s = sb_load + e;
+      const uint32_t pi = S_load * ZP + s + (s >> 4);
+      rv[e] = active ? srec[pi] : zero_rec<T>();
+      tv[e] = active ? stag[pi] : kDummyTag;
+    }
+    lds_barrier();
+  };
+
+  // ---- one block -----------------------------------------------------------
+  auto process = [&](uint32_t item) {
+    const uint64_t r = uint64_t(item) & ((1ull << i0) - 1ull), h = uint64_t(item) >> i0;
+    for (uint32_t d = 0; d < klev; ++d) {
+      const uint32_t lev = i0 + d, shift = L - 1u - lev;
+      const uint32_t S0 = ((ms >> d) << (d + 1)) | (ms & ((1u << d) - 1u)), S1 = S0 | (1u << d);
+      const uint32_t base0 = S0 * ZP, base1 = S1 * ZP;
+      // layout A: this lane's 16 slots are bucket (lt < TPM/2 ? S0 : S1),
+      // slots 16*(lt mod TPM/2) + e
+      const uint32_t baseA = (lt < HALF_LANES ? base0 : base1) + 17u * (lt % HALF_LANES);
+      if (d > 0) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          rv[e] = active ? srec[baseA + e] : zero_rec<T>();
+          tv[e] = active ? stag[baseA + e] : kDummyTag;
+        }
+      }
+      // prefix counts of (class-0 reals, dummies) in 16-bit halves
+      uint32_t pk[16];
+      uint32_t run = 0;
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        const uint32_t tg = tv[e];
+        const bool real = tg != kDummyTag;
+        const bool c0 = real && ((tg >> shift) & 1u) == 0u;
+        pk[e] = run;
+        run += (c0 ? 1u : 0u) | (real ? 0u : 0x10000u);
+      }
+      uint32_t tot;
+      const uint32_t excl = seg_scan<TPM>(active ? run : 0u, swave, &tot);
+      const uint32_t x = tot & 0xFFFFu, nd = tot >> 16, y = 2u * Z - x - nd;
+      const uint32_t need = x <= Z ? Z - x : 0u;
+      uint32_t pm[16];
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        const uint32_t pe = excl + pk[e];
+        pm[e] = (pe & 0xFFFFu) + min(pe >> 16, need);
+      }
+      if (active) {
+        spfx[ms * TPM + lt] = pm[0];
+        if (lt == 0 && (x > Z || y > Z)) {
+          const uint64_t G = S0 >> (d + 1);
+          const uint64_t v = brev_k(S0 & ((1u << d) - 1u), d);
+          const uint64_t j = (((h << (klev - d - 1)) + G) << lev) + (r << d) + v;
+          atomicMin(a.status, (unsigned long long)((uint64_t(lev) << 32) | j));
+        }
+      }
+      // -- layout A, q bits 0..3: register pairs
+#pragma unroll
+      for (uint32_t eb = 0; eb < 4; ++eb) {
+        const uint32_t half = 1u << eb;
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          if (e & half) continue;
+          const uint32_t e2 = e | half, es = e & ~(2u * half - 1u);
+          const bool b = swap_bit(pm[es], pm[es | half], half, e & (half - 1u));
+          const T r1 = rv[e], r2 = rv[e2];
+          const uint32_t t1 = tv[e], t2 = tv[e2];
+          rv[e] = sel(b, r2, r1);
+          rv[e2] = sel(b, r1, r2);
+          tv[e] = b ? t2 : t1;
+          tv[e2] = b ? t1 : t2;
+        }
+      }
+      // -- layout A, q bit 4: lanes l and l^1 (node = 2 lanes, half = 16)
+      if constexpr (LQ >= 5) {
+        const uint32_t P0 = dpp<kDppB0022>(pm[0]), Ph = dpp<kDppB1133>(pm[0]);
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const bool b = swap_bit(P0, Ph, 16u, e);
+          const T pr = dpp<kDppXor1>(rv[e]);
+          const uint32_t pt = dpp<kDppXor1>(tv[e]);
+          rv[e] = sel(b, pr, rv[e]);
+          tv[e] = b ? pt : tv[e];
+        }
+      }
+      // -- layout A, q bit 5: lanes l and l^2 (node = 4 lanes, half = 32)
+      if constexpr (LQ >= 6) {
+        const uint32_t P0 = dpp<kDppB0000>(pm[0]), Ph = dpp<kDppB2222>(pm[0]);
+        const uint32_t ioff = 16u * (lt & 1u);
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const bool b = swap_bit(P0, Ph, 32u, ioff + e);
+          const T pr = dpp<kDppXor2>(rv[e]);
+          const uint32_t pt = dpp<kDppXor2>(tv[e]);
+          rv[e] = sel(b, pr, rv[e]);
+          tv[e] = b ? pt : tv[e];
+        }
+      }
+      // lane lt in layout B: q = e << (LQ-4) | lb1 << (LQ-5) | lb0 << (LQ-6) | rest
+      uint32_t baseB0 = 0, baseB1 = 0, lowB = 0;
+      if constexpr (HAS_B) {
+        // A -> LDS
+        if (active) {
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            srec[baseA + e] = rv[e];
+            stag[baseA + e] = tv[e];
+          }
+        }
+        lds_barrier();
+        const uint32_t lb0 = lt & 1u, lb1 = (lt >> 1) & 1u, rest = lt >> 2;
+        lowB = (lb1 << (LQ - 5)) | (lb0 << (LQ - 6)) | rest;
+        baseB0 = base0 + lowB + (lowB >> 4);
+        baseB1 = base1 + lowB + (lowB >> 4);
+        // marks prefix at node boundaries (multiples of 16 slots)
+        uint32_t pv[16], pvh[16];
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t q = e << (LQ - 4);
+          const uint32_t i1 = (q & 15u) == 0u ? (q >> 4) : 0u;
+          pv[e] = active ? spfx[ms * TPM + i1] : 0u;
+          if constexpr (LQ >= 11) {
+            const uint32_t qh = q | (1u << (LQ - 5));
+            pvh[e] = active ? spfx[ms * TPM + (qh >> 4)] : 0u;
+          } else {
+            pvh[e] = 0;
+          }
+        }
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t sl = (e & 7u) << (LQ - 4);
+          const uint32_t off = sl + (sl >> 4);  // lowB + sl: padding adds (lowB + sl) >> 4
+          const uint32_t bb = (e < 8) ? baseB0 : baseB1;
+          // padded index of slot s = sl + lowB: s + s/16 = sl + sl/16 + lowB + lowB/16
+          // holds because sl is a multiple of 16 whenever LQ >= 8; for
+          // smaller Z compute it directly
+          uint32_t pi;
+          if constexpr (LQ >= 8) {
+            pi = bb + off;
+          } else {
+            const uint32_t s = sl + lowB;
+            pi = (e < 8 ? base0 : base1) + s + (s >> 4);
+          }
+          rv[e] = active ? srec[pi] : zero_rec<T>();
+          tv[e] = active ? stag[pi] : kDummyTag;
+        }
+        // -- layout B, q bit LQ-6 (lane bit 0), only for Z = 2048
+        if constexpr (LQ - 6 >= 6) {
+          const uint32_t half = 1u << (LQ - 6);
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            // node: q bits 0..LQ-6 cleared; its start and middle are 16-aligned
+            const uint32_t qn = (e << (LQ - 4)) | (lb1 << (LQ - 5));
+            const uint32_t P0 = spfx[ms * TPM + (qn >> 4)];
+            const uint32_t Ph = spfx[ms * TPM + ((qn | half) >> 4)];
+            const bool b = swap_bit(P0, Ph, half, rest);
+            const T pr = dpp<kDppXor1>(rv[e]);
+            const uint32_t pt = dpp<kDppXor1>(tv[e]);
+            rv[e] = sel(b, pr, rv[e]);
+            tv[e] = b ? pt : tv[e];
+          }
+        }
+        // -- layout B, q bit LQ-5 (lane bit 1), for Z >= 1024
+        if constexpr (LQ - 5 >= 6) {
+          const uint32_t half = 1u << (LQ - 5);
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            const bool b = swap_bit(pv[e], pvh[e], half, (lb0 << (LQ - 6)) | rest);
+            const T pr = dpp<kDppXor2>(rv[e]);
+            const uint32_t pt = dpp<kDppXor2>(tv[e]);
+            rv[e] = sel(b, pr, rv[e]);
+            tv[e] = b ? pt : tv[e];
+          }
+        }
+        // -- layout B, q bits LQ-4 .. LQ-1: register pairs (those >= 6)
+#pragma unroll
+        for (uint32_t eb = 0; eb < 4; ++eb) {
+          if (LQ - 4 + eb < 6) continue;
+          const uint32_t hb = 1u << eb;
+          const uint32_t half = 1u << (LQ - 4 + eb);
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            if (e & hb) continue;
+            const uint32_t e2 = e | hb, es = e & ~(2u * hb - 1u);
+            const uint32_t i = ((e & (hb - 1u)) << (LQ - 4)) | lowB;
+            const bool b = swap_bit(pv[es], pv[es | hb], half, i);
+            const T r1 = rv[e], r2 = rv[e2];
+            const uint32_t t1 = tv[e], t2 = tv[e2];
+            rv[e] = sel(b, r2, r1);
+            rv[e2] = sel(b, r1, r2);
+            tv[e] = b ? t2 : t1;
+            tv[e2] = b ? t1 : t2;
+          }
+        }
+      }
+      // -- hand the level's output to LDS (next level or last-pass finish)
+      if (d + 1 < klev || LAST) {
+        if constexpr (HAS_B) {
+          // every lane rewrites exactly the layout-B slots it read: no barrier
+          if (active) {
+#pragma unroll
+            for (uint32_t e = 0; e < 16; ++e) {
+              const uint32_t sl = (e & 7u) << (LQ - 4);
+              uint32_t pi;
+              if constexpr (LQ >= 8) {
+                pi = ((e < 8) ? baseB0 : baseB1) + sl + (sl >> 4);
+              } else {
+                const uint32_t s = sl + lowB;
+                pi = (e < 8 ? base0 : base1) + s + (s >> 4);
+              }
+              srec[pi] = rv[e];
+              stag[pi] = tv[e];
+            }
+          }
+        } else {
+          if (active) {
+#pragma unroll
+            for (uint32_t e = 0; e < 16; ++e) {
+              srec[baseA + e] = rv[e];
+              stag[baseA + e] = tv[e];
+            }
+          }
+        }
+        lds_barrier();
+      } else {
+        // last level of a non-last pass: write the 2^klev output buckets
+        // (LDS bucket S is output digit bitrev(S)) straight from registers
+        T* RO = static_cast<T*>(a.rec_out);
+        const uint64_t ob0 = (h << (i0 + klev)) + (r << klev) + brev_k(S0, klev);
+        const uint64_t ob1 = (h << (i0 + klev)) + (r << klev) + brev_k(S1, klev);
+        if (active) {
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            uint64_t gi;
+            if constexpr (HAS_B) {
+              const uint32_t s = ((e & 7u) << (LQ - 4)) | lowB;
+              gi = (((e < 8) ? ob0 : ob1) << LZ) + s;
+            } else {
+              gi = (((lt < HALF_LANES) ? ob0 : ob1) << LZ) + sb_load + e;
+            }
+            RO[gi] = rv[e];
+            a.tag_out[gi] = tv[e];
+          }
+        }
+      }
+    }
+  };
+
+  if constexpr (!LAST) {
+    // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...
+    uint32_t item = blockIdx.x;
+    if (item >= nitems) return;
+    if (FIRST && !aligned) {
+      staged_first_load(item);
+    } else {
+      issue_load(item, rv, tv);
+      finish_load(item, tv);
+    }
+    for (;;) {
+      const uint32_t next = item + gridDim.x;
+      const bool has_next = next < nitems;
+      if constexpr (PREFETCH) {
+        if (has_next && !(FIRST && !aligned)) issue_load(next, pf_rv, pf_tv);
+      }
+      process(item);
+      if (!has_next) break;
+      item = next;
+      lds_barrier();  // LDS of the previous block is no longer read
+      if (FIRST && !aligned) {
+        staged_first_load(item);
+      } else {
+        if constexpr (PREFETCH) {
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            rv[e] = pf_rv[e];
+            tv[e] = pf_tv[e];
+          }
+        } else {
+          issue_load(item, rv, tv);
+        }
+        finish_load(item, tv);
+      }
+    }
+  } else {
+    // Last pass: one block per launch block; the block index is a ticket so
+    // that the look-back of the strip only waits on blocks that started
+    // earlier.
+    if (tid == 0) smisc[0] = atomicAdd(a.ticket, 1u);
+    lds_barrier();
+    const uint32_t blk = smisc[0];
+    if (FIRST && !aligned) {
+      staged_first_load(blk);
+    } else {
+      issue_load(blk, rv, tv);
+      finish_load(blk, tv);
+    }
+    process(blk);
+    // every final bin (LDS bucket S) now sits in LDS with padded slots
+    finish_bins<R, LZ>(a, blk, klev, srec, stag, srhi, saux, sload, soff);
+  }
+}
+
+}  // namespace bos

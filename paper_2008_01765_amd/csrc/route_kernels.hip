@@ -1,0 +1,52 @@
+// route_kernels.hip — dispatch of the register-resident routing kernels
+// (route_impl.h) over record size and Z; the instantiations live in
+// route_r*_z*.hip so that they compile in parallel.
+#include "bos_common.h"
+
+namespace bos {
+hipError_t launch_route_r8_z4(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z5(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z6(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z7(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z8(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z9(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z10(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r8_z11(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z4(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z5(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z6(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z7(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z8(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z9(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z10(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+hipError_t launch_route_r16_z11(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
+
+// Routing pass with the register-resident kernel (Z in [16, 2048], klev >= 1).
+hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
+                        hipStream_t s) {
+  const int mode = (first ? 1 : 0) | (last ? 2 : 0);
+  if (rec == 8) {
+    switch (a.lz) {
+    case 4: return launch_route_r8_z4(a, mode, nitems, grid, s);
+    case 5: return launch_route_r8_z5(a, mode, nitems, grid, s);
+    case 6: return launch_route_r8_z6(a, mode, nitems, grid, s);
+    case 7: return launch_route_r8_z7(a, mode, nitems, grid, s);
+    case 8: return launch_route_r8_z8(a, mode, nitems, grid, s);
+    case 9: return launch_route_r8_z9(a, mode, nitems, grid, s);
+    case 10: return launch_route_r8_z10(a, mode, nitems, grid, s);
+    default: return launch_route_r8_z11(a, mode, nitems, grid, s);
+    }
+  }
+  switch (a.lz) {
+    case 4: return launch_route_r16_z4(a, mode, nitems, grid, s);
+    case 5: return launch_route_r16_z5(a, mode, nitems, grid, s);
+    case 6: return launch_route_r16_z6(a, mode, nitems, grid, s);
+    case 7: return launch_route_r16_z7(a, mode, nitems, grid, s);
+    case 8: return launch_route_r16_z8(a, mode, nitems, grid, s);
+    case 9: return launch_route_r16_z9(a, mode, nitems, grid, s);
+    case 10: return launch_route_r16_z10(a, mode, nitems, grid, s);
+    default: return launch_route_r16_z11(a, mode, nitems, grid, s);
+  }
+}
+
+}  // namespace bos

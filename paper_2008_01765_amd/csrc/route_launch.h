@@ -1,0 +1,45 @@
+// route_launch.h — launch helpers of the register-resident routing kernel.
+#pragma once
+#include "route_impl.h"
+
+namespace bos {
+
+template <int R, int LZ, int MODE>
+hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hipStream_t s) {
+  const uint32_t m = (1u << LZ) << a.klev;
+  uint32_t threads = m >> 4;
+  if (threads < 64) threads = 64;
+  const uint32_t lds = pass_lds_bytes(R, 1u << LZ, a.klev, (MODE & 2) && a.fin == 0);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&route_kernel<R, LZ, MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  static uint32_t occ_lds = 0, occ_blocks = 0;
+  if (occ_lds != lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&route_kernel<R, LZ, MODE>),
+                                                     int(threads), lds) != hipSuccess || nb < 1)
+      nb = 1;
+    occ_lds = lds;
+    occ_blocks = uint32_t(nb);
+  }
+  const uint32_t persistent = grid * occ_blocks;
+  const uint32_t g = (MODE & 2) ? nitems : (persistent < nitems ? persistent : nitems);
+  hipLaunchKernelGGL((route_kernel<R, LZ, MODE>), dim3(g), dim3(threads), lds, s, a, nitems);
+  return hipGetLastError();
+}
+
+template <int R, int LZ>
+hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
+  switch (mode) {
+    case 0: return launch_route_t<R, LZ, 0>(a, nitems, grid, s);
+    case 1: return launch_route_t<R, LZ, 1>(a, nitems, grid, s);
+    case 2: return launch_route_t<R, LZ, 2>(a, nitems, grid, s);
+    default: return launch_route_t<R, LZ, 3>(a, nitems, grid, s);
+  }
+}
+
+}  // namespace bos

@@ -1,0 +1,8 @@
+// route_r16_z8.hip — routing kernels for 16-byte records, Z = 256.
+#include "route_launch.h"
+
+namespace bos {
+hipError_t launch_route_r16_z8(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
+  return launch_route_m<16, 8>(a, mode, nitems, grid, s);
+}
+}  // namespace bos

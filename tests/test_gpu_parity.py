@@ -52,6 +52,13 @@ def test_labels_match(L):
 
 ORP_CASES = [  # n, rec, Z, k
     (1 << 16, 8, 512, 4),     # the small workload
+    (1 << 17, 8, 256, 4),
+    (1 << 17, 16, 2048, 2),
+    (100000, 8, 1024, 3),     # ragged: first pass staged through LDS
+    (1024, 8, 16, 4),         # tiny Z: several attempts overflow first
+    (5000, 16, 128, 1),       # last pass with 16 of 64 lanes holding bins
+    (9000, 8, 256, 1),        # last pass with 32 of 64 lanes holding bins
+    (1 << 14, 16, 32, 3),
     (1 << 16, 8, 512, 1),
     (1 << 16, 8, 512, 2),
     (1 << 16, 8, 512, 3),
@@ -68,12 +75,14 @@ ORP_CASES = [  # n, rec, Z, k
 ]
 
 
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("n,rec,z,k", ORP_CASES)
-def test_orp_bit_exact(ora, n, rec, z, k):
+def test_orp_bit_exact(ora, n, rec, z, k, generic):
     a = _recs(n, rec)
     for seed in (1, 99):
         want = ora.orp(a, seed, z=z, max_retries=40)
-        out, rep = bos.orp(_gpu(a), seed=seed, z=z, k=k, max_retries=40, min_security_bits=0, report=True)
+        out, rep = bos.orp(_gpu(a), seed=seed, z=z, k=k, max_retries=40, min_security_bits=0, report=True,
+                           generic=generic)
         assert want["rc"] == 0
         assert rep["attempts"] == want["report"]["attempts"]
         assert (rep["first_overflow_level"], rep["first_overflow_pair"]) == \
@@ -97,12 +106,14 @@ def test_empty_input():
     assert bos.sort(t, seed=1).shape == (0, 2)
 
 
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("n,rec,z,k", [(1 << 14, 8, 64, 2), (5000, 16, 32, 3), (1 << 16, 8, 512, 1),
-                                       (9999, 8, 16, 4)])
-def test_pass_boundaries_match_oracle_levels(ora, n, rec, z, k):
+                                       (9999, 8, 16, 4), (1 << 15, 16, 128, 3), (1 << 16, 8, 256, 4),
+                                       (1 << 16, 16, 1024, 2), (1 << 17, 8, 2048, 2), (40000, 8, 512, 3)])
+def test_pass_boundaries_match_oracle_levels(ora, n, rec, z, k, generic):
     a = _recs(n, rec)
     for seed in range(3):
-        g = bos.debug_levels(_gpu(a), seed=seed, z=z, k=k)
+        g = bos.debug_levels(_gpu(a), seed=seed, z=z, k=k, generic=generic)
         o = ora.levels(a, seed, z=z)
         for t in range(1, len(g["levels"])):
             lev = int(g["levels"][t])
