@@ -63,7 +63,7 @@ typedef struct {
   uint32_t z;                 /* bucket capacity Z (Algorithm 3.1); power of two in
                                  [8, 2048]; 0 = 512, the paper's choice */
   uint32_t k;                 /* butterfly levels fused per pass; 0 = planner's choice */
-  uint32_t tile;              /* records per tile of the final sort; 0 = default */
+  uint32_t tile;              /* records per tile of the final sort: 0 or 4096 */
   uint32_t max_retries;       /* extra attempts after an overflow (default 3) */
   uint32_t min_security_bits; /* reject Z when log2(B log2 B e^(-Z/6)) > -bits;
                                  0 disables the check (default 80) */

@@ -25,9 +25,10 @@ hipError_t launch_labels(uint32_t* out, uint64_t n, uint32_t L, uint64_t seed, u
 hipError_t launch_pass(int rec, const PassArgs& a, bool first, bool last, uint32_t nblocks, hipStream_t s);
 hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
                         hipStream_t s);
-hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, hipStream_t s,
-                                  void** result);
+hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
+                                  hipStream_t s, void** result);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
+size_t comparison_sort_split_bytes(uint64_t n);
 hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
                           hipStream_t s);
 }  // namespace bos
@@ -94,7 +95,7 @@ struct Plan {
   int rec = 8;
   uint32_t Z = 512, lz = 9, L = 0, P = 1, k = 0, tile = kDefaultTile;
   uint32_t klev[kMaxPasses] = {0}, lev0[kMaxPasses] = {0};
-  size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_scan = 0, total = 0;
+  size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_scan = 0, off_split = 0, total = 0;
   uint32_t nblocks_last = 1;
   bool generic = false;
 };
@@ -174,7 +175,7 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   uint32_t k = q.k ? std::min(q.k, kmid) : std::min(4u, kmid);
   pl->k = k;
   pl->tile = q.tile ? q.tile : kDefaultTile;
-  if (pl->tile < 2048 || (pl->tile & (pl->tile - 1)) || pl->tile > 8192) return BOS_ERR_INVALID_ARG;
+  if (pl->tile != kDefaultTile) return BOS_ERR_INVALID_ARG;  // the tile sort is built for 4096
   if (L == 0) {
     pl->P = 1;
     pl->klev[0] = 0;
@@ -213,6 +214,8 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   }
   pl->off_status = off;  // status word, ticket, then look-back words
   off = align_up(off + 16 + size_t(pl->nblocks_last) * 8);
+  pl->off_split = off;   // merge-path splits of the comparison sort
+  off = align_up(off + comparison_sort_split_bytes(n));
   pl->total = off;
   return BOS_OK;
 }
@@ -428,7 +431,8 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
     return st;
   }
   void* result = nullptr;
-  hipError_t e = launch_comparison_sort(pl.rec, start, other, n, pl.tile, s, &result);
+  hipError_t e = launch_comparison_sort(pl.rec, start, other, n, pl.tile,
+                                        reinterpret_cast<uint64_t*>(w + pl.off_split), s, &result);
   if (e != hipSuccess) return BOS_ERR_HIP;
   if (result != out) {
     e = hipMemcpyAsync(out, result, n * pl.rec, hipMemcpyDeviceToDevice, s);

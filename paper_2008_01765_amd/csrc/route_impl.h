@@ -63,6 +63,7 @@ __device__ __forceinline__ uint32_t brev_k(uint32_t x, uint32_t k) { return k ? 
 // Swap decision of the compaction network for the pair at offset i of a node
 // of 2*half slots whose marks prefix is P0 at its start and Ph at its middle.
 __device__ __forceinline__ bool swap_bit(uint32_t P0, uint32_t Ph, uint32_t half, uint32_t i) {
+  if (half == 1u) return (Ph - P0) == (P0 & 1u);  // the rule below with half = 1
   const uint32_t z = P0 & (2u * half - 1u), mm = Ph - P0;
   const bool s = (((z & (half - 1u)) + mm) >= half) != (z >= half);
   const uint32_t t = (z + mm) & (half - 1u);
@@ -114,39 +115,40 @@ using namespace route_detail;
 // random permutation of bos_orp), then (r, p) with dummies last, r the 64-bit
 // Philox key of the p-th real in record order (bos_orp).
 
+// Sort elements.  Dummies are given the maximal record (record order) or the
+// maximal key (random-key order), so that comparing keys alone puts them
+// last; a real element can only tie with a dummy when both are byte-identical,
+// where either order gives the same output bytes.
 template <typename T>
-struct ElemRT {  // record + tag
+struct ElemR {  // a record
   T r;
-  uint32_t t;
 };
 template <typename T>
-struct ElemRK {  // record + 64-bit random key + (p | dummy << 15)
+struct ElemRK {  // a record with its 64-bit random key and rank p (0xFFFF for dummies)
   T r;
   uint32_t klo, khi, aux;
 };
 
 template <typename T>
-__device__ __forceinline__ bool e_less(const ElemRT<T>& a, const ElemRT<T>& b) {
-  const bool da = a.t == kDummyTag, db = b.t == kDummyTag;
-  return !da && (db || rec_less(a.r, b.r));
+__device__ __forceinline__ bool e_less(const ElemR<T>& a, const ElemR<T>& b) {
+  return rec_less(a.r, b.r);
 }
 template <typename T>
 __device__ __forceinline__ bool e_less(const ElemRK<T>& a, const ElemRK<T>& b) {
-  const bool da = (a.aux & 0x8000u) != 0, db = (b.aux & 0x8000u) != 0;
   const uint64_t ka = (uint64_t(a.khi) << 32) | a.klo, kb = (uint64_t(b.khi) << 32) | b.klo;
-  return !da && (db || ka < kb || (ka == kb && a.aux < b.aux));
+  return ka < kb || (ka == kb && a.aux < b.aux);
 }
 template <typename T>
-__device__ __forceinline__ ElemRT<T> e_sel(bool c, const ElemRT<T>& a, const ElemRT<T>& b) {
-  return ElemRT<T>{sel(c, a.r, b.r), c ? a.t : b.t};
+__device__ __forceinline__ ElemR<T> e_sel(bool c, const ElemR<T>& a, const ElemR<T>& b) {
+  return ElemR<T>{sel(c, a.r, b.r)};
 }
 template <typename T>
 __device__ __forceinline__ ElemRK<T> e_sel(bool c, const ElemRK<T>& a, const ElemRK<T>& b) {
   return ElemRK<T>{sel(c, a.r, b.r), c ? a.klo : b.klo, c ? a.khi : b.khi, c ? a.aux : b.aux};
 }
 template <uint32_t CTRL, typename T>
-__device__ __forceinline__ ElemRT<T> e_dpp(const ElemRT<T>& a) {
-  return ElemRT<T>{dpp<CTRL>(a.r), dpp<CTRL>(a.t)};
+__device__ __forceinline__ ElemR<T> e_dpp(const ElemR<T>& a) {
+  return ElemR<T>{dpp<CTRL>(a.r)};
 }
 template <uint32_t CTRL, typename T>
 __device__ __forceinline__ ElemRK<T> e_dpp(const ElemRK<T>& a) {
@@ -155,14 +157,10 @@ __device__ __forceinline__ ElemRK<T> e_dpp(const ElemRK<T>& a) {
 
 // LDS views of the bins (padded slot index)
 template <typename T>
-struct LdsRT {
+struct LdsR {
   T* rec;
-  uint32_t* tag;
-  __device__ ElemRT<T> ld(uint32_t i) const { return ElemRT<T>{rec[i], tag[i]}; }
-  __device__ void st(uint32_t i, const ElemRT<T>& v) const {
-    rec[i] = v.r;
-    tag[i] = v.t;
-  }
+  __device__ ElemR<T> ld(uint32_t i) const { return ElemR<T>{rec[i]}; }
+  __device__ void st(uint32_t i, const ElemR<T>& v) const { rec[i] = v.r; }
 };
 template <typename T>
 struct LdsRK {
@@ -179,9 +177,11 @@ struct LdsRK {
   }
 };
 
+// Compare-exchange with one comparison: equal elements are byte-identical, so
+// swapping them or not is the same.
 template <typename E>
 __device__ __forceinline__ void cx_reg(E& x, E& y, bool asc) {
-  const bool sw = asc ? e_less(y, x) : e_less(x, y);
+  const bool sw = e_less(y, x) == asc;
   const E nx = e_sel(sw, y, x), ny = e_sel(sw, x, y);
   x = nx;
   y = ny;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void cx_reg(E& x, E& y, bool asc) {
 template <uint32_t CTRL, typename E>
 __device__ __forceinline__ void cx_lane(E& x, bool is_lo, bool asc) {
   const E p = e_dpp<CTRL>(x);
-  const bool take = (is_lo == asc) ? e_less(p, x) : e_less(x, p);
+  const bool take = e_less(p, x) == (is_lo == asc);
   x = e_sel(take, p, x);
 }
 
@@ -209,9 +209,11 @@ __device__ __forceinline__ bool asc_p(uint32_t e, const BinLane& bl) {
   else return ((bl.lq >> (KK - 4)) & 1u) == 0u;
 }
 template <int LZ, int KK>
-__device__ __forceinline__ bool asc_q(uint32_t e) {
+__device__ __forceinline__ bool asc_q(uint32_t e, const BinLane& bl) {
   if constexpr (KK == LZ) return true;
-  else return ((e >> (KK - (LZ - 4))) & 1u) == 0u;
+  else if constexpr (KK >= LZ - 4) return ((e >> (KK - (LZ - 4))) & 1u) == 0u;
+  else if constexpr (KK == LZ - 5) return bl.lb1 == 0u;  // lane bits of layout Q (Z >= 2048)
+  else return bl.lb0 == 0u;
 }
 
 template <int LZ, int KK, int JJ, typename E>
@@ -245,12 +247,15 @@ __device__ __forceinline__ void q_stages(E (&v)[16], const BinLane& bl) {
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
         if (e & hb) continue;
-        cx_reg(v[e], v[e | hb], asc_q<LZ, KK>(e));
+        cx_reg(v[e], v[e | hb], asc_q<LZ, KK>(e, bl));
       }
-    } else {  // slot bit LZ-5 = lane bit 1 of layout Q (Z = 2048)
-      static_assert(JJ == LZ - 5, "layout Q covers slot bits >= LZ-5");
+    } else if constexpr (JJ == LZ - 5) {  // lane bit 1 of layout Q (2^LZ >= 2048)
 #pragma unroll
-      for (uint32_t e = 0; e < 16; ++e) cx_lane<kDppXor2>(v[e], bl.lb1 == 0u, asc_q<LZ, KK>(e));
+      for (uint32_t e = 0; e < 16; ++e) cx_lane<kDppXor2>(v[e], bl.lb1 == 0u, asc_q<LZ, KK>(e, bl));
+    } else {  // lane bit 0 of layout Q (2^LZ = 4096)
+      static_assert(JJ == LZ - 6, "layout Q covers slot bits >= LZ-6");
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) cx_lane<kDppXor1>(v[e], bl.lb0 == 0u, asc_q<LZ, KK>(e, bl));
     }
     q_stages<LZ, KK, JJ - 1>(v, bl);
   }
@@ -302,7 +307,9 @@ __device__ __forceinline__ void bin_bitonic(E (&v)[16], const V& lds, uint32_t b
   bl.lb0 = lq & 1u;
   bl.lb1 = (lq >> 1) & 1u;
   const uint32_t rest = lq >> 2;
-  bl.lowQ = LZ >= 6 ? ((bl.lb1 << (LZ >= 6 ? LZ - 5 : 0)) | (bl.lb0 << (LZ >= 6 ? LZ - 6 : 0)) | rest) : 0u;
+  // layout Q pairs lanes through DPP only for Z = 2048; otherwise lanes take
+  // consecutive slots
+  bl.lowQ = LZ >= 11 ? ((bl.lb1 << (LZ - 5)) | (bl.lb0 << (LZ - 6)) | rest) : (LZ >= 6 ? lq : 0u);
   bitonic_phase<LZ, 1>(v, lds, bl);
 }
 
@@ -319,17 +326,28 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
   const bool active = tid < (m >> 4);
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   const uint32_t bbase = S * ZP;
-  for (uint32_t b = tid; b < NB; b += blockDim.x) sload[b] = 0;
-  lds_barrier();
+  // The bin loads (sload, written by the last level) are known before the
+  // bins are sorted: publish the block's aggregate now so that later blocks'
+  // look-back does not wait for this block's sort.
+  uint64_t agg = 0;
+  if (tid == 0) {
+    for (uint32_t b = 0; b < NB; ++b) agg += sload[b];
+    __hip_atomic_store(&a.scan[blk], ((blk == 0 ? 2ull : 1ull) << 62) | agg, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
 
-  const LdsRT<T> lrt{srec, stag};
-  ElemRT<T> v[16];
+  // record order, dummies (maximal record) last
+  const LdsR<T> lr{srec};
+  ElemR<T> v[16];
 #pragma unroll
-  for (uint32_t e = 0; e < 16; ++e) v[e] = active ? lrt.ld(bbase + 17u * lq + e) : ElemRT<T>{zero_rec<T>(), kDummyTag};
-  bin_bitonic<LZ>(v, lrt, bbase, lq, active);
+  for (uint32_t e = 0; e < 16; ++e) {
+    const uint32_t i = bbase + 17u * lq + e;
+    v[e] = ElemR<T>{(active && stag[i] != kDummyTag) ? srec[i] : max_rec<T>()};
+  }
+  bin_bitonic<LZ>(v, lr, bbase, lq, active);
+  const uint32_t load = active ? sload[S] : 0u;
 
   T outr[16];
-  bool real[16];
   if (a.fin == 0) {
     // random permutation: the p-th real (record order) of global bin gb gets
     // key r(gb*Z + p), word (g mod 4) of Philox block g/4 with key (seed, 1)
@@ -342,71 +360,67 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
         const uint32_t e = 4u * e4 + q;
-        const bool dummy = v[e].t == kDummyTag;
-        w[e] = ElemRK<T>{v[e].r, uint32_t(ph.v[q]), uint32_t(ph.v[q] >> 32), (p0 + q) | (dummy ? 0x8000u : 0u)};
+        const bool real = p0 + q < load;  // reals occupy the first `load` slots
+        w[e] = ElemRK<T>{v[e].r, real ? uint32_t(ph.v[q]) : ~0u, real ? uint32_t(ph.v[q] >> 32) : ~0u,
+                         real ? p0 + q : 0xFFFFu};
       }
     }
     lds_barrier();  // the record sort's last LDS reads are done
     const LdsRK<T> lrk{srec, stag, srhi, saux};
     bin_bitonic<LZ>(w, lrk, bbase, lq, active);
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) {
-      outr[e] = w[e].r;
-      real[e] = (w[e].aux & 0x8000u) == 0u;
-    }
+    for (uint32_t e = 0; e < 16; ++e) outr[e] = w[e].r;
   } else {
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) {
-      outr[e] = v[e].r;
-      real[e] = v[e].t != kDummyTag;
-    }
+    for (uint32_t e = 0; e < 16; ++e) outr[e] = v[e].r;
   }
-  // bin loads: reals occupy the first slots of every sorted bin
-  uint32_t cnt = 0;
-#pragma unroll
-  for (uint32_t e = 0; e < 16; ++e) cnt += (active && real[e]) ? 1u : 0u;
-  if (active) atomicAdd(&sload[S], cnt);
-  lds_barrier();
-  if (tid == 0) {
-    uint64_t agg = 0;
-    for (uint32_t b = 0; b < NB; ++b) agg += sload[b];
-    uint64_t excl = 0;
+  // look back for the block's output offset (reals occupy the first slots of
+  // every sorted bin).  Wave 0 inspects 64 predecessors per step: it sums
+  // their aggregates back to the nearest one whose inclusive prefix is known.
+  if (tid < 64) {
+    const uint32_t lane = tid;
     const uint64_t kVal = (1ull << 62) - 1ull;
-    if (blk == 0) {
-      __hip_atomic_store(&a.scan[0], (2ull << 62) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&a.scan[blk], (1ull << 62) | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      int64_t p = int64_t(blk) - 1;
-      while (p >= 0) {
-        const unsigned long long w = __hip_atomic_load(&a.scan[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t flag = uint32_t(w >> 62);
-        if (flag == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += w & kVal;
-        if (flag == 2) break;
-        --p;
+    uint64_t excl = 0;
+    int64_t p = int64_t(blk) - 1;
+    while (p >= 0) {
+      const int64_t idx = p - int64_t(lane);
+      const unsigned long long w =
+          idx >= 0 ? __hip_atomic_load(&a.scan[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : (2ull << 62);
+      const uint32_t flag = uint32_t(w >> 62);
+      const unsigned long long inc = __ballot(flag == 2u), none = __ballot(flag == 0u);
+      const uint32_t first2 = inc ? uint32_t(__ffsll((long long)inc) - 1) : 64u;
+      const unsigned long long need = first2 < 63u ? ((2ull << first2) - 1ull) : ~0ull;
+      if (none & need) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
       }
-      __hip_atomic_store(&a.scan[blk], (2ull << 62) | (excl + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t v = lane <= first2 ? (w & kVal) : 0ull;
+#pragma unroll
+      for (uint32_t o = 32; o > 0; o >>= 1) v += __shfl_xor(v, int(o), 64);
+      excl += v;
+      if (first2 < 64u) break;
+      p -= 64;
     }
-    uint64_t off = excl;
-    for (uint32_t u = 0; u < NB; ++u) {
-      const uint32_t b = brev_k(u, klev);
-      soff[2 * b] = uint32_t(off);
-      soff[2 * b + 1] = uint32_t(off >> 32);
-      off += sload[b];
+    if (lane == 0) {
+      if (blk != 0)
+        __hip_atomic_store(&a.scan[blk], (2ull << 62) | (excl + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t off = excl;
+      for (uint32_t u = 0; u < NB; ++u) {
+        const uint32_t b = brev_k(u, klev);
+        soff[2 * b] = uint32_t(off);
+        soff[2 * b + 1] = uint32_t(off >> 32);
+        off += sload[b];
+      }
     }
   }
   lds_barrier();
   if (active) {
     T* OUT = static_cast<T*>(a.out);
     const uint64_t off = (uint64_t(soff[2 * S + 1]) << 32) | soff[2 * S];
-    const uint32_t k = sload[S];
 #pragma unroll
     for (uint32_t e = 0; e < 16; ++e) {
       const uint32_t p = 16u * lq + e;
-      if (p < k && off + p < a.n) OUT[off + p] = outr[e];
+      if (p < load && off + p < a.n) OUT[off + p] = outr[e];
     }
   }
 }
@@ -580,6 +594,13 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t
       }
       if (active) {
         spfx[ms * TPM + lt] = pm[0];
+        if (LAST && lt == 0 && d + 1 == klev) {
+          // bin loads of this block: S0 keeps min(x, Z) reals, S1 the rest of
+          // the pair's reals (exact even when the MergeSplit overflowed)
+          const uint32_t k0 = x < Z ? x : Z;
+          sload[S0] = k0;
+          sload[S1] = x + y - k0;
+        }
         if (lt == 0 && (x > Z || y > Z)) {
           const uint64_t G = S0 >> (d + 1);
           const uint64_t v = brev_k(S0 & ((1u << d) - 1u), d);
@@ -641,8 +662,10 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t
           }
         }
         lds_barrier();
+        // Layout B pairs lanes through DPP only for Z >= 1024; below that the
+        // lanes simply take consecutive slots (conflict-free LDS access).
         const uint32_t lb0 = lt & 1u, lb1 = (lt >> 1) & 1u, rest = lt >> 2;
-        lowB = (lb1 << (LQ - 5)) | (lb0 << (LQ - 6)) | rest;
+        lowB = (LQ >= 11) ? ((lb1 << (LQ - 5)) | (lb0 << (LQ - 6)) | rest) : lt;
         baseB0 = base0 + lowB + (lowB >> 4);
         baseB1 = base1 + lowB + (lowB >> 4);
         // marks prefix at node boundaries (multiples of 16 slots)

@@ -1,7 +1,8 @@
 // sort_kernels.hip — gfx950 kernels of the comparison sorts.
 //
 // 1. The non-oblivious comparison sort that finishes bucket oblivious sort
-//    (Section 3.3): tiles sorted in LDS, then merge-path merge passes.  Its
+//    (Section 3.3): tiles of 4096 records sorted by a register bitonic network,
+//    then merge passes (merge-path splits per 4096-record output tile).  Its
 //    memory accesses depend on the relative order of the (randomly permuted)
 //    records only, which is what the paper's composition argument needs.
 // 2. An oblivious bitonic sort (Batcher), the baseline of the paper's Table 1,
@@ -10,6 +11,7 @@
 #include "bos.h"
 #include "bos_common.h"
 #include "bos_prof.h"
+#include "route_impl.h"
 
 namespace bos {
 
@@ -40,24 +42,6 @@ __device__ __forceinline__ void lds_bitonic(T* s, uint32_t cnt, uint32_t k2_firs
   }
 }
 
-// Sort tiles of `ts` records of buf (in place) ascending; the tail tile is
-// padded with maximal records in LDS.
-template <int R>
-__global__ __launch_bounds__(kTileThreads) void tile_sort_kernel(void* buf, uint64_t n, uint32_t ts) {
-  using T = typename RecOf<R>::T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* s = reinterpret_cast<T*>(smem);
-  T* B = static_cast<T*>(buf);
-  const uint64_t base = uint64_t(blockIdx.x) * ts;
-  for (uint32_t t = threadIdx.x; t < ts; t += blockDim.x)
-    s[lpad(t)] = (base + t < n) ? B[base + t] : max_rec<T>();
-  __syncthreads();
-  // all tiles ascending: direction taken from a bit above the tile
-  lds_bitonic(s, ts, 2, ts, 1, 0);
-  for (uint32_t t = threadIdx.x; t < ts; t += blockDim.x)
-    if (base + t < n) B[base + t] = s[lpad(t)];
-}
-
 // Number of elements of A among the first d outputs of the stable merge of
 // A[0..la) and B[0..lb) (A wins ties).
 template <typename T>
@@ -73,52 +57,103 @@ __device__ __forceinline__ uint64_t merge_path(const T* A, uint64_t la, const T*
   return lo;
 }
 
-constexpr uint32_t kMergeThreads = 256, kMergeItems = 8, kMergeTile = kMergeThreads * kMergeItems;
+// ---- register-resident tile sort and partitioned merge passes -------------
 
-// One merge pass: runs of width w (a multiple of kMergeTile) are merged in
-// pairs from src into dst.  One block produces kMergeTile outputs.
+constexpr uint32_t kRegTileLog = 12, kRegTile = 1u << kRegTileLog;  // 4096 records per tile
+constexpr uint32_t kRegTileThreads = kRegTile / 16;
+
+// Sort tiles of 4096 records of buf in place with the register bitonic network
+// of the per-bin finish (record order; slots past n sort last as dummies).
 template <int R>
-__global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(const void* src_, void* dst_, uint64_t n,
-                                                                    uint64_t w) {
+__global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel(void* buf, uint64_t n) {
   using T = typename RecOf<R>::T;
-  __shared__ T s[kMergeTile + 1];
-  __shared__ uint64_t sp[4];
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr uint32_t ZP = kRegTile + (kRegTile >> 4);
+  T* srec = reinterpret_cast<T*>(smem);
+  T* B = static_cast<T*>(buf);
+  const uint32_t lq = threadIdx.x;
+  const uint64_t base = uint64_t(blockIdx.x) * kRegTile + 16u * lq;
+  ElemR<T> v[16];
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
+  const LdsR<T> lds{srec};
+  bin_bitonic<kRegTileLog>(v, lds, 0u, lq, true);
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e)
+    if (base + e < n) B[base + e] = v[e].r;
+}
+
+constexpr uint32_t kMTile = 4096, kMThreads = 256, kMItems = kMTile / kMThreads;
+
+// Merge-path split of every output tile boundary of one merge pass (runs of
+// width w merged in pairs).  split[2b], split[2b+1] = absolute start of tile
+// b's part of the left and the right run.
+template <int R>
+__global__ void merge_partition_kernel(const void* src_, uint64_t n, uint64_t w, uint64_t* split,
+                                       uint64_t ntiles) {
+  using T = typename RecOf<R>::T;
+  const T* src = static_cast<const T*>(src_);
+  const uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= ntiles) return;
+  const uint64_t o = b * kMTile;
+  const uint64_t lo = (o / (2 * w)) * (2 * w);
+  const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
+  const uint64_t a = merge_path(src + lo, mid - lo, src + mid, hi - mid, o - lo);
+  split[2 * b] = lo + a;
+  split[2 * b + 1] = mid + (o - lo - a);
+}
+
+// One output tile of a merge pass: load the two parts into LDS, every thread
+// merges kMItems outputs (merge path inside the tile), outputs are staged in
+// LDS and written coalesced.
+template <int R>
+__global__ __launch_bounds__(kMThreads) void merge_tile_kernel(const void* src_, void* dst_, uint64_t n, uint64_t w,
+                                                               const uint64_t* split) {
+  using T = typename RecOf<R>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s = reinterpret_cast<T*>(smem);
   const T* src = static_cast<const T*>(src_);
   T* dst = static_cast<T*>(dst_);
-  const uint64_t o0 = uint64_t(blockIdx.x) * kMergeTile;
-  if (o0 >= n) return;
+  const uint64_t b = blockIdx.x;
+  const uint64_t o0 = b * kMTile;
   const uint64_t lo = (o0 / (2 * w)) * (2 * w);
   const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
-  const T* A = src + lo;
-  const T* Bv = src + mid;
-  const uint64_t la = mid - lo, lb = hi - mid;
-  const uint64_t d0 = o0 - lo, d1 = (o0 + kMergeTile < hi ? o0 + kMergeTile : hi) - lo;
-  if (threadIdx.x == 0) sp[0] = merge_path(A, la, Bv, lb, d0);
-  if (threadIdx.x == 32) sp[1] = merge_path(A, la, Bv, lb, d1);
-  __syncthreads();
-  const uint64_t a0 = sp[0], a1 = sp[1], b0 = d0 - a0, b1 = d1 - a1;
+  const uint64_t o1 = o0 + kMTile < hi ? o0 + kMTile : hi;
+  const uint64_t a0 = split[2 * b], b0 = split[2 * b + 1];
+  const uint64_t a1 = o1 == hi ? mid : split[2 * b + 2], b1 = o1 == hi ? hi : split[2 * b + 3];
   const uint32_t na = uint32_t(a1 - a0), nb = uint32_t(b1 - b0), cnt = na + nb;
-  for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) s[t] = t < na ? A[a0 + t] : Bv[b0 + t - na];
+  for (uint32_t t = threadIdx.x; t < cnt; t += kMThreads) s[t] = t < na ? src[a0 + t] : src[b0 + t - na];
   __syncthreads();
-  // each thread merges kMergeItems outputs of the tile
-  const uint32_t dd = threadIdx.x * kMergeItems;
-  if (dd >= cnt) return;
-  uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
-  const T* SA = s;
-  const T* SB = s + na;
-  while (l < h) {
-    const uint32_t md = (l + h) >> 1;
-    if (!rec_less(SB[dd - md - 1], SA[md]))
-      l = md + 1;
-    else
-      h = md;
+  const uint32_t dd = threadIdx.x * kMItems;
+  T out[kMItems];
+  if (dd < cnt) {
+    uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
+    const T* SA = s;
+    const T* SB = s + na;
+    while (l < h) {
+      const uint32_t md = (l + h) >> 1;
+      if (!rec_less(SB[dd - md - 1], SA[md]))
+        l = md + 1;
+      else
+        h = md;
+    }
+    uint32_t ia = l, ib = dd - l;
+#pragma unroll
+    for (uint32_t k = 0; k < kMItems; ++k) {
+      const bool take_a = ia < na && (ib >= nb || !rec_less(SB[ib], SA[ia]));
+      const T va = SA[ia < na ? ia : 0], vb = SB[ib < nb ? ib : 0];
+      out[k] = take_a ? va : vb;
+      ia += take_a ? 1u : 0u;
+      ib += take_a ? 0u : 1u;
+    }
   }
-  uint32_t ia = l, ib = dd - l;
-  const uint32_t end = dd + kMergeItems < cnt ? dd + kMergeItems : cnt;
-  for (uint32_t k = dd; k < end; ++k) {
-    const bool take_a = ia < na && (ib >= nb || !rec_less(SB[ib], SA[ia]));
-    dst[o0 + k] = take_a ? SA[ia++] : SB[ib++];
+  __syncthreads();
+  if (dd < cnt) {
+#pragma unroll
+    for (uint32_t k = 0; k < kMItems; ++k) s[dd + k + (dd >> 4)] = out[k];  // one pad slot per 16
   }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < cnt; t += kMThreads) dst[o0 + t] = s[t + (t >> 4)];
 }
 
 // ---- bitonic baseline ------------------------------------------------------
@@ -226,29 +261,37 @@ static hipError_t allow_lds(K kernel) {
 uint32_t tile_lds_bytes(int rec, uint32_t ts) { return (ts + (ts >> 5)) * uint32_t(rec); }
 
 template <int R>
-static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t ts, hipStream_t s, void** result) {
+static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
+                                    hipStream_t s, void** result) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = allow_lds(tile_sort_kernel<R>);
+    hipError_t e = allow_lds(tile_sort_reg_kernel<R>);
+    if (e == hipSuccess) e = allow_lds(merge_tile_kernel<R>);
     if (e != hipSuccess) return e;
     attr = true;
   }
+  (void)ts;
   *result = buf0;
   if (n <= 1) return hipSuccess;
-  const uint64_t tiles = (n + ts - 1) / ts;
+  const uint64_t tiles = (n + kRegTile - 1) / kRegTile;
+  const uint32_t tile_lds = (kRegTile + (kRegTile >> 4)) * uint32_t(R);
   prof_begin(BOS_K_SORT_TILE, 0, 2 * n * R, s);
-  hipLaunchKernelGGL(tile_sort_kernel<R>, dim3(uint32_t(tiles)), dim3(kTileThreads), tile_lds_bytes(R, ts), s,
-                     buf0, n, ts);
+  hipLaunchKernelGGL(tile_sort_reg_kernel<R>, dim3(uint32_t(tiles)), dim3(kRegTileThreads), tile_lds, s, buf0, n);
   prof_end(s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* src = buf0;
   void* dst = buf1;
   uint32_t pass = 0;
-  for (uint64_t w = ts; w < n; w *= 2) {
-    const uint64_t blocks = (n + kMergeTile - 1) / kMergeTile;
+  const uint64_t mtiles = (n + kMTile - 1) / kMTile;
+  const uint32_t merge_lds = (kMTile + (kMTile >> 4)) * uint32_t(R);
+  for (uint64_t w = kRegTile; w < n; w *= 2) {
     prof_begin(BOS_K_SORT_MERGE, pass++, 2 * n * R, s);
-    hipLaunchKernelGGL(merge_pass_kernel<R>, dim3(uint32_t(blocks)), dim3(kMergeThreads), 0, s, src, dst, n, w);
+    // boundaries 0..mtiles-1 (the end of the last tile is the end of its run pair)
+    hipLaunchKernelGGL(merge_partition_kernel<R>, dim3(uint32_t((mtiles + 255) / 256)), dim3(256), 0, s, src, n, w,
+                       split, mtiles);
+    hipLaunchKernelGGL(merge_tile_kernel<R>, dim3(uint32_t(mtiles)), dim3(kMThreads), merge_lds, s, src, dst, n, w,
+                       split);
     prof_end(s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -262,16 +305,20 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
 
 // Number of merge passes the comparison sort runs for n records and tile ts.
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts) {
+  (void)ts;
   uint32_t c = 0;
   if (n <= 1) return 0;
-  for (uint64_t w = ts; w < n; w *= 2) ++c;
+  for (uint64_t w = kRegTile; w < n; w *= 2) ++c;
   return c;
 }
 
-hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, hipStream_t s,
-                                  void** result) {
-  return rec == 8 ? comparison_sort_t<8>(buf0, buf1, n, ts, s, result)
-                  : comparison_sort_t<16>(buf0, buf1, n, ts, s, result);
+// Bytes of the split array the merge passes need.
+size_t comparison_sort_split_bytes(uint64_t n) { return size_t((n + kMTile - 1) / kMTile + 2) * 16; }
+
+hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
+                                  hipStream_t s, void** result) {
+  return rec == 8 ? comparison_sort_t<8>(buf0, buf1, n, ts, split, s, result)
+                  : comparison_sort_t<16>(buf0, buf1, n, ts, split, s, result);
 }
 
 template <int R>
