@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <vector>
 
@@ -29,6 +30,13 @@ hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, u
                                   hipStream_t s, void** result);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
 size_t comparison_sort_split_bytes(uint64_t n);
+hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
+                                const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
+                                uint32_t lds, hipStream_t s);
+hipError_t launch_sort_batched(int rec, int kind, const SortSeg* segs, uint32_t nsegs, uint32_t total,
+                               hipStream_t s);
+hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
+hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s);
 hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
                           hipStream_t s);
 }  // namespace bos
@@ -317,10 +325,11 @@ void fill_report(bos_report* rep, const Plan& pl, uint32_t attempts, uint64_t ov
 
 // Runs the routing phase with the retry loop; *attempts_out / *ovf_out report.
 bos_status run_routing(const Plan& pl, const bos_params& q, const void* in, void* out, uint32_t fin, char* ws,
-                       hipStream_t s, uint32_t* attempts_out, uint64_t* ovf_out) {
-  uint64_t last_ovf = kNoOverflow;
+                       hipStream_t s, uint32_t* attempts_out, uint64_t* ovf_out, uint32_t first_attempt = 0,
+                       uint64_t prev_ovf = kNoOverflow) {
+  uint64_t last_ovf = prev_ovf;
   const uint32_t tries = (q.flags & BOS_SYNC) ? q.max_retries + 1 : 1;
-  for (uint32_t att = 0; att < tries; ++att) {
+  for (uint32_t att = first_attempt; att < tries; ++att) {
     hipError_t e = enqueue_routing(pl, in, out, q.seed, att, fin, ws, s);
     if (e != hipSuccess) return BOS_ERR_HIP;
     *attempts_out = att + 1;
@@ -346,6 +355,332 @@ bool has_gpu() {
   int c = 0;
   return hipGetDeviceCount(&c) == hipSuccess && c > 0;
 }
+
+// ---- batched engine -----------------------------------------------------
+//
+// bos_sort_batched plans every instance on its own (same Z and k), gives each
+// a workspace region, and runs all of them pass-major: one launch per routing
+// pass index and pass kind (first / middle / last / single) over a table of
+// per-instance pass arguments, then one batched tile sort and one batched
+// launch pair per merge pass.  The launch sequence is captured once into a
+// hipGraph per batch shape (sizes, record type, Z, k, workspace) and
+// replayed; the tables (pointers, seeds) are re-uploaded before every replay.
+
+struct BatchJob {
+  const void* in = nullptr;
+  void* out = nullptr;
+  uint64_t n = 0, seed = 0;
+  Plan pl;
+  char* ws = nullptr;
+  void* start = nullptr;  // routing output (where the comparison sort starts)
+  void* other = nullptr;
+  uint32_t merges = 0;
+  bool special = false;   // single bin (L = 0): routed by the generic kernel
+};
+
+struct BLaunch {
+  int kind = 0;  // 0 fill, 1 route, 2 tile sort, 3 merge pass, 4 status, 5 plain routing of one job
+  int mode = 0;  // route: bit 0 first, bit 1 last
+  uint32_t nsegs = 0, blocks = 0, threads = 0, lds = 0, total = 0, job = 0;
+  size_t tab = 0, aux = 0;
+};
+
+struct Batch {
+  std::vector<BatchJob> jobs;
+  std::vector<BLaunch> launches;
+  std::vector<char> tables;
+  size_t tab_base = 0;  // offset of the tables in the workspace
+  size_t total = 0;
+  bool batched = true;
+  uint32_t lz = 9;
+  int rec = 8;
+};
+
+template <typename V>
+size_t push_table(std::vector<char>& tab, const std::vector<V>& v) {
+  size_t off = align_up(tab.size());
+  tab.resize(off + v.size() * sizeof(V));
+  if (!v.empty()) std::memcpy(tab.data() + off, v.data(), v.size() * sizeof(V));
+  return off;
+}
+
+bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t count, int rec, const bos_params& q,
+                       char* ws, Batch* b) {
+  b->jobs.assign(count, BatchJob());
+  b->rec = rec;
+  b->batched = !(q.flags & BOS_GENERIC_ROUTING) && (q.z == 32 || q.z == 256 || q.z == 512 || q.z == 1024);
+  size_t off = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    BatchJob& j = b->jobs[i];
+    j.n = ns[i];
+    if (inst) {
+      j.in = inst[i].in;
+      j.out = inst[i].out;
+      j.seed = inst[i].seed;
+    }
+    const bos_status st = make_plan(j.n, rec, q, true, &j.pl);
+    if (st != BOS_OK) return st;
+    b->lz = j.pl.lz;
+    j.ws = ws ? ws + off : nullptr;
+    off = align_up(off + j.pl.total);
+    j.merges = comparison_sort_passes(j.n, j.pl.tile);
+    char* tmp = j.ws ? j.ws + j.pl.off_rec[(j.pl.P + 1) & 1] : nullptr;
+    j.start = (j.merges % 2 == 0) ? j.out : static_cast<void*>(tmp);
+    j.other = (j.merges % 2 == 0) ? static_cast<void*>(tmp) : j.out;
+    j.special = j.pl.L == 0 || !use_route_kernel(j.pl, 0);
+  }
+  b->tab_base = align_up(off);
+  if (!b->batched) {
+    b->total = b->tab_base;
+    return BOS_OK;
+  }
+  std::vector<char>& tab = b->tables;
+  tab.clear();
+  auto dev = [&](size_t o) -> char* { return ws ? ws + b->tab_base + o : nullptr; };
+  // 0. status words
+  {
+    std::vector<FillSeg> f;
+    for (const BatchJob& j : b->jobs)
+      if (j.n && !j.special)
+        f.push_back(FillSeg{reinterpret_cast<unsigned long long*>(j.ws + j.pl.off_status), 2 + j.pl.nblocks_last, 0});
+    BLaunch l;
+    l.kind = 0;
+    l.nsegs = uint32_t(f.size());
+    l.tab = push_table(tab, f);
+    if (l.nsegs) b->launches.push_back(l);
+  }
+  // 1. routing passes, pass-major
+  uint32_t maxP = 0;
+  for (const BatchJob& j : b->jobs)
+    if (j.n && !j.special) maxP = std::max(maxP, j.pl.P);
+  for (uint32_t t = 0; t < maxP; ++t) {
+    for (int mode : {3, 1, 0, 2}) {
+      std::vector<PassArgs> segs;
+      std::vector<uint32_t> starts;
+      uint32_t blocks = 0, threads = 64, lds = 0;
+      for (const BatchJob& j : b->jobs) {
+        if (!j.n || j.special || t >= j.pl.P) continue;
+        const bool first = t == 0, last = t + 1 == j.pl.P;
+        if (((first ? 1 : 0) | (last ? 2 : 0)) != mode) continue;
+        PassArgs a;
+        std::memset(&a, 0, sizeof(a));
+        const Plan& pl = j.pl;
+        unsigned long long* status = reinterpret_cast<unsigned long long*>(j.ws + pl.off_status);
+        a.x_in = j.in;
+        a.out = j.start;
+        a.rec_in = j.ws + pl.off_rec[(t + 1) & 1];
+        a.tag_in = reinterpret_cast<const uint32_t*>(j.ws + pl.off_tag[(t + 1) & 1]);
+        a.rec_out = j.ws + pl.off_rec[t & 1];
+        a.tag_out = reinterpret_cast<uint32_t*>(j.ws + pl.off_tag[t & 1]);
+        a.status = status;
+        a.ticket = reinterpret_cast<uint32_t*>(status + 1);
+        a.scan = status + 2;
+        a.n = pl.n;
+        a.buckets = pl.B;
+        a.seed = j.seed;
+        a.z = pl.Z;
+        a.lz = pl.lz;
+        a.levels = pl.L;
+        a.level0 = pl.lev0[t];
+        a.klev = pl.klev[t];
+        a.attempt = 0;
+        a.fin = 1;
+        segs.push_back(a);
+        starts.push_back(blocks);
+        blocks += uint32_t(pl.B >> pl.klev[t]);
+        threads = std::max(threads, uint32_t((pl.Z << pl.klev[t]) >> 4));
+        lds = std::max(lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false));
+      }
+      if (segs.empty()) continue;
+      BLaunch l;
+      l.kind = 1;
+      l.mode = mode;
+      l.nsegs = uint32_t(segs.size());
+      l.blocks = blocks;
+      l.threads = threads;
+      l.lds = lds;
+      l.tab = push_table(tab, segs);
+      l.aux = push_table(tab, starts);
+      b->launches.push_back(l);
+    }
+  }
+  for (uint32_t i = 0; i < count; ++i)
+    if (b->jobs[i].n && b->jobs[i].special) {
+      BLaunch l;
+      l.kind = 5;
+      l.job = i;
+      b->launches.push_back(l);
+    }
+  // 2. tile sort
+  const uint64_t T = kDefaultTile;
+  {
+    std::vector<SortSeg> segs;
+    uint32_t tiles = 0;
+    for (const BatchJob& j : b->jobs) {
+      if (j.n <= 1) continue;
+      const uint32_t c = uint32_t((j.n + T - 1) / T);
+      segs.push_back(SortSeg{j.start, nullptr, j.n, 0, nullptr, tiles, c});
+      tiles += c;
+    }
+    BLaunch l;
+    l.kind = 2;
+    l.nsegs = uint32_t(segs.size());
+    l.total = tiles;
+    l.tab = push_table(tab, segs);
+    if (l.nsegs) b->launches.push_back(l);
+  }
+  // 3. merge passes
+  uint32_t maxM = 0;
+  for (const BatchJob& j : b->jobs) maxM = std::max(maxM, j.merges);
+  for (uint32_t pass = 0; pass < maxM; ++pass) {
+    std::vector<SortSeg> segs;
+    uint32_t tiles = 0;
+    for (const BatchJob& j : b->jobs) {
+      if (pass >= j.merges) continue;
+      const uint32_t c = uint32_t((j.n + T - 1) / T);
+      void* src = (pass % 2 == 0) ? j.start : j.other;
+      void* dst = (pass % 2 == 0) ? j.other : j.start;
+      segs.push_back(SortSeg{src, dst, j.n, T << pass, reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), tiles, c});
+      tiles += c;
+    }
+    BLaunch l;
+    l.kind = 3;
+    l.nsegs = uint32_t(segs.size());
+    l.total = tiles;
+    l.tab = push_table(tab, segs);
+    b->launches.push_back(l);
+  }
+  // 4. per-instance status
+  {
+    std::vector<unsigned long long*> st;
+    for (const BatchJob& j : b->jobs)
+      st.push_back(j.n ? reinterpret_cast<unsigned long long*>(j.ws + j.pl.off_status) : nullptr);
+    BLaunch l;
+    l.kind = 4;
+    l.nsegs = count;
+    l.tab = push_table(tab, st);
+    b->launches.push_back(l);
+  }
+  (void)dev;
+  b->total = b->tab_base + align_up(tab.size());
+  return BOS_OK;
+}
+
+hipError_t enqueue_batch(const Batch& b, char* tables, hipStream_t s, uint32_t* d_status) {
+  for (const BLaunch& l : b.launches) {
+    hipError_t e = hipSuccess;
+    switch (l.kind) {
+      case 0:
+        e = launch_fill_status_batched(reinterpret_cast<const FillSeg*>(tables + l.tab), l.nsegs, s);
+        break;
+      case 1:
+        e = launch_route_batched(b.rec, b.lz, (l.mode & 1) != 0, (l.mode & 2) != 0,
+                                 reinterpret_cast<const PassArgs*>(tables + l.tab),
+                                 reinterpret_cast<const uint32_t*>(tables + l.aux), l.nsegs, l.blocks, l.threads,
+                                 l.lds, s);
+        break;
+      case 2:
+        e = launch_sort_batched(b.rec, 0, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
+        break;
+      case 3:
+        e = launch_sort_batched(b.rec, 1, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
+        if (e == hipSuccess)
+          e = launch_sort_batched(b.rec, 2, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
+        break;
+      case 4:
+        e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(tables + l.tab), d_status, l.nsegs, s);
+        break;
+      case 5: {
+        const BatchJob& j = b.jobs[l.job];
+        e = enqueue_routing(j.pl, j.in, j.start, j.seed, 0, 1, j.ws, s);
+        break;
+      }
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> host_tables;  // kept alive while the upload is in flight
+};
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry> g_graphs;
+hipStream_t g_cap_stream = nullptr;
+hipEvent_t g_ev_in = nullptr, g_ev_out = nullptr;
+
+std::string batch_key(const Batch& b, const bos_params& q, const char* tables, const uint32_t* d_status) {
+  std::string k;
+  auto add = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+  const uint32_t cnt = uint32_t(b.jobs.size());
+  add(&cnt, 4);
+  add(&b.rec, sizeof(b.rec));
+  add(&q.z, 4);
+  add(&q.k, 4);
+  add(&tables, sizeof(tables));
+  add(&d_status, sizeof(d_status));
+  for (const BatchJob& j : b.jobs) add(&j.n, 8);
+  // jobs whose routing is launched directly carry their pointers in kernel
+  // arguments, not in the tables
+  for (const BatchJob& j : b.jobs)
+    if (j.special) {
+      add(&j.in, sizeof(j.in));
+      add(&j.start, sizeof(j.start));
+      add(&j.seed, 8);
+    }
+  return k;
+}
+
+bos_status run_batch(Batch& b, const bos_params& q, hipStream_t s, uint32_t* d_status) {
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  // the tables live right after the per-instance regions of the workspace
+  char* tables = b.jobs[0].ws + b.tab_base;
+  if (!g_cap_stream) {
+    if (hipStreamCreateWithFlags(&g_cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g_ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g_ev_out, hipEventDisableTiming) != hipSuccess)
+      return BOS_ERR_HIP;
+  }
+  const std::string key = batch_key(b, q, tables, d_status);
+  GraphEntry& ge = g_graphs[key];
+  ge.host_tables = b.tables;
+  hipStream_t cs = g_cap_stream;
+  if (hipEventRecord(g_ev_in, s) != hipSuccess || hipStreamWaitEvent(cs, g_ev_in, 0) != hipSuccess) return BOS_ERR_HIP;
+  if (!ge.host_tables.empty() &&
+      hipMemcpyAsync(tables, ge.host_tables.data(), ge.host_tables.size(), hipMemcpyHostToDevice, cs) != hipSuccess)
+    return BOS_ERR_HIP;
+  if (!ge.exec) {
+    const bool prof = g_prof_on;
+    g_prof_on = false;  // no event records inside the captured graph
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      const hipError_t e1 = enqueue_batch(b, tables, cs, d_status);
+      e = hipStreamEndCapture(cs, &graph);
+      if (e1 != hipSuccess) e = e1;
+    }
+    g_prof_on = prof;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g_graphs.erase(key);
+      return BOS_ERR_HIP;
+    }
+  }
+  prof_begin(BOS_K_OTHER, 0, 0, cs);
+  hipError_t e = hipGraphLaunch(ge.exec, cs);
+  prof_end(cs);
+  if (e != hipSuccess) return BOS_ERR_HIP;
+  if (hipEventRecord(g_ev_out, cs) != hipSuccess || hipStreamWaitEvent(s, g_ev_out, 0) != hipSuccess)
+    return BOS_ERR_HIP;
+  // the host copy of the tables must outlive the upload
+  if (hipStreamSynchronize(cs) != hipSuccess) return BOS_ERR_HIP;
+  return BOS_OK;
+}
+
+bos_status sort_batched_sequential(const bos_instance* inst, uint32_t count, bos_rec rec, bos_params q, void* ws,
+                                   size_t ws_bytes, hipStream_t s, uint32_t* d_status, bos_report* rep);
 
 }  // namespace
 
@@ -446,42 +781,80 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
 }
 
 size_t bos_batched_workspace_bytes(const uint64_t* n, uint32_t count, bos_rec rec, const bos_params* p) {
-  size_t mx = 0;
-  for (uint32_t i = 0; i < count; ++i) mx = std::max(mx, bos_workspace_bytes(n[i], rec, p));
-  return mx;
+  if (!has_gpu() || (count && !n)) return 0;
+  bos_params q = resolve(p);
+  q.min_security_bits = 0;
+  Batch b;
+  if (build_batch(nullptr, n, count, int(rec), q, nullptr, &b) != BOS_OK) return 0;
+  return b.total;
 }
 
 bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec rec, const bos_params* p,
                             void* ws, size_t ws_bytes, void* stream, uint32_t* d_status, bos_report* rep) {
   if (!has_gpu()) return BOS_ERR_UNSUPPORTED;
   if (count && !inst) return BOS_ERR_INVALID_ARG;
-  bos_params q = resolve(p);
-  bos_status worst = BOS_OK;
-  uint64_t bytes = 0;
-  uint32_t attempts = 0;
-  std::vector<uint32_t> host_status(count, BOS_OK);
-  for (uint32_t i = 0; i < count; ++i) {
-    q.seed = inst[i].seed;
-    bos_report r;
-    const bos_status st = bos_sort(inst[i].in, inst[i].out, inst[i].n, rec, &q, ws, ws_bytes, stream, &r);
-    host_status[i] = st;
-    if (st != BOS_OK && worst == BOS_OK) worst = st;
-    bytes += r.algorithmic_bytes;
-    attempts += r.attempts;
-  }
-  if (d_status && count) {
-    if (hipMemcpyAsync(d_status, host_status.data(), count * 4, hipMemcpyHostToDevice,
-                       static_cast<hipStream_t>(stream)) != hipSuccess ||
-        hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
-      return BOS_ERR_HIP;
-  }
+  const bos_params q = resolve(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<uint64_t> ns(count);
+  for (uint32_t i = 0; i < count; ++i) ns[i] = inst[i].n;
+  Batch b;
+  bos_status st = build_batch(inst, ns.data(), count, int(rec), q, static_cast<char*>(ws), &b);
+  if (st != BOS_OK) return st;
+  if (!ws || ws_bytes < b.total) return BOS_ERR_WORKSPACE;
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
-    rep->attempts = attempts;
     rep->z = q.z;
-    rep->algorithmic_bytes = bytes;
+    rep->k = q.k;
+    rep->tile = kDefaultTile;
     rep->first_overflow_level = -1;
     rep->first_overflow_pair = -1;
+  }
+  if (count == 0) return BOS_OK;
+  if (!b.batched) return sort_batched_sequential(inst, count, rec, q, ws, ws_bytes, s, d_status, rep);
+  if (!d_status) return BOS_ERR_INVALID_ARG;
+  st = run_batch(b, q, s, d_status);
+  if (st != BOS_OK) return st;
+  uint32_t attempts = 0;
+  uint64_t bytes = 0;
+  bos_status worst = BOS_OK;
+  std::vector<uint32_t> hs(count, 0);
+  if (q.flags & BOS_SYNC) {
+    if (hipMemcpyAsync(hs.data(), d_status, count * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return BOS_ERR_HIP;
+    // Instances whose first attempt overflowed continue alone from attempt 1
+    // (the same attempts and labels bos_sort would use).
+    for (uint32_t i = 0; i < count; ++i) {
+      const BatchJob& j = b.jobs[i];
+      uint32_t att = j.n ? 1u : 0u;
+      if (hs[i] != BOS_OK) {
+        uint64_t ovf = kNoOverflow, prev = kNoOverflow;
+        if (hipMemcpyAsync(&prev, j.ws + j.pl.off_status, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return BOS_ERR_HIP;
+        bos_params qi = q;
+        qi.seed = inst[i].seed;
+        const bos_status rs = run_routing(j.pl, qi, j.in, j.start, 1, j.ws, s, &att, &ovf, 1, prev);
+        if (rs == BOS_OK) {
+          void* result = nullptr;
+          if (launch_comparison_sort(j.pl.rec, j.start, j.other, j.n, j.pl.tile,
+                                     reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), s, &result) != hipSuccess)
+            return BOS_ERR_HIP;
+        }
+        hs[i] = rs;
+        if (hipMemcpyAsync(d_status + i, &hs[i], 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return BOS_ERR_HIP;
+        if (rs != BOS_OK && worst == BOS_OK) worst = rs;
+      }
+      attempts += att;
+      bytes += routing_bytes(j.pl) + uint64_t(2 + 2 * j.merges) * j.n * j.pl.rec;
+    }
+  }
+  if (rep) {
+    rep->attempts = attempts;
+    rep->algorithmic_bytes = bytes;
+    rep->buckets = count;
   }
   return worst;
 }
@@ -506,7 +879,12 @@ bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, 
   return hip_status(launch_bitonic(int(rec), in, out, n, ws, N, kBitonicTile, static_cast<hipStream_t>(stream)));
 }
 
-void bos_release_cache(void) {}
+void bos_release_cache(void) {
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (auto& kv : g_graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  g_graphs.clear();
+}
 
 void bos_profile_enable(int on) {
   g_prof_on = on != 0;
@@ -591,3 +969,33 @@ bos_status bos_debug_levels(const void* in, uint64_t n, bos_rec rec, const bos_p
 }
 
 }  // extern "C"
+
+namespace {
+bos_status sort_batched_sequential(const bos_instance* inst, uint32_t count, bos_rec rec, bos_params q, void* ws,
+                                   size_t ws_bytes, hipStream_t s, uint32_t* d_status, bos_report* rep) {
+  bos_status worst = BOS_OK;
+  uint64_t bytes = 0;
+  uint32_t attempts = 0;
+  std::vector<uint32_t> host_status(count, BOS_OK);
+  for (uint32_t i = 0; i < count; ++i) {
+    q.seed = inst[i].seed;
+    bos_report r;
+    const bos_status st = bos_sort(inst[i].in, inst[i].out, inst[i].n, rec, &q, ws, ws_bytes, s, &r);
+    host_status[i] = st;
+    if (st != BOS_OK && worst == BOS_OK) worst = st;
+    bytes += r.algorithmic_bytes;
+    attempts += r.attempts;
+  }
+  if (d_status && count) {
+    if (hipMemcpyAsync(d_status, host_status.data(), count * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return BOS_ERR_HIP;
+  }
+  if (rep) {
+    rep->attempts = attempts;
+    rep->algorithmic_bytes = bytes;
+    rep->buckets = count;
+  }
+  return worst;
+}
+}  // namespace

@@ -96,6 +96,24 @@ struct PassArgs {
   uint32_t fin;               // last pass: 0 = random permutation of each bin, 1 = sort each bin
 };
 
+// One instance of a batched comparison-sort launch (tile sort or merge pass).
+struct SortSeg {
+  void* src;         // tile sort: the buffer sorted in place; merge pass: source runs
+  void* dst;         // merge pass: destination
+  uint64_t n;        // records of the instance
+  uint64_t w;        // merge pass: run width
+  uint64_t* split;   // merge pass: this instance's split array
+  uint32_t first;    // first block (and first partition thread) of the segment in the launch
+  uint32_t count;    // 4096-record tiles of the instance
+};
+
+// One instance's status words to initialise before its first routing pass.
+struct FillSeg {
+  unsigned long long* p;  // status word, ticket, look-back words
+  uint32_t count;
+  uint32_t pad;
+};
+
 // Dynamic LDS bytes of a routing block (must match the carve in the kernel).
 __host__ __device__ inline uint32_t pass_lds_bytes(int rec, uint32_t z, uint32_t klev, bool last_shuffle) {
   const uint32_t m = z << klev;

@@ -426,8 +426,11 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
 }
 
 // R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last.
-template <int R, int LZ, int MODE>
-__global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t nitems) {
+// Body of one routing launch.  BATCH = false: a persistent workgroup walks
+// over items blockIdx.x, + gridDim.x, ... (last pass: tickets).  BATCH = true:
+// the workgroup runs the single item `item0` of one instance of a batch.
+template <int R, int LZ, int MODE, bool BATCH>
+__device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, uint32_t item0) {
   using T = typename RecOf<R>::T;
   constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0;
   constexpr uint32_t Z = 1u << LZ, LQ = LZ + 1, TPM = 1u << (LQ - 4), ZP = Z + (Z >> 4);
@@ -802,9 +805,17 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t
     }
   };
 
-  if constexpr (!LAST) {
+  if constexpr (!LAST && BATCH) {
+    if (FIRST && !aligned) {
+      staged_first_load(item0);
+    } else {
+      issue_load(item0, rv, tv);
+      finish_load(item0, tv);
+    }
+    process(item0);
+  } else if constexpr (!LAST) {
     // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...
-    uint32_t item = blockIdx.x;
+    uint32_t item = item0;
     if (item >= nitems) return;
     if (FIRST && !aligned) {
       staged_first_load(item);
@@ -854,6 +865,29 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t
     // every final bin (LDS bucket S) now sits in LDS with padded slots
     finish_bins<R, LZ>(a, blk, klev, srec, stag, srhi, saux, sload, soff);
   }
+  (void)nitems;
+}
+
+template <int R, int LZ, int MODE>
+__global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t nitems) {
+  route_run<R, LZ, MODE, false>(a, nitems, blockIdx.x);
+}
+
+// Batched routing: segment s of the launch is one instance's pass; its blocks
+// are blockIdx.x in [blk_start[s], blk_start[s+1]).
+template <int R, int LZ, int MODE>
+__global__ __launch_bounds__(kMaxThreads) void route_kernel_b(const PassArgs* segs, const uint32_t* blk_start,
+                                                              uint32_t nsegs) {
+  uint32_t lo = 0, hi = nsegs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (blk_start[mid] <= blockIdx.x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const PassArgs a = segs[lo];
+  route_run<R, LZ, MODE, true>(a, 0u, blockIdx.x - blk_start[lo]);
 }
 
 }  // namespace bos

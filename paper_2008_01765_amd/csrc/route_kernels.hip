@@ -49,4 +49,37 @@ hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint3
   }
 }
 
+hipError_t launch_route_b_r8_z5(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r8_z8(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r8_z9(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r8_z10(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r16_z5(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r16_z8(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r16_z9(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+hipError_t launch_route_b_r16_z10(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads, uint32_t lds, int mode, hipStream_t s);
+
+// Batched routing pass (all segments share record size, Z and mode); batches
+// are built for Z in {256, 512, 1024} and, for tests of the overflow path, 32.
+hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
+                                const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
+                                uint32_t lds, hipStream_t s) {
+  const int mode = (first ? 1 : 0) | (last ? 2 : 0);
+  if (rec == 8) {
+    switch (lz) {
+      case 5: return launch_route_b_r8_z5(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+      case 8: return launch_route_b_r8_z8(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+      case 9: return launch_route_b_r8_z9(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+      case 10: return launch_route_b_r8_z10(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+      default: return hipErrorNotSupported;
+    }
+  }
+  switch (lz) {
+    case 5: return launch_route_b_r16_z5(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+    case 8: return launch_route_b_r16_z8(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+    case 9: return launch_route_b_r16_z9(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+    case 10: return launch_route_b_r16_z10(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
 }  // namespace bos

@@ -32,6 +32,33 @@ hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hip
   return hipGetLastError();
 }
 
+// Batched launch: nsegs segments (device tables segs / blk_start), total
+// `blocks` workgroups of `threads` lanes and `lds` bytes of LDS each.
+template <int R, int LZ, int MODE>
+hipError_t launch_route_bt(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks,
+                           uint32_t threads, uint32_t lds, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&route_kernel_b<R, LZ, MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((route_kernel_b<R, LZ, MODE>), dim3(blocks), dim3(threads), lds, s, segs, blk_start, nsegs);
+  return hipGetLastError();
+}
+
+template <int R, int LZ>
+hipError_t launch_route_bm(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks,
+                           uint32_t threads, uint32_t lds, int mode, hipStream_t s) {
+  switch (mode) {
+    case 0: return launch_route_bt<R, LZ, 0>(segs, blk_start, nsegs, blocks, threads, lds, s);
+    case 1: return launch_route_bt<R, LZ, 1>(segs, blk_start, nsegs, blocks, threads, lds, s);
+    case 2: return launch_route_bt<R, LZ, 2>(segs, blk_start, nsegs, blocks, threads, lds, s);
+    default: return launch_route_bt<R, LZ, 3>(segs, blk_start, nsegs, blocks, threads, lds, s);
+  }
+}
+
 template <int R, int LZ>
 hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
   switch (mode) {

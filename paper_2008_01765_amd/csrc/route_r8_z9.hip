@@ -5,4 +5,8 @@ namespace bos {
 hipError_t launch_route_r8_z9(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
   return launch_route_m<8, 9>(a, mode, nitems, grid, s);
 }
+hipError_t launch_route_b_r8_z9(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks,
+                               uint32_t threads, uint32_t lds, int mode, hipStream_t s) {
+  return launch_route_bm<8, 9>(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
+}
 }  // namespace bos

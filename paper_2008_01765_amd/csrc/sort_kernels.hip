@@ -62,17 +62,17 @@ __device__ __forceinline__ uint64_t merge_path(const T* A, uint64_t la, const T*
 constexpr uint32_t kRegTileLog = 12, kRegTile = 1u << kRegTileLog;  // 4096 records per tile
 constexpr uint32_t kRegTileThreads = kRegTile / 16;
 
-// Sort tiles of 4096 records of buf in place with the register bitonic network
-// of the per-bin finish (record order; slots past n sort last as dummies).
+// Sort one tile of 4096 records of buf in place with the register bitonic
+// network of the per-bin finish (record order; slots past n sort last as the
+// maximal record).
 template <int R>
-__global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel(void* buf, uint64_t n) {
+__device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t tile) {
   using T = typename RecOf<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr uint32_t ZP = kRegTile + (kRegTile >> 4);
   T* srec = reinterpret_cast<T*>(smem);
   T* B = static_cast<T*>(buf);
   const uint32_t lq = threadIdx.x;
-  const uint64_t base = uint64_t(blockIdx.x) * kRegTile + 16u * lq;
+  const uint64_t base = tile * kRegTile + 16u * lq;
   ElemR<T> v[16];
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
@@ -83,18 +83,40 @@ __global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel(void* bu
     if (base + e < n) B[base + e] = v[e].r;
 }
 
+template <int R>
+__global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel(void* buf, uint64_t n) {
+  tile_sort_one<R>(buf, n, blockIdx.x);
+}
+
+// Segment holding launch index x (largest s with segs[s].first <= x).
+__device__ __forceinline__ uint32_t find_seg(const SortSeg* segs, uint32_t nsegs, uint32_t x) {
+  uint32_t lo = 0, hi = nsegs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segs[mid].first <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int R>
+__global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel_b(const SortSeg* segs, uint32_t nsegs) {
+  const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
+  tile_sort_one<R>(sg.src, sg.n, blockIdx.x - sg.first);
+}
+
 constexpr uint32_t kMTile = 4096, kMThreads = 256, kMItems = kMTile / kMThreads;
 
-// Merge-path split of every output tile boundary of one merge pass (runs of
-// width w merged in pairs).  split[2b], split[2b+1] = absolute start of tile
-// b's part of the left and the right run.
+// Merge-path split of output tile boundary b of one merge pass (runs of width
+// w merged in pairs): absolute start of the tile's part of the left and the
+// right run.
 template <int R>
-__global__ void merge_partition_kernel(const void* src_, uint64_t n, uint64_t w, uint64_t* split,
-                                       uint64_t ntiles) {
+__device__ __forceinline__ void merge_partition_one(const void* src_, uint64_t n, uint64_t w, uint64_t* split,
+                                                    uint64_t b) {
   using T = typename RecOf<R>::T;
   const T* src = static_cast<const T*>(src_);
-  const uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (b >= ntiles) return;
   const uint64_t o = b * kMTile;
   const uint64_t lo = (o / (2 * w)) * (2 * w);
   const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
@@ -103,18 +125,31 @@ __global__ void merge_partition_kernel(const void* src_, uint64_t n, uint64_t w,
   split[2 * b + 1] = mid + (o - lo - a);
 }
 
+template <int R>
+__global__ void merge_partition_kernel(const void* src, uint64_t n, uint64_t w, uint64_t* split, uint64_t ntiles) {
+  const uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b < ntiles) merge_partition_one<R>(src, n, w, split, b);
+}
+
+template <int R>
+__global__ void merge_partition_kernel_b(const SortSeg* segs, uint32_t nsegs, uint32_t total) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= total) return;
+  const SortSeg sg = segs[find_seg(segs, nsegs, x)];
+  merge_partition_one<R>(sg.src, sg.n, sg.w, sg.split, x - sg.first);
+}
+
 // One output tile of a merge pass: load the two parts into LDS, every thread
 // merges kMItems outputs (merge path inside the tile), outputs are staged in
 // LDS and written coalesced.
 template <int R>
-__global__ __launch_bounds__(kMThreads) void merge_tile_kernel(const void* src_, void* dst_, uint64_t n, uint64_t w,
-                                                               const uint64_t* split) {
+__device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uint64_t n, uint64_t w,
+                                               const uint64_t* split, uint64_t b) {
   using T = typename RecOf<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   T* s = reinterpret_cast<T*>(smem);
   const T* src = static_cast<const T*>(src_);
   T* dst = static_cast<T*>(dst_);
-  const uint64_t b = blockIdx.x;
   const uint64_t o0 = b * kMTile;
   const uint64_t lo = (o0 / (2 * w)) * (2 * w);
   const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
@@ -154,6 +189,31 @@ __global__ __launch_bounds__(kMThreads) void merge_tile_kernel(const void* src_,
   }
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < cnt; t += kMThreads) dst[o0 + t] = s[t + (t >> 4)];
+}
+
+template <int R>
+__global__ __launch_bounds__(kMThreads) void merge_tile_kernel(const void* src, void* dst, uint64_t n, uint64_t w,
+                                                               const uint64_t* split) {
+  merge_tile_one<R>(src, dst, n, w, split, blockIdx.x);
+}
+
+template <int R>
+__global__ __launch_bounds__(kMThreads) void merge_tile_kernel_b(const SortSeg* segs, uint32_t nsegs) {
+  const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
+  merge_tile_one<R>(sg.src, sg.dst, sg.n, sg.w, sg.split, blockIdx.x - sg.first);
+}
+
+// Batched status words: segment s gets p[0] = no overflow, p[1..count) = 0.
+__global__ void fill_status_kernel_b(const FillSeg* segs, uint32_t nsegs) {
+  if (blockIdx.x >= nsegs) return;
+  const FillSeg sg = segs[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < sg.count; i += blockDim.x) sg.p[i] = i == 0 ? kNoOverflow : 0ull;
+}
+
+// Per-instance outcome of a batch: BOS_OK (0) or BOS_ERR_OVERFLOW (2).
+__global__ void batch_status_kernel(unsigned long long* const* status, uint32_t* out, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (status[i] == nullptr || *status[i] == kNoOverflow) ? 0u : 2u;
 }
 
 // ---- bitonic baseline ------------------------------------------------------
@@ -366,6 +426,49 @@ static hipError_t bitonic_t(const void* in, void* out, uint64_t n, void* ws, uin
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipMemcpyAsync(out, ws, n * R, hipMemcpyDeviceToDevice, s);
+}
+
+template <int R>
+static hipError_t batched_sort_launch_t(int kind, const SortSeg* segs, uint32_t nsegs, uint32_t total,
+                                        hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = allow_lds(tile_sort_reg_kernel_b<R>);
+    if (e == hipSuccess) e = allow_lds(merge_tile_kernel_b<R>);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  if (total == 0) return hipSuccess;
+  if (kind == 0) {
+    const uint32_t lds = (kRegTile + (kRegTile >> 4)) * uint32_t(R);
+    hipLaunchKernelGGL(tile_sort_reg_kernel_b<R>, dim3(total), dim3(kRegTileThreads), lds, s, segs, nsegs);
+  } else if (kind == 1) {
+    hipLaunchKernelGGL(merge_partition_kernel_b<R>, dim3((total + 255) / 256), dim3(256), 0, s, segs, nsegs, total);
+  } else {
+    const uint32_t lds = (kMTile + (kMTile >> 4)) * uint32_t(R);
+    hipLaunchKernelGGL(merge_tile_kernel_b<R>, dim3(total), dim3(kMThreads), lds, s, segs, nsegs);
+  }
+  return hipGetLastError();
+}
+
+// Batched comparison-sort launch: kind 0 = tile sort, 1 = merge partition,
+// 2 = merge tiles; `total` = tiles summed over the segments.
+hipError_t launch_sort_batched(int rec, int kind, const SortSeg* segs, uint32_t nsegs, uint32_t total,
+                               hipStream_t s) {
+  return rec == 8 ? batched_sort_launch_t<8>(kind, segs, nsegs, total, s)
+                  : batched_sort_launch_t<16>(kind, segs, nsegs, total, s);
+}
+
+hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s) {
+  if (nsegs == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_status_kernel_b, dim3(nsegs), dim3(256), 0, s, segs, nsegs);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_status_kernel, dim3((count + 255) / 256), dim3(256), 0, s, status, out, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
