@@ -44,6 +44,13 @@ def parse():
     ap.add_argument("--cpu-log2n", type=int, default=24, help="oracle sample size; 0 skips it")
     ap.add_argument("--mode", default="sort", choices=("sort", "orp", "copy"),
                     help="copy: a plain device copy of the input (counter calibration)")
+    ap.add_argument("--batched-count", type=int, default=4096,
+                    help="instances of the batched workload (log-uniform 2^10..2^20, 16 B, total <= 2^28); 0 skips")
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--serving-requests", type=int, default=1024,
+                    help="requests of the serving workload (log-uniform 2^12..2^24, 16 B, Poisson); 0 skips")
+    ap.add_argument("--serving-load", type=float, default=0.7,
+                    help="offered load as a fraction of the sequential server's capacity")
     return ap.parse_args()
 
 
@@ -69,6 +76,118 @@ def traffic_from_profile(kind, config_tag):
     if not m_src or not m_b or m_src.group(1) != kernel_source_digest():
         return None
     return float(m_b.group(1))
+
+
+def bench_batched(args, torch, bos, inputs):
+    """4096 independent sorts of log-uniform sizes in one bos_sort_batched call
+    (graph replay) against the same instances sorted one call each."""
+    import numpy as np
+
+    dev = torch.device("cuda", 0)
+    sizes = inputs.batched_sizes(args.batched_count, 10, 20, 1 << 28, seed=4242)
+    total = int(sizes.sum())
+    master = bos.from_numpy(inputs.records(total, 16, args.data_seed + 1), dev)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    ins = [master[int(o):int(o) + int(n)] for o, n in zip(offs, sizes)]
+    outm = torch.empty_like(master)
+    outs = [outm[int(o):int(o) + int(n)] for o, n in zip(offs, sizes)]
+    seeds = list(range(len(ins)))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - t0) * 1e3 / reps
+
+    batched_ms, batched_wall = timed(lambda: bos.sort_batched(ins, seeds, outs=outs), args.batched_steps)
+    sorted_ok = True
+    chk = bos.to_numpy(outm)
+    for o, n in zip(offs, sizes):
+        seg = chk[int(o):int(o) + int(n)]
+        if n > 1:
+            k = seg[:, 0]
+            p = seg[:, 1]
+            if not bool(np.all((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (p[1:] >= p[:-1])))):
+                sorted_ok = False
+                break
+    del chk
+
+    def plain(sync):
+        for t, o, sd in zip(ins, outs, seeds):
+            bos.sort(t, seed=sd, out=o, sync=sync)
+
+    _, sync_wall = timed(lambda: plain(True), 1)
+    _, async_wall = timed(lambda: plain(False), 1)
+    res = {"instances": len(ins), "total_records": total, "rec_bytes": 16,
+           "sizes": "log-uniform 2^10..2^20, rescaled to total <= 2^28",
+           "batched_ms": round(batched_wall, 3), "batched_gpu_ms": round(batched_ms, 3),
+           "batched_Melem/s": round(total / batched_wall / 1e3, 1),
+           "plain_sync_ms": round(sync_wall, 3), "plain_async_ms": round(async_wall, 3),
+           "speedup_vs_plain_sync": round(sync_wall / batched_wall, 2),
+           "speedup_vs_plain_async": round(async_wall / batched_wall, 2), "correct": sorted_ok}
+    del ins, outs, master, outm
+    bos.release_workspaces()
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serving(args, torch, bos, inputs):
+    """Poisson arrivals of sort requests (log-uniform 2^12..2^24 records of
+    16 B) served by the continuous-batching server and by a first-come
+    first-served loop of single sorts, at the same offered load."""
+    import numpy as np
+
+    from paper_2008_01765_amd import serving
+
+    dev = torch.device("cuda", 0)
+    sizes = inputs.request_sizes(args.serving_requests, 12, 24, seed=7)
+    master_n = 1 << 25
+    master = bos.from_numpy(inputs.records(master_n, 16, args.data_seed + 2), dev)
+    starts = (inputs.splitmix64(99, 0, len(sizes)) % np.uint64(master_n - (1 << 24) + 1)).astype(np.int64)
+    reqs = [master[int(s0):int(s0) + int(n)] for s0, n in zip(starts, sizes)]
+    # service time of each request alone (warm), to set the arrival rate
+    big = int(np.argmax(sizes))
+    bos.sort(reqs[big], seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        bos.sort(r, seed=i)
+    torch.cuda.synchronize()
+    busy = time.perf_counter() - t0
+    rate = args.serving_load * len(reqs) / busy
+    arr = serving.poisson_arrivals(len(reqs), rate, seed=11)
+    srv = serving.Server(hbm_budget_bytes=64 << 30)
+    w = srv.submit(reqs[big], seed=0)  # warm the server's allocations
+    srv.run_until_idle()
+    srv = serving.Server(hbm_budget_bytes=64 << 30)
+    futs = serving.run_trace(srv, reqs, arr)
+    lat_b = [f.latency for f in futs]
+    span_b = max(f.finished for f in futs) - min(f.arrival for f in futs)
+    ok = all(f.status == bos.OK for f in futs) and w.status == bos.OK
+    lat_s, _ = serving.run_trace_sequential(reqs, arr)
+    span_s = max(a + l for a, l in zip(arr, lat_s))
+    total = int(sizes.sum())
+    res = {"requests": len(reqs), "rec_bytes": 16, "sizes": "log-uniform 2^12..2^24",
+           "arrivals": "Poisson, %.1f req/s (%.0f%% of the sequential capacity)" % (rate, 100 * args.serving_load),
+           "hbm_budget_GiB": 64, "steps": srv.steps, "peak_resident_GiB": round(srv.peak_used / 2 ** 30, 2),
+           "batching": {"p50_ms": round(serving.percentile(lat_b, 50) * 1e3, 3),
+                        "p99_ms": round(serving.percentile(lat_b, 99) * 1e3, 3),
+                        "Melem/s": round(total / span_b / 1e6, 1)},
+           "sequential": {"p50_ms": round(serving.percentile(lat_s, 50) * 1e3, 3),
+                          "p99_ms": round(serving.percentile(lat_s, 99) * 1e3, 3),
+                          "Melem/s": round(total / span_s / 1e6, 1)},
+           "correct": ok}
+    del reqs, master, futs, srv
+    bos.release_workspaces()
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -211,6 +330,15 @@ def main():
                                                                   "sec_sort")},
                "host": os.uname().nodename, "nproc": os.cpu_count()}
 
+    batched = None
+    if args.batched_count > 0 and args.mode == "sort":
+        batched = bench_batched(args, torch, bos, inputs)
+        print("batched: %s" % json.dumps(batched), file=sys.stderr, flush=True)
+    served = None
+    if args.serving_requests > 0 and args.mode == "sort":
+        served = bench_serving(args, torch, bos, inputs)
+        print("serving: %s" % json.dumps(served), file=sys.stderr, flush=True)
+
     rep = reps[-1]
     value = n / ms_per_step / 1e3  # Melem/s
     line = {
@@ -224,11 +352,12 @@ def main():
                    "n": n, "rec_bytes": args.rec, "z": rep["z"], "k": rep["k"], "levels": rep["levels"],
                    "passes": rep["passes"], "tile": rep["tile"], "parallelism": "1 GPU"},
         "attempts": rep["attempts"], "correct": ok,
-        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "kernels": kern,
+        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "batched": batched, "serving": served,
+        "kernels": kern,
         "kernel_sources": kernel_source_digest(),
     }
     print(json.dumps(line), flush=True)
-    if not ok:
+    if not ok or (batched and not batched["correct"]) or (served and not served["correct"]):
         sys.exit(1)
 
 

@@ -124,6 +124,49 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
                             const bos_params* p, void* ws, size_t ws_bytes, void* stream,
                             uint32_t* d_status, bos_report* rep);
 
+/* ---- continuous batching ------------------------------------------------ */
+
+#define BOS_PHASE_DONE 0xFFFFFFFFu
+
+/* One sort request driven by bos_sort_step. */
+typedef struct {
+  const void* in;     /* device, n records */
+  void* out;          /* device, n records */
+  uint64_t n;
+  uint64_t seed;
+  void* ws;           /* device workspace of this job: bos_workspace_bytes(n) bytes */
+  size_t ws_bytes;
+  uint32_t phase;     /* in/out: 0 for a new job, BOS_PHASE_DONE once finished */
+  uint32_t attempt;   /* in/out: routing attempt, 0 for a new job */
+  uint32_t status;    /* out: BOS_OK, or BOS_ERR_OVERFLOW once every attempt overflowed */
+  uint32_t reserved;
+} bos_job;
+
+/* Device bytes of the step tables bos_sort_step needs for `count` jobs. */
+size_t bos_step_workspace_bytes(uint32_t count);
+
+/* Continuous batching of bucket oblivious sorts (Section 3.3): run one step
+ * of every unfinished job and return.  A job's phases are its routing passes
+ * (Algorithm 3.1; the last pass also sorts each bin and strips the dummies),
+ * the tile sort and the merge passes of the comparison sort: phase values
+ * 0..P-1, P, P+1.. (P = routing passes of the job's plan).  Array order is
+ * priority: a step runs at least one phase of the first unfinished job and
+ * hands a work budget of about twice that phase to the jobs after it, in
+ * order, each running as many phases as fit (possibly none); jobs in the same
+ * phase kind share launches, so requests admitted between steps run alongside
+ * those already on the device.  The overflow check (Algorithm 3.1's abort) happens at the
+ * end of the step in which a job's routing finished: an overflowed job goes
+ * back to phase 0 with attempt + 1, or ends with BOS_ERR_OVERFLOW once
+ * max_retries is used up.  Each finished job's output equals bos_sort's for
+ * the same input, parameters and seed, and so does its attempt count.
+ * jobs: host array, updated in place (phase, attempt, status).
+ * step_ws: device, bos_step_workspace_bytes(count) bytes.  Synchronizes
+ * `stream` before returning.  Errors: INVALID_ARG (aliasing in/out, a phase
+ * beyond the job's last), WORKSPACE (a job's ws or step_ws too small),
+ * INSECURE_Z, HIP. */
+bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p, void* step_ws,
+                         size_t step_ws_bytes, void* stream);
+
 /* Oblivious bitonic sort (Batcher) of the same records by (key, payload): the
  * GPU baseline the bucket sort is measured against.  ws: bos_bitonic_workspace_bytes. */
 size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec);

@@ -47,6 +47,15 @@ class Instance(C.Structure):
     _fields_ = [("in_", C.c_void_p), ("out", C.c_void_p), ("n", C.c_uint64), ("seed", C.c_uint64)]
 
 
+class Job(C.Structure):
+    _fields_ = [("in_", C.c_void_p), ("out", C.c_void_p), ("n", C.c_uint64), ("seed", C.c_uint64),
+                ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("phase", C.c_uint32), ("attempt", C.c_uint32),
+                ("status", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+PHASE_DONE = 0xFFFFFFFF
+
+
 class LaunchTime(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("index", C.c_uint32), ("ms", C.c_float), ("reserved", C.c_uint32),
                 ("bytes", C.c_uint64)]
@@ -58,7 +67,7 @@ KERNEL_KINDS = {1: "route_first", 2: "route_mid", 3: "route_last", 4: "route_sin
 EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "bos_batched_workspace_bytes",
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
-           "bos_profile_read"]
+           "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step"]
 
 _lib = None
 
@@ -83,6 +92,10 @@ def lib():
         L.bos_batched_workspace_bytes.restype = C.c_size_t
         L.bos_sort_batched.argtypes = [C.POINTER(Instance), u32, C.c_int, P, vp, C.c_size_t, vp, vp, R]
         L.bos_sort_batched.restype = C.c_int
+        L.bos_step_workspace_bytes.argtypes = [u32]
+        L.bos_step_workspace_bytes.restype = C.c_size_t
+        L.bos_sort_step.argtypes = [C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
+        L.bos_sort_step.restype = C.c_int
         L.bos_bitonic_workspace_bytes.argtypes = [u64, C.c_int]
         L.bos_bitonic_workspace_bytes.restype = C.c_size_t
         L.bos_bitonic_sort.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
@@ -185,9 +198,11 @@ def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stre
 
 
 def sort(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
-         report=False, generic=False):
-    """Bucket oblivious sort of the records in t (Section 3.3)."""
-    p = params(seed, z, k, tile, max_retries, min_security_bits, generic=generic)
+         report=False, generic=False, sync=True):
+    """Bucket oblivious sort of the records in t (Section 3.3).  With
+    sync=False the call does not wait for the overflow check (one attempt,
+    stream-ordered); the report then cannot tell an overflow."""
+    p = params(seed, z, k, tile, max_retries, min_security_bits, sync=sync, generic=generic)
     o, rep = _run(lib().bos_sort, t, p, out, stream)
     return (o, rep) if report else o
 
@@ -221,6 +236,19 @@ def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_b
                                 _stream(stream), C.c_void_p(dstat.data_ptr()), C.byref(rep))
     _check(st)
     return (outs, rep.as_dict()) if report else outs
+
+
+def sort_step(jobs, rec, p, step_ws, stream=None):
+    """Advance every unfinished Job in the ctypes array `jobs` by one phase
+    (bos_sort_step); returns the number of jobs still unfinished."""
+    count = len(jobs)
+    _check(lib().bos_sort_step(jobs, count, rec, C.byref(p), C.c_void_p(step_ws.data_ptr()), step_ws.numel(),
+                               _stream(stream)))
+    return sum(1 for j in jobs if j.phase != PHASE_DONE)
+
+
+def step_workspace_bytes(count):
+    return lib().bos_step_workspace_bytes(count)
 
 
 def bitonic_sort(t, out=None, stream=None):

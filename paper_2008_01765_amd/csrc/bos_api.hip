@@ -859,6 +859,268 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
   return worst;
 }
 
+
+// ---- continuous batching --------------------------------------------------
+//
+// A step is a budget of device work, handed out in array order (the caller
+// puts its oldest job first).  The first unfinished job always runs at least
+// one phase (several if they are cheap: up to kStepMinQuantum); later jobs
+// backfill the rest of a budget of twice that, each as many phases as fit,
+// so small requests run several phases next to one phase of a large request
+// and large requests keep their order.  The phase cost model is
+// n + kStepFixed records (kStepFixed stands for the launch overhead of a
+// phase).  The overflow check of an attempt is
+// speculative: a job that finished its routing passes goes on to the
+// comparison sort in the same step, and the status words of those jobs are
+// read once at the end of the step; a job whose attempt overflowed goes back
+// to pass 0 with the next attempt, and whatever it wrote is redone.
+
+constexpr uint32_t kStepRounds = 32;           // sub-rounds per step at most
+constexpr uint64_t kStepFixed = 1ull << 17;    // launch overhead, in records
+constexpr uint64_t kStepMinQuantum = 1ull << 21;
+
+size_t step_round_bytes(uint32_t count) {
+  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + 2 * sizeof(SortSeg)) + 12 * kAlign;
+}
+
+size_t bos_step_workspace_bytes(uint32_t count) {
+  return align_up(kStepRounds * step_round_bytes(count) + size_t(count) * 12 + 4 * kAlign);
+}
+
+bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p, void* step_ws,
+                         size_t step_ws_bytes, void* stream) {
+  if (!has_gpu()) return BOS_ERR_UNSUPPORTED;
+  if (count && !jobs) return BOS_ERR_INVALID_ARG;
+  const bos_params q = resolve(p);
+  const int R = int(rec);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (count == 0) return BOS_OK;
+  if (!step_ws || step_ws_bytes < bos_step_workspace_bytes(count)) return BOS_ERR_WORKSPACE;
+  const bool batched_z = !(q.flags & BOS_GENERIC_ROUTING) && (q.z == 32 || q.z == 256 || q.z == 512 || q.z == 1024);
+  std::vector<Plan> plans(count);
+  std::vector<uint32_t> merges(count, 0), allowed(count, 0);
+  std::vector<char> routed(count, 0);  // finished an attempt's routing in this step
+  uint64_t quantum = kStepMinQuantum;
+  for (uint32_t i = 0; i < count; ++i) {
+    bos_job& j = jobs[i];
+    if (j.phase == BOS_PHASE_DONE) continue;
+    if (j.n == 0) {
+      j.phase = BOS_PHASE_DONE;
+      j.status = BOS_OK;
+      continue;
+    }
+    if (!j.in || !j.out || j.in == j.out) return BOS_ERR_INVALID_ARG;
+    const bos_status st = make_plan(j.n, R, q, true, &plans[i]);
+    if (st != BOS_OK) return st;
+    if (!j.ws || j.ws_bytes < plans[i].total) return BOS_ERR_WORKSPACE;
+    merges[i] = comparison_sort_passes(j.n, plans[i].tile);
+    if (j.phase > plans[i].P + merges[i]) return BOS_ERR_INVALID_ARG;
+  }
+  {
+    bool head = true;
+    uint64_t left = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+      const bos_job& j = jobs[i];
+      if (j.phase == BOS_PHASE_DONE) continue;
+      const uint64_t c = j.n + kStepFixed;
+      const uint64_t remaining = uint64_t(plans[i].P) + 1 + merges[i] - j.phase;
+      uint64_t k;
+      if (head) {
+        quantum = std::max(quantum, c);
+        k = std::max<uint64_t>(1, kStepMinQuantum / c);
+        left = 2 * quantum;
+        head = false;
+      } else {
+        k = left / c;
+      }
+      k = std::min<uint64_t>({k, remaining, kStepRounds});
+      allowed[i] = uint32_t(k);
+      left -= std::min(left, k * c);
+    }
+  }
+  auto tmp_buf = [&](uint32_t i) -> void* {
+    return static_cast<char*>(jobs[i].ws) + plans[i].off_rec[(plans[i].P + 1) & 1];
+  };
+  auto start_buf = [&](uint32_t i) -> void* { return (merges[i] % 2 == 0) ? jobs[i].out : tmp_buf(i); };
+  auto other_buf = [&](uint32_t i) -> void* { return (merges[i] % 2 == 0) ? tmp_buf(i) : jobs[i].out; };
+
+  // Build every sub-round's tables on the host, then upload them at once.
+  struct Round {
+    size_t o_fill = 0, o_route[4] = {0, 0, 0, 0}, o_start[4] = {0, 0, 0, 0}, o_tile = 0, o_merge = 0;
+    uint32_t nfill = 0, nroute[4] = {0, 0, 0, 0}, ntile = 0, nmerge = 0;
+    uint32_t rblocks[4] = {0, 0, 0, 0}, rthreads[4] = {64, 64, 64, 64}, rlds[4] = {0, 0, 0, 0}, rlz[4] = {0, 0, 0, 0};
+    uint32_t tiles = 0, mtiles = 0;
+    PassArgs single[4];
+    uint32_t single_items[4] = {0, 0, 0, 0};
+    std::vector<uint32_t> whole;  // jobs routed by the per-job path in this round
+  };
+  std::vector<Round> rounds;
+  std::vector<char> tab;
+  std::vector<uint32_t> phase(count);
+  for (uint32_t i = 0; i < count; ++i) phase[i] = jobs[i].phase;
+  const uint64_t T = kDefaultTile;
+  for (uint32_t r = 0; r < kStepRounds; ++r) {
+    Round rd;
+    std::vector<FillSeg> fills;
+    std::vector<PassArgs> route[4];
+    std::vector<uint32_t> starts[4];
+    std::vector<SortSeg> tiles, mseg;
+    bool any = false;
+    for (uint32_t i = 0; i < count; ++i) {
+      if (phase[i] == BOS_PHASE_DONE || allowed[i] <= r) continue;
+      bos_job& j = jobs[i];
+      const Plan& pl = plans[i];
+      char* w = static_cast<char*>(j.ws);
+      any = true;
+      const uint32_t ph = phase[i];
+      if (ph < pl.P) {
+        if (pl.L == 0 || !batched_z || !use_route_kernel(pl, ph)) {
+          if (ph != 0) return BOS_ERR_INVALID_ARG;  // per-job routing runs a whole attempt at once
+          rd.whole.push_back(i);
+          phase[i] = pl.P;
+          routed[i] = 1;
+          continue;
+        }
+        unsigned long long* status = reinterpret_cast<unsigned long long*>(w + pl.off_status);
+        if (ph == 0) fills.push_back(FillSeg{status, 2 + pl.nblocks_last, 0});
+        const bool first = ph == 0, last = ph + 1 == pl.P;
+        const int mode = (first ? 1 : 0) | (last ? 2 : 0);
+        PassArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.x_in = j.in;
+        a.out = start_buf(i);
+        a.rec_in = w + pl.off_rec[(ph + 1) & 1];
+        a.tag_in = reinterpret_cast<const uint32_t*>(w + pl.off_tag[(ph + 1) & 1]);
+        a.rec_out = w + pl.off_rec[ph & 1];
+        a.tag_out = reinterpret_cast<uint32_t*>(w + pl.off_tag[ph & 1]);
+        a.status = status;
+        a.ticket = reinterpret_cast<uint32_t*>(status + 1);
+        a.scan = status + 2;
+        a.n = pl.n;
+        a.buckets = pl.B;
+        a.seed = j.seed;
+        a.z = pl.Z;
+        a.lz = pl.lz;
+        a.levels = pl.L;
+        a.level0 = pl.lev0[ph];
+        a.klev = pl.klev[ph];
+        a.attempt = j.attempt;
+        a.fin = 1;
+        const uint32_t items = uint32_t(pl.B >> pl.klev[ph]);
+        rd.single[mode] = a;
+        rd.single_items[mode] = items;
+        route[mode].push_back(a);
+        starts[mode].push_back(rd.rblocks[mode]);
+        rd.rblocks[mode] += items;
+        rd.rthreads[mode] = std::max(rd.rthreads[mode], uint32_t((pl.Z << pl.klev[ph]) >> 4));
+        rd.rlds[mode] = std::max(rd.rlds[mode], pass_lds_bytes(R, pl.Z, pl.klev[ph], false));
+        rd.rlz[mode] = pl.lz;
+        if (last) {
+          phase[i] = pl.P;  // on to the tile sort; the check is at the end of the step
+          routed[i] = 1;
+        } else {
+          ++phase[i];
+        }
+      } else if (ph == pl.P) {
+        const uint32_t c = uint32_t((j.n + T - 1) / T);
+        if (j.n > 1) tiles.push_back(SortSeg{start_buf(i), nullptr, j.n, 0, nullptr, rd.tiles, c});
+        if (j.n > 1) rd.tiles += c;
+        phase[i] = merges[i] == 0 ? BOS_PHASE_DONE : pl.P + 1;
+      } else {
+        const uint32_t pass = ph - (pl.P + 1);
+        const uint32_t c = uint32_t((j.n + T - 1) / T);
+        void* src = (pass % 2 == 0) ? start_buf(i) : other_buf(i);
+        void* dst = (pass % 2 == 0) ? other_buf(i) : start_buf(i);
+        mseg.push_back(SortSeg{src, dst, j.n, T << pass, reinterpret_cast<uint64_t*>(w + pl.off_split), rd.mtiles, c});
+        rd.mtiles += c;
+        phase[i] = pass + 1 >= merges[i] ? BOS_PHASE_DONE : ph + 1;
+      }
+    }
+    if (!any) break;
+    rd.nfill = uint32_t(fills.size());
+    rd.o_fill = push_table(tab, fills);
+    for (int m = 0; m < 4; ++m) {
+      rd.nroute[m] = uint32_t(route[m].size());
+      rd.o_route[m] = push_table(tab, route[m]);
+      rd.o_start[m] = push_table(tab, starts[m]);
+    }
+    rd.ntile = uint32_t(tiles.size());
+    rd.o_tile = push_table(tab, tiles);
+    rd.nmerge = uint32_t(mseg.size());
+    rd.o_merge = push_table(tab, mseg);
+    rounds.push_back(std::move(rd));
+  }
+  // status pointers of the jobs whose routing finished in this step
+  std::vector<unsigned long long*> st_ptr;
+  std::vector<uint32_t> st_job;
+  for (uint32_t i = 0; i < count; ++i)
+    if (routed[i]) {
+      st_ptr.push_back(reinterpret_cast<unsigned long long*>(static_cast<char*>(jobs[i].ws) + plans[i].off_status));
+      st_job.push_back(i);
+    }
+  const size_t o_stp = push_table(tab, st_ptr);
+  const size_t o_sto = align_up(tab.size());
+  if (o_sto + align_up(st_ptr.size() * 4) > step_ws_bytes) return BOS_ERR_WORKSPACE;
+  char* dtab = static_cast<char*>(step_ws);
+  if (!tab.empty() && hipMemcpyAsync(dtab, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return BOS_ERR_HIP;
+  hipError_t e = hipSuccess;
+  for (const Round& rd : rounds) {
+    if (e == hipSuccess && rd.nfill)
+      e = launch_fill_status_batched(reinterpret_cast<const FillSeg*>(dtab + rd.o_fill), rd.nfill, s);
+    for (uint32_t i : rd.whole) {
+      if (e != hipSuccess) break;
+      e = enqueue_routing(plans[i], jobs[i].in, start_buf(i), jobs[i].seed, jobs[i].attempt, 1,
+                          static_cast<char*>(jobs[i].ws), s);
+    }
+    for (int m : {3, 1, 0, 2}) {
+      if (e != hipSuccess || rd.nroute[m] == 0) continue;
+      if (rd.nroute[m] == 1)  // one job: the persistent kernel of the single-sort path
+        e = launch_route(R, rd.single[m], (m & 1) != 0, (m & 2) != 0, rd.single_items[m], num_cus(), s);
+      else
+        e = launch_route_batched(R, rd.rlz[m], (m & 1) != 0, (m & 2) != 0,
+                                 reinterpret_cast<const PassArgs*>(dtab + rd.o_route[m]),
+                                 reinterpret_cast<const uint32_t*>(dtab + rd.o_start[m]), rd.nroute[m], rd.rblocks[m],
+                                 rd.rthreads[m], rd.rlds[m], s);
+    }
+    if (e == hipSuccess && rd.ntile)
+      e = launch_sort_batched(R, 0, reinterpret_cast<const SortSeg*>(dtab + rd.o_tile), rd.ntile, rd.tiles, s);
+    if (e == hipSuccess && rd.nmerge) {
+      e = launch_sort_batched(R, 1, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
+      if (e == hipSuccess)
+        e = launch_sort_batched(R, 2, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
+    }
+  }
+  std::vector<uint32_t> st_host(st_ptr.size(), 0);
+  if (e == hipSuccess && !st_ptr.empty()) {
+    uint32_t* d_out = reinterpret_cast<uint32_t*>(dtab + o_sto);
+    e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(dtab + o_stp), d_out,
+                            uint32_t(st_ptr.size()), s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(st_host.data(), d_out, st_host.size() * 4, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return BOS_ERR_HIP;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (jobs[i].phase == BOS_PHASE_DONE) continue;
+    jobs[i].phase = phase[i];
+    if (phase[i] == BOS_PHASE_DONE) jobs[i].status = BOS_OK;
+  }
+  for (size_t t = 0; t < st_job.size(); ++t) {
+    if (st_host[t] == 0) continue;
+    bos_job& j = jobs[st_job[t]];
+    if (j.attempt < q.max_retries) {
+      ++j.attempt;
+      j.phase = 0;
+      j.status = BOS_OK;
+    } else {
+      j.phase = BOS_PHASE_DONE;
+      j.status = BOS_ERR_OVERFLOW;
+    }
+  }
+  return BOS_OK;
+}
+
 size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec) {
   if (rec != 8 && rec != 16) return 0;
   uint64_t N = kBitonicTile;

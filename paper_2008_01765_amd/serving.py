@@ -1,0 +1,254 @@
+"""Serving loop for bucket oblivious sort requests on one GPU.
+
+Requests (record tensors already in HBM) queue up in arrival order.  Between
+scheduler steps the server admits queued requests while their HBM footprint
+(input + output + the sort's workspace) fits under the budget; each step then
+advances every resident request by one phase of its sort (a routing pass of the
+butterfly network of Section 3.2, the overflow check, the tile sort or a merge
+pass of the comparison sort that Section 3.3 applies to the permuted array)
+through one bos_sort_step call.  Requests of different sizes and phases share
+the step's launches, and new requests start at the next step boundary
+(continuous batching).  A finished request frees its memory and records its
+completion time.
+
+Every result is the one bos.sort gives for the same input alone: the sort's
+output is the sorted array whatever the seed, and each request keeps its own
+seed and attempt counter through the steps.
+"""
+import time
+from collections import deque
+
+import torch
+
+from . import bos
+
+
+def admit_prefix(footprints, free_bytes):
+    """How many of the queued requests, taken in order, fit in free_bytes.
+
+    Admission is first-come first-served: it stops at the first request that
+    does not fit, so a large request is not starved by smaller ones behind it.
+    """
+    k = 0
+    for f in footprints:
+        if f > free_bytes:
+            break
+        free_bytes -= f
+        k += 1
+    return k
+
+
+def percentile(values, q):
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence."""
+    v = sorted(values)
+    if not v:
+        raise ValueError("percentile of an empty sequence")
+    rank = max(1, -(-len(v) * q // 100))
+    return v[int(rank) - 1]
+
+
+class Future:
+    """Handle of one submitted request."""
+
+    def __init__(self, server, rid, tensor, seed, arrival):
+        self._server = server
+        self.id = rid
+        self.input = tensor
+        self.n = tensor.shape[0]
+        self.seed = seed
+        self.arrival = arrival
+        self.admitted = None
+        self.finished = None
+        self.status = None
+        self.out = None
+        self.attempts = 0
+        self.steps = 0
+        self.footprint = 0
+        self.phase = 0
+        self._ws = None
+
+    def done(self):
+        return self.finished is not None
+
+    def result(self):
+        """Block (driving the server) until this request is done; returns its
+        sorted tensor or raises BosError if every routing attempt overflowed."""
+        while not self.done():
+            self._server.step()
+        if self.status != bos.OK:
+            raise bos.BosError(self.status, "libbos: " + bos.lib().bos_status_string(self.status).decode())
+        return self.out
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+class Server:
+    """Continuous-batching server of bucket oblivious sorts on one device.
+
+    hbm_budget_bytes bounds the sum of the resident requests' footprints;
+    z, k, max_retries and min_security_bits are shared by every request (the
+    step entry point takes one parameter block).  All requests must use the
+    same record type.
+    """
+
+    def __init__(self, hbm_budget_bytes=64 << 30, z=0, k=0, max_retries=3, min_security_bits=80,
+                 device=None, stream=None, clock=time.perf_counter):
+        self.budget = int(hbm_budget_bytes)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream
+        self.clock = clock
+        self.params = bos.params(0, z, k, 0, max_retries, min_security_bits, sync=True)
+        self.rec = None
+        self.queue = deque()
+        self.active = []
+        self.used = 0
+        self.peak_used = 0
+        self.steps = 0
+        self._next_id = 0
+        self._step_ws = None
+        self.completed = []
+
+    # ---- admission ---------------------------------------------------------
+    def footprint(self, n, rec):
+        return 2 * n * rec + bos.workspace_bytes(n, rec, self.params) if n else 0
+
+    def submit(self, tensor, seed=None, arrival=None):
+        """Queue one request (an (n, 2) record tensor on the server's device)."""
+        rec = bos.rec_bytes(tensor)
+        if self.rec is None:
+            self.rec = rec
+        elif rec != self.rec:
+            raise ValueError("all requests of a server must use the same record type")
+        if tensor.device != self.device:
+            raise ValueError("request tensor is on %s, server on %s" % (tensor.device, self.device))
+        rid = self._next_id
+        self._next_id += 1
+        f = Future(self, rid, tensor, rid if seed is None else seed, self.clock() if arrival is None else arrival)
+        if f.n:
+            bos.plan(f.n, rec, self.params.z, self.params.k, 0, self.params.min_security_bits)  # raises if Z is rejected
+        f.footprint = self.footprint(f.n, rec)
+        if f.footprint > self.budget:
+            raise bos.BosError(bos.WORKSPACE, "request of %d records needs %d bytes, over the %d-byte budget"
+                               % (f.n, f.footprint, self.budget))
+        self.queue.append(f)
+        return f
+
+    def _admit(self):
+        k = admit_prefix([f.footprint for f in self.queue], self.budget - self.used)
+        now = self.clock()
+        for _ in range(k):
+            f = self.queue.popleft()
+            f.admitted = now
+            f.out = torch.empty_like(f.input)
+            if f.n:
+                f._ws = torch.empty(max(bos.workspace_bytes(f.n, self.rec, self.params), 256), dtype=torch.uint8,
+                                    device=self.device)
+            self.used += f.footprint
+            self.active.append(f)
+        self.peak_used = max(self.peak_used, self.used)
+        return k
+
+    # ---- scheduling --------------------------------------------------------
+    def idle(self):
+        return not self.queue and not self.active
+
+    def step(self):
+        """Admit what fits, advance every resident request by one phase and
+        retire the finished ones; returns the requests finished in this step."""
+        self._admit()
+        if not self.active:
+            return []
+        cnt = len(self.active)
+        jobs = (bos.Job * cnt)()
+        for i, f in enumerate(self.active):
+            j = jobs[i]
+            j.in_ = f.input.data_ptr()
+            j.out = f.out.data_ptr()
+            j.n = f.n
+            j.seed = f.seed & 0xFFFFFFFFFFFFFFFF
+            j.ws = f._ws.data_ptr() if f._ws is not None else None
+            j.ws_bytes = f._ws.numel() if f._ws is not None else 0
+            j.phase = f.phase
+            j.attempt = f.attempts
+            j.status = 0
+        need = bos.step_workspace_bytes(cnt)
+        if self._step_ws is None or self._step_ws.numel() < need:
+            self._step_ws = torch.empty(2 * need, dtype=torch.uint8, device=self.device)
+        bos.sort_step(jobs, self.rec, self.params, self._step_ws, self.stream)
+        self.steps += 1
+        now = self.clock()
+        done, keep = [], []
+        for i, f in enumerate(self.active):
+            f.phase = jobs[i].phase
+            f.attempts = jobs[i].attempt
+            f.steps += 1
+            if jobs[i].phase == bos.PHASE_DONE:
+                f.finished = now
+                f.status = jobs[i].status
+                f._ws = None
+                self.used -= f.footprint
+                done.append(f)
+            else:
+                keep.append(f)
+        self.active = keep
+        self.completed.extend(done)
+        return done
+
+    def run_until_idle(self):
+        while not self.idle():
+            self.step()
+
+
+def run_trace(server, tensors, arrivals, seeds=None, spin=True):
+    """Replay an arrival trace (seconds from now, ascending) through `server`;
+    returns the futures in submission order."""
+    clock = server.clock
+    t0 = clock()
+    futs = []
+    i = 0
+    N = len(tensors)
+    while i < N or not server.idle():
+        now = clock() - t0
+        while i < N and arrivals[i] <= now:
+            futs.append(server.submit(tensors[i], seed=None if seeds is None else seeds[i], arrival=t0 + arrivals[i]))
+            i += 1
+        if server.idle():
+            if i < N and spin:
+                while clock() - t0 < arrivals[i]:
+                    pass
+            continue
+        server.step()
+    return futs
+
+
+def run_trace_sequential(tensors, arrivals, z=0, k=0, seeds=None, clock=time.perf_counter, stream=None):
+    """First-come first-served baseline: each request sorted alone by bos.sort
+    once it has arrived and the previous one has finished.  Returns
+    (latencies, outputs)."""
+    t0 = clock()
+    lat, outs = [], []
+    for i, t in enumerate(tensors):
+        while clock() - t0 < arrivals[i]:
+            pass
+        o = bos.sort(t, seed=i if seeds is None else seeds[i], z=z, k=k, stream=stream)
+        torch.cuda.synchronize()
+        lat.append(clock() - t0 - arrivals[i])
+        outs.append(o)
+    return lat, outs
+
+
+def poisson_arrivals(count, rate_per_s, seed=11):
+    """Arrival times of a Poisson process (exponential gaps from splitmix64)."""
+    import numpy as np
+
+    from . import inputs
+
+    u = (inputs.splitmix64(seed, 0, count) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    gaps = -np.log1p(-u) / rate_per_s
+    return np.cumsum(gaps).tolist()
+
+
+__all__ = ["Server", "Future", "admit_prefix", "percentile", "run_trace", "run_trace_sequential",
+           "poisson_arrivals"]

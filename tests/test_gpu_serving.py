@@ -1,0 +1,132 @@
+"""Continuous batching (bos_sort_step) and the serving loop on the GPU.
+
+Every request served in a mix must come out byte-identical to the same request
+sorted alone (bos_sort) and to the oracle's sort, with the same number of
+routing attempts; admission must keep the resident footprint under the budget.
+"""
+import numpy as np
+import pytest
+
+import closed_forms as cf
+from paper_2008_01765_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2008_01765_amd import bos, serving  # noqa: E402
+
+
+def _hosts(sizes, rec, data_seed):
+    return [inputs.records(int(n), rec, data_seed + i, key_bits=(20 if rec == 16 else None))
+            for i, n in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("rec,z", [(16, 512), (8, 512), (16, 256)])
+def test_mix_equals_alone(rec, z):
+    sizes = [4096, 1 << 16, 0, 1, 5000, 70000, 1 << 12, 333, 1 << 18, 9999]
+    hosts = _hosts(sizes, rec, 300)
+    srv = serving.Server(hbm_budget_bytes=1 << 34, z=z, min_security_bits=0)
+    futs = []
+    ts = [bos.from_numpy(h) for h in hosts]
+    # requests join while others are mid-flight
+    for i, t in enumerate(ts):
+        futs.append(srv.submit(t, seed=50 + i))
+        if i % 3 == 2:
+            srv.step()
+    srv.run_until_idle()
+    for h, t, f in zip(hosts, ts, futs):
+        got = bos.to_numpy(f.result())
+        np.testing.assert_array_equal(got, cf.sorted_records(h))
+        if len(h):
+            alone, rep = bos.sort(t, seed=f.seed, z=z, min_security_bits=0, report=True)
+            np.testing.assert_array_equal(got, bos.to_numpy(alone))
+            assert f.attempts + 1 == rep["attempts"]
+    assert srv.used == 0
+
+
+def test_budget_bounds_resident_footprint():
+    sizes = [1 << 16] * 6 + [1 << 14] * 4
+    hosts = _hosts(sizes, 16, 900)
+    probe = serving.Server(hbm_budget_bytes=1 << 40, min_security_bits=0)
+    one = probe.footprint(1 << 16, 16)
+    srv = serving.Server(hbm_budget_bytes=2 * one + one // 2, min_security_bits=0)
+    futs = [srv.submit(bos.from_numpy(h), seed=i) for i, h in enumerate(hosts)]
+    while not srv.idle():
+        srv.step()
+        assert srv.used <= srv.budget
+        assert sum(f.footprint for f in srv.active) == srv.used
+    assert srv.peak_used <= srv.budget
+    assert len(srv.completed) == len(futs)
+    # first come, first served: admission times follow submission order
+    adm = [f.admitted for f in futs]
+    assert adm == sorted(adm)
+    for h, f in zip(hosts, futs):
+        np.testing.assert_array_equal(bos.to_numpy(f.out), cf.sorted_records(h))
+
+
+def test_overflow_retries_in_mix_match_alone():
+    # Z = 32 overflows often at these sizes; a job that overflows retries from
+    # pass 0 with the next attempt, as bos_sort does.  The oracle fixes the
+    # attempt count of every job.
+    import oracle
+    oracle.build(force=False)
+    sizes = [1 << 14, 9000, 1 << 13, 6000, 20000]
+    hosts = _hosts(sizes, 8, 5)
+    seeds = [11, 12, 13, 14, 15]
+    srv = serving.Server(hbm_budget_bytes=1 << 34, z=32, min_security_bits=0, max_retries=30)
+    futs = [srv.submit(bos.from_numpy(h), seed=s) for h, s in zip(hosts, seeds)]
+    srv.run_until_idle()
+    retried = 0
+    for h, f, s in zip(hosts, futs, seeds):
+        want = oracle.sort(h, s, z=32, max_retries=30)
+        assert want["rc"] == 0 and f.status == bos.OK
+        assert f.attempts + 1 == want["report"]["attempts"]
+        retried += f.attempts > 0
+        np.testing.assert_array_equal(bos.to_numpy(f.out), want["out"])
+    assert retried > 0
+
+
+def test_trace_replay_and_sequential_agree():
+    sizes = inputs.request_sizes(12, lo_log2=10, hi_log2=16, seed=3)
+    hosts = _hosts(sizes, 16, 77)
+    ts = [bos.from_numpy(h) for h in hosts]
+    arr = serving.poisson_arrivals(len(ts), rate_per_s=2000.0, seed=5)
+    srv = serving.Server(hbm_budget_bytes=1 << 34, min_security_bits=0)
+    futs = serving.run_trace(srv, ts, arr)
+    lat, outs = serving.run_trace_sequential(ts, arr)
+    assert len(lat) == len(futs) == len(ts)
+    for h, f, o in zip(hosts, futs, outs):
+        np.testing.assert_array_equal(bos.to_numpy(f.out), cf.sorted_records(h))
+        np.testing.assert_array_equal(bos.to_numpy(o), cf.sorted_records(h))
+        assert f.latency >= 0
+
+
+def test_step_rejects_small_workspace():
+    t = bos.from_numpy(inputs.records(5000, 16, 1))
+    out = torch.empty_like(t)
+    p = bos.params(0, 512, 0, 0, 3, 0)
+    ws = torch.empty(bos.workspace_bytes(5000, 16, p), dtype=torch.uint8, device="cuda")
+    jobs = (bos.Job * 1)()
+    jobs[0].in_, jobs[0].out, jobs[0].n, jobs[0].seed = t.data_ptr(), out.data_ptr(), 5000, 1
+    jobs[0].ws, jobs[0].ws_bytes = ws.data_ptr(), ws.numel() - 256
+    sws = torch.empty(bos.step_workspace_bytes(1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(bos.BosError) as e:
+        bos.sort_step(jobs, 16, p, sws)
+    assert e.value.status == bos.WORKSPACE
+    jobs[0].ws_bytes = ws.numel()
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bos.BosError) as e:
+        bos.sort_step(jobs, 16, p, small)
+    assert e.value.status == bos.WORKSPACE
+    while bos.sort_step(jobs, 16, p, sws):
+        pass
+    np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(bos.to_numpy(t)))
+
+
+def test_request_over_budget_rejected():
+    srv = serving.Server(hbm_budget_bytes=1 << 20, min_security_bits=0)
+    with pytest.raises(bos.BosError):
+        srv.submit(bos.from_numpy(inputs.records(1 << 16, 16, 1)))
