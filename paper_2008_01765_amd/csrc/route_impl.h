@@ -45,6 +45,22 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_barrier();
 }
 
+// Orders this wave's LDS writes before its later LDS reads.  Enough when the
+// lanes that exchange data through LDS all belong to one wave: LDS executes a
+// wave's instructions in order.
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// LDS exchange among `LANES` consecutive lanes (a power of two): a wave-local
+// wait when they fit in one wave, a workgroup barrier otherwise.
+template <uint32_t LANES>
+__device__ __forceinline__ void lds_group_sync() {
+  if constexpr (LANES <= 64u) lds_wave_sync();
+  else lds_barrier();
+}
+
 template <uint32_t CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {
   return uint32_t(__builtin_amdgcn_mov_dpp(int(v), CTRL, 0xF, 0xF, false));
@@ -70,19 +86,47 @@ __device__ __forceinline__ bool swap_bit(uint32_t P0, uint32_t Ph, uint32_t half
   return s != (i >= t);
 }
 
+// DPP source with lanes outside the pattern (or rows outside ROW_MASK)
+// reading 0.
+template <uint32_t CTRL, uint32_t ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Inclusive scan over aligned groups of W lanes (W a power of two <= 64):
+// row_shr steps inside rows of 16 lanes, then row broadcasts across rows.
+template <uint32_t W>
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t lane) {
+  constexpr uint32_t kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  if constexpr (W >= 2) {
+    const uint32_t y = dpp_or_zero<kRowShr + 1>(x);
+    x += (W >= 16 || (lane & (W - 1u)) >= 1u) ? y : 0u;
+  }
+  if constexpr (W >= 4) {
+    const uint32_t y = dpp_or_zero<kRowShr + 2>(x);
+    x += (W >= 16 || (lane & (W - 1u)) >= 2u) ? y : 0u;
+  }
+  if constexpr (W >= 8) {
+    const uint32_t y = dpp_or_zero<kRowShr + 4>(x);
+    x += (W >= 16 || (lane & (W - 1u)) >= 4u) ? y : 0u;
+  }
+  if constexpr (W >= 16) x += dpp_or_zero<kRowShr + 8>(x);
+  if constexpr (W >= 32) x += dpp_or_zero<kRowBcast15, 0xA>(x);  // row 0 -> row 1, row 2 -> row 3
+  if constexpr (W >= 64) x += dpp_or_zero<kRowBcast31, 0xC>(x);  // lane 31 -> rows 2 and 3
+  return x;
+}
+
 // Exclusive scan over aligned segments of SEG lanes (SEG a power of two).
 template <uint32_t SEG>
 __device__ __forceinline__ uint32_t seg_scan(uint32_t v, uint32_t* swave, uint32_t* total) {
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   constexpr uint32_t W = SEG < 64u ? SEG : 64u;
-  uint32_t x = v;
-#pragma unroll
-  for (uint32_t off = 1; off < W; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if ((lane & (W - 1u)) >= off) x += y;
-  }
+  const uint32_t x = wave_incl_scan<W>(v, lane);
   if constexpr (SEG <= 64u) {
-    *total = __shfl(x, int(lane | (W - 1u)), 64);
+    if constexpr (W == 64u)
+      *total = uint32_t(__builtin_amdgcn_readlane(int(x), 63));
+    else
+      *total = __shfl(x, int(lane | (W - 1u)), 64);
     return x - v;
   } else {
     if (lane == 63u) swave[wave] = x;
@@ -270,7 +314,7 @@ __device__ __forceinline__ void bitonic_phase(E (&v)[16], const V& lds, const Bi
 #pragma unroll
         for (uint32_t e = 0; e < 16; ++e) lds.st(bl.pbase + e, v[e]);
       }
-      lds_barrier();
+      lds_group_sync<(1u << LZ) / 16u>();  // a bin's lanes
       if (bl.active) {
 #pragma unroll
         for (uint32_t e = 0; e < 16; ++e) {
@@ -286,7 +330,7 @@ __device__ __forceinline__ void bitonic_phase(E (&v)[16], const V& lds, const Bi
           lds.st(bl.bbase + sl + (sl >> 4), v[e]);
         }
       }
-      lds_barrier();
+      lds_group_sync<(1u << LZ) / 16u>();
       if (bl.active) {
 #pragma unroll
         for (uint32_t e = 0; e < 16; ++e) v[e] = lds.ld(bl.pbase + e);
@@ -664,7 +708,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
             stag[baseA + e] = tv[e];
           }
         }
-        lds_barrier();
+        lds_group_sync<TPM>();  // layouts A and B of one MergeSplit share its lanes
         // Layout B pairs lanes through DPP only for Z >= 1024; below that the
         // lanes simply take consecutive slots (conflict-free LDS access).
         const uint32_t lb0 = lt & 1u, lb1 = (lt >> 1) & 1u, rest = lt >> 2;

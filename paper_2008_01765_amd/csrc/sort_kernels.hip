@@ -157,7 +157,20 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
   const uint64_t a0 = split[2 * b], b0 = split[2 * b + 1];
   const uint64_t a1 = o1 == hi ? mid : split[2 * b + 2], b1 = o1 == hi ? hi : split[2 * b + 3];
   const uint32_t na = uint32_t(a1 - a0), nb = uint32_t(b1 - b0), cnt = na + nb;
-  for (uint32_t t = threadIdx.x; t < cnt; t += kMThreads) s[t] = t < na ? src[a0 + t] : src[b0 + t - na];
+  {
+    // issue every load of this thread before the first LDS store
+    T in[kMItems];
+#pragma unroll
+    for (uint32_t k = 0; k < kMItems; ++k) {
+      const uint32_t t = threadIdx.x + k * kMThreads;
+      if (t < cnt) in[k] = t < na ? src[a0 + t] : src[b0 + t - na];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kMItems; ++k) {
+      const uint32_t t = threadIdx.x + k * kMThreads;
+      if (t < cnt) s[t] = in[k];
+    }
+  }
   __syncthreads();
   const uint32_t dd = threadIdx.x * kMItems;
   T out[kMItems];
@@ -188,7 +201,11 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
     for (uint32_t k = 0; k < kMItems; ++k) s[dd + k + (dd >> 4)] = out[k];  // one pad slot per 16
   }
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < cnt; t += kMThreads) dst[o0 + t] = s[t + (t >> 4)];
+#pragma unroll
+  for (uint32_t k = 0; k < kMItems; ++k) {
+    const uint32_t t = threadIdx.x + k * kMThreads;
+    if (t < cnt) dst[o0 + t] = s[t + (t >> 4)];
+  }
 }
 
 template <int R>
