@@ -51,6 +51,8 @@ def parse():
                     help="requests of the serving workload (log-uniform 2^12..2^24, 16 B, Poisson); 0 skips")
     ap.add_argument("--serving-load", type=float, default=0.7,
                     help="offered load as a fraction of the sequential server's capacity")
+    ap.add_argument("--tuning", default="",
+                    help="tuning table for the batched and serving legs (default: the stored table)")
     return ap.parse_args()
 
 
@@ -78,9 +80,22 @@ def traffic_from_profile(kind, config_tag):
     return float(m_b.group(1))
 
 
+def install_tuning(args, bos):
+    """Install the autotuner's table (z, k, tile = 0 then resolve per size class)."""
+    from paper_2008_01765_amd import autotune
+
+    path = args.tuning or autotune.DEFAULT_TABLE
+    if not os.path.exists(path):
+        bos.set_tuning([])
+        return None
+    autotune.install(path=path)
+    return os.path.relpath(path, ROOT)
+
+
 def bench_batched(args, torch, bos, inputs):
     """4096 independent sorts of log-uniform sizes in one bos_sort_batched call
-    (graph replay) against the same instances sorted one call each."""
+    (graph replay) against the same instances sorted one call each, all with
+    Z, k and tile from the tuning table per size class."""
     import numpy as np
 
     dev = torch.device("cuda", 0)
@@ -125,7 +140,7 @@ def bench_batched(args, torch, bos, inputs):
 
     _, sync_wall = timed(lambda: plain(True), 1)
     _, async_wall = timed(lambda: plain(False), 1)
-    res = {"instances": len(ins), "total_records": total, "rec_bytes": 16,
+    res = {"instances": len(ins), "total_records": total, "rec_bytes": 16, "tuning": args.tuning_used,
            "sizes": "log-uniform 2^10..2^20, rescaled to total <= 2^28",
            "batched_ms": round(batched_wall, 3), "batched_gpu_ms": round(batched_ms, 3),
            "batched_Melem/s": round(total / batched_wall / 1e3, 1),
@@ -174,7 +189,7 @@ def bench_serving(args, torch, bos, inputs):
     lat_s, _ = serving.run_trace_sequential(reqs, arr)
     span_s = max(a + l for a, l in zip(arr, lat_s))
     total = int(sizes.sum())
-    res = {"requests": len(reqs), "rec_bytes": 16, "sizes": "log-uniform 2^12..2^24",
+    res = {"requests": len(reqs), "rec_bytes": 16, "sizes": "log-uniform 2^12..2^24", "tuning": args.tuning_used,
            "arrivals": "Poisson, %.1f req/s (%.0f%% of the sequential capacity)" % (rate, 100 * args.serving_load),
            "hbm_budget_GiB": 64, "steps": srv.steps, "peak_resident_GiB": round(srv.peak_used / 2 ** 30, 2),
            "batching": {"p50_ms": round(serving.percentile(lat_b, 50) * 1e3, 3),
@@ -331,6 +346,9 @@ def main():
                "host": os.uname().nodename, "nproc": os.cpu_count()}
 
     batched = None
+    args.tuning_used = None
+    if (args.batched_count > 0 or args.serving_requests > 0) and args.mode == "sort":
+        args.tuning_used = install_tuning(args, bos)
     if args.batched_count > 0 and args.mode == "sort":
         batched = bench_batched(args, torch, bos, inputs)
         print("batched: %s" % json.dumps(batched), file=sys.stderr, flush=True)

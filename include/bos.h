@@ -61,9 +61,12 @@ typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
 typedef struct {
   uint64_t seed;              /* Philox key: labels and per-bin permutation keys */
   uint32_t z;                 /* bucket capacity Z (Algorithm 3.1); power of two in
-                                 [8, 2048]; 0 = 512, the paper's choice */
-  uint32_t k;                 /* butterfly levels fused per pass; 0 = planner's choice */
-  uint32_t tile;              /* records per tile of the final sort: 0 or 4096 */
+                                 [8, 2048]; 0 = the tuning table's, else 512 (the
+                                 paper's choice) */
+  uint32_t k;                 /* butterfly levels fused per pass; 0 = the tuning
+                                 table's, else the planner's choice (4) */
+  uint32_t tile;              /* records per tile of the final sort: 1024, 2048 or
+                                 4096; 0 = the tuning table's, else 4096 */
   uint32_t max_retries;       /* extra attempts after an overflow (default 3) */
   uint32_t min_security_bits; /* reject Z when log2(B log2 B e^(-Z/6)) > -bits;
                                  0 disables the check (default 80) */
@@ -172,6 +175,34 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
 size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec);
 bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, void* ws,
                             size_t ws_bytes, void* stream);
+
+/* ---- tuning table --------------------------------------------------------- */
+
+/* One autotuner result: for records of `rec` bytes and n in size class
+ * `log2n` (the smallest c with 2^c >= n), use bucket capacity z, k levels per
+ * pass and comparison-sort tile `tile` (1024, 2048 or 4096).  A zero field
+ * leaves the library default (Z = 512, k = 4, tile = 4096). */
+typedef struct {
+  uint32_t rec;
+  uint32_t log2n;
+  uint32_t z;
+  uint32_t k;
+  uint32_t tile;
+  uint32_t reserved;
+} bos_tune_entry;
+
+/* Replace the process-wide tuning table (count 0 clears it).  Wherever a
+ * caller's bos_params leaves z, k or tile at 0, the plan of an n-record
+ * instance takes them from the entry of the same record size whose size class
+ * is nearest to n's; a tuned z that falls short of min_security_bits at that
+ * n is doubled until it meets it (Lemma 3.2).  With z = 0, bos_orp's output
+ * therefore depends on the table: pass an explicit z for a fixed result
+ * (bos_sort's output never depends on it).  Drops cached batch graphs.
+ * Errors: INVALID_ARG (record size, z, k or tile out of range). */
+bos_status bos_set_tuning(const bos_tune_entry* entries, uint32_t count);
+
+/* Copy up to `cap` entries of the table into `out`; returns the entry count. */
+uint32_t bos_get_tuning(bos_tune_entry* out, uint32_t cap);
 
 /* Drop cached graphs and plans. */
 void bos_release_cache(void);

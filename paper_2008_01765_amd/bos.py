@@ -56,6 +56,11 @@ class Job(C.Structure):
 PHASE_DONE = 0xFFFFFFFF
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("rec", C.c_uint32), ("log2n", C.c_uint32), ("z", C.c_uint32), ("k", C.c_uint32),
+                ("tile", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 class LaunchTime(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("index", C.c_uint32), ("ms", C.c_float), ("reserved", C.c_uint32),
                 ("bytes", C.c_uint64)]
@@ -67,7 +72,7 @@ KERNEL_KINDS = {1: "route_first", 2: "route_mid", 3: "route_last", 4: "route_sin
 EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "bos_batched_workspace_bytes",
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
-           "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step"]
+           "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning"]
 
 _lib = None
 
@@ -96,6 +101,10 @@ def lib():
         L.bos_step_workspace_bytes.restype = C.c_size_t
         L.bos_sort_step.argtypes = [C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
         L.bos_sort_step.restype = C.c_int
+        L.bos_set_tuning.argtypes = [C.POINTER(TuneEntry), u32]
+        L.bos_set_tuning.restype = C.c_int
+        L.bos_get_tuning.argtypes = [C.POINTER(TuneEntry), u32]
+        L.bos_get_tuning.restype = u32
         L.bos_bitonic_workspace_bytes.argtypes = [u64, C.c_int]
         L.bos_bitonic_workspace_bytes.restype = C.c_size_t
         L.bos_bitonic_sort.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
@@ -249,6 +258,22 @@ def sort_step(jobs, rec, p, step_ws, stream=None):
 
 def step_workspace_bytes(count):
     return lib().bos_step_workspace_bytes(count)
+
+
+def set_tuning(entries):
+    """Install the tuning table: dicts {rec, log2n, z, k, tile} (bos_set_tuning)."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i].rec, arr[i].log2n = int(e["rec"]), int(e["log2n"])
+        arr[i].z, arr[i].k, arr[i].tile = int(e.get("z", 0)), int(e.get("k", 0)), int(e.get("tile", 0))
+    _check(lib().bos_set_tuning(arr, len(entries)))
+
+
+def get_tuning():
+    cnt = lib().bos_get_tuning(None, 0)
+    arr = (TuneEntry * max(1, cnt))()
+    lib().bos_get_tuning(arr, cnt)
+    return [{"rec": e.rec, "log2n": e.log2n, "z": e.z, "k": e.k, "tile": e.tile} for e in arr[:cnt]]
 
 
 def bitonic_sort(t, out=None, stream=None):

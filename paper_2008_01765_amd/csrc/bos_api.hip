@@ -33,7 +33,7 @@ size_t comparison_sort_split_bytes(uint64_t n);
 hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
                                 const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
                                 uint32_t lds, hipStream_t s);
-hipError_t launch_sort_batched(int rec, int kind, const SortSeg* segs, uint32_t nsegs, uint32_t total,
+hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs, uint32_t total,
                                hipStream_t s);
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
 hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s);
@@ -137,8 +137,39 @@ bos_params resolve(const bos_params* p) {
   } else {
     fill_defaults(&q);
   }
-  if (q.z == 0) q.z = 512;
   return q;
+}
+
+// ---- tuning table: (record size, size class) -> Z, k, tile -----------------
+// Filled by bos_set_tuning (the autotuner); consulted by make_plan wherever
+// the caller leaves z, k or tile at 0.
+std::mutex g_tune_mu;
+std::vector<bos_tune_entry> g_tune;
+
+uint32_t size_class(uint64_t n) {
+  uint32_t c = 0;
+  while (c < 63 && (1ull << c) < n) ++c;
+  return c;
+}
+
+// The entry for this record size whose size class is nearest to n's (the
+// smaller class on a tie).
+bool tuned_for(uint64_t n, int rec, bos_tune_entry* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const int64_t c = size_class(n);
+  const bos_tune_entry* best = nullptr;
+  int64_t bd = 0;
+  for (const bos_tune_entry& e : g_tune) {
+    if (int(e.rec) != rec) continue;
+    const int64_t d = int64_t(e.log2n) - c, ad = d < 0 ? -d : d;
+    if (!best || ad < bd || (ad == bd && e.log2n < best->log2n)) {
+      best = &e;
+      bd = ad;
+    }
+  }
+  if (!best) return false;
+  *out = *best;
+  return true;
 }
 
 // Largest k such that a block of 2^k buckets fits in LDS and in 512 threads.
@@ -153,60 +184,85 @@ uint32_t max_klev(int rec, uint32_t z, bool last_shuffle) {
   return best;
 }
 
-bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last, Plan* pl) {
-  if (rec != 8 && rec != 16) return BOS_ERR_INVALID_ARG;
-  if (n > kMaxN) return BOS_ERR_INVALID_ARG;
-  const uint32_t Z = q.z;
-  if (Z < 8 || Z > 2048 || (Z & (Z - 1))) return BOS_ERR_INVALID_ARG;
-  pl->n = n;
-  pl->rec = rec;
-  pl->Z = Z;
-  pl->generic = (q.flags & BOS_GENERIC_ROUTING) != 0;
-  pl->lz = 0;
-  while ((1u << pl->lz) < Z) ++pl->lz;
+bool tile_ok(uint32_t t) { return t == 1024 || t == 2048 || t == 4096; }
+
+// Lemma 3.2: overflow probability <= B log2 B e^(-Z/6) (B = 2^L)
+bool insecure(uint32_t L, uint32_t Z, uint32_t bits) {
+  if (!bits || L == 0) return false;
+  const double log2eps = double(L) + std::log2(double(L)) - double(Z) / (6.0 * std::log(2.0));
+  return log2eps > -double(bits);
+}
+
+uint32_t levels_for(uint64_t n, uint32_t Z, uint64_t* B_out) {
   uint64_t B = 1;
   uint32_t L = 0;
   while (B * Z < 2 * n) {
     B *= 2;
     ++L;
   }
+  *B_out = B;
+  return L;
+}
+
+bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last, Plan* pl) {
+  if (rec != 8 && rec != 16) return BOS_ERR_INVALID_ARG;
+  if (n > kMaxN) return BOS_ERR_INVALID_ARG;
+  bos_tune_entry te;
+  std::memset(&te, 0, sizeof(te));
+  const bool tuned = (q.z == 0 || q.k == 0 || q.tile == 0) && tuned_for(n, rec, &te);
+  uint32_t Z = q.z ? q.z : (tuned && te.z ? te.z : 512u);
+  if (Z < 8 || Z > 2048 || (Z & (Z - 1))) return BOS_ERR_INVALID_ARG;
+  uint64_t B = 1;
+  uint32_t L = levels_for(n, Z, &B);
+  if (q.z == 0) {
+    // a tuned Z below the caller's security floor gives way to a larger one
+    while (insecure(L, Z, q.min_security_bits) && Z < 2048) {
+      Z *= 2;
+      L = levels_for(n, Z, &B);
+    }
+  }
   if (L > 31) return BOS_ERR_INVALID_ARG;
+  if (insecure(L, Z, q.min_security_bits)) return BOS_ERR_INSECURE_Z;
+  pl->n = n;
+  pl->rec = rec;
+  pl->Z = Z;
+  pl->generic = (q.flags & BOS_GENERIC_ROUTING) != 0;
+  pl->lz = 0;
+  while ((1u << pl->lz) < Z) ++pl->lz;
   pl->B = B;
   pl->L = L;
-  // Lemma 3.2: overflow probability <= B log2 B e^(-Z/6)
-  if (q.min_security_bits && L > 0) {
-    const double log2eps = double(L) + std::log2(double(L)) - double(Z) / (6.0 * std::log(2.0));
-    if (log2eps > -double(q.min_security_bits)) return BOS_ERR_INSECURE_Z;
-  }
   const uint32_t kmid = max_klev(rec, Z, false), klast = max_klev(rec, Z, shuffle_last);
   if (kmid == 0 || klast == 0) return BOS_ERR_UNSUPPORTED;
-  uint32_t k = q.k ? std::min(q.k, kmid) : std::min(4u, kmid);
+  const uint32_t kreq = q.k ? q.k : (tuned && te.k && te.z == Z ? te.k : 4u);
+  const uint32_t k = std::min(kreq, kmid);
   pl->k = k;
-  pl->tile = q.tile ? q.tile : kDefaultTile;
-  if (pl->tile != kDefaultTile) return BOS_ERR_INVALID_ARG;  // the tile sort is built for 4096
+  pl->tile = q.tile ? q.tile : (tuned && te.tile ? te.tile : kDefaultTile);
+  if (!tile_ok(pl->tile)) return BOS_ERR_INVALID_ARG;
   if (L == 0) {
     pl->P = 1;
     pl->klev[0] = 0;
     pl->lev0[0] = 0;
   } else {
+    // fewest passes of at most k levels, balanced; the larger passes go last
+    // (the last pass, whose per-bin finish is amortized over its bins, gets
+    // as many levels as it may)
     uint32_t P = (L + k - 1) / k;
     for (;; ++P) {
       if (P > kMaxPasses) return BOS_ERR_UNSUPPORTED;
       const uint32_t base = L / P, extra = L % P;
-      // passes 0..extra-1 get base+1 levels, the rest base; the last gets base
-      // (or base+1 if P == extra, impossible since extra < P)
-      const uint32_t last_lv = base;
-      if (base + (extra ? 1 : 0) <= k && last_lv <= klast && last_lv >= 1) {
-        uint32_t lv = 0;
-        for (uint32_t t = 0; t < P; ++t) {
-          pl->klev[t] = base + (t < extra ? 1 : 0);
-          pl->lev0[t] = lv;
-          lv += pl->klev[t];
-        }
-        pl->P = P;
-        break;
-      }
       if (base == 0) return BOS_ERR_UNSUPPORTED;
+      if (base + (extra ? 1u : 0u) > k) continue;
+      const bool big_last = extra > 0 && base + 1 <= klast;
+      if (!big_last && base > klast) continue;
+      uint32_t lv = 0;
+      for (uint32_t t = 0; t < P; ++t) {
+        const bool big = big_last ? (t >= P - extra) : (t < extra);
+        pl->klev[t] = base + (big ? 1u : 0u);
+        pl->lev0[t] = lv;
+        lv += pl->klev[t];
+      }
+      pl->P = P;
+      break;
     }
   }
   pl->nblocks_last = uint32_t(B >> pl->klev[pl->P - 1]);
@@ -358,13 +414,17 @@ bool has_gpu() {
 
 // ---- batched engine -----------------------------------------------------
 //
-// bos_sort_batched plans every instance on its own (same Z and k), gives each
-// a workspace region, and runs all of them pass-major: one launch per routing
-// pass index and pass kind (first / middle / last / single) over a table of
-// per-instance pass arguments, then one batched tile sort and one batched
-// launch pair per merge pass.  The launch sequence is captured once into a
-// hipGraph per batch shape (sizes, record type, Z, k, workspace) and
-// replayed; the tables (pointers, seeds) are re-uploaded before every replay.
+// bos_sort_batched plans every instance on its own (its own Z, k and tile when
+// they come from the tuning table), gives each a workspace region, and runs
+// all of them pass-major: one launch per routing pass index, pass kind
+// (first / middle / last / single) and Z over a table of per-instance pass
+// arguments, then one batched tile sort per tile size and one batched launch
+// pair per merge pass.  The launch sequence is captured once into a hipGraph
+// per batch shape (sizes, record type, plans, workspace) and replayed; the
+// tables (pointers, seeds) are re-uploaded before every replay.
+
+// Z values with batched routing kernels.
+bool batched_lz(uint32_t lz) { return lz == 5 || lz == 8 || lz == 9 || lz == 10; }
 
 struct BatchJob {
   const void* in = nullptr;
@@ -375,12 +435,14 @@ struct BatchJob {
   void* start = nullptr;  // routing output (where the comparison sort starts)
   void* other = nullptr;
   uint32_t merges = 0;
-  bool special = false;   // single bin (L = 0): routed by the generic kernel
+  bool special = false;   // routed on its own (single bin, or a Z without batched kernels)
 };
 
 struct BLaunch {
   int kind = 0;  // 0 fill, 1 route, 2 tile sort, 3 merge pass, 4 status, 5 plain routing of one job
   int mode = 0;  // route: bit 0 first, bit 1 last
+  uint32_t lz = 0;    // route: log2 Z of the launch
+  uint32_t tile = 0;  // tile sort: records per tile
   uint32_t nsegs = 0, blocks = 0, threads = 0, lds = 0, total = 0, job = 0;
   size_t tab = 0, aux = 0;
 };
@@ -392,7 +454,6 @@ struct Batch {
   size_t tab_base = 0;  // offset of the tables in the workspace
   size_t total = 0;
   bool batched = true;
-  uint32_t lz = 9;
   int rec = 8;
 };
 
@@ -408,7 +469,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
                        char* ws, Batch* b) {
   b->jobs.assign(count, BatchJob());
   b->rec = rec;
-  b->batched = !(q.flags & BOS_GENERIC_ROUTING) && (q.z == 32 || q.z == 256 || q.z == 512 || q.z == 1024);
+  b->batched = !(q.flags & BOS_GENERIC_ROUTING);
   size_t off = 0;
   for (uint32_t i = 0; i < count; ++i) {
     BatchJob& j = b->jobs[i];
@@ -420,14 +481,13 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     }
     const bos_status st = make_plan(j.n, rec, q, true, &j.pl);
     if (st != BOS_OK) return st;
-    b->lz = j.pl.lz;
     j.ws = ws ? ws + off : nullptr;
     off = align_up(off + j.pl.total);
     j.merges = comparison_sort_passes(j.n, j.pl.tile);
     char* tmp = j.ws ? j.ws + j.pl.off_rec[(j.pl.P + 1) & 1] : nullptr;
     j.start = (j.merges % 2 == 0) ? j.out : static_cast<void*>(tmp);
     j.other = (j.merges % 2 == 0) ? static_cast<void*>(tmp) : j.out;
-    j.special = j.pl.L == 0 || !use_route_kernel(j.pl, 0);
+    j.special = j.pl.L == 0 || !use_route_kernel(j.pl, 0) || !batched_lz(j.pl.lz);
   }
   b->tab_base = align_up(off);
   if (!b->batched) {
@@ -455,53 +515,56 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     if (j.n && !j.special) maxP = std::max(maxP, j.pl.P);
   for (uint32_t t = 0; t < maxP; ++t) {
     for (int mode : {3, 1, 0, 2}) {
-      std::vector<PassArgs> segs;
-      std::vector<uint32_t> starts;
-      uint32_t blocks = 0, threads = 64, lds = 0;
-      for (const BatchJob& j : b->jobs) {
-        if (!j.n || j.special || t >= j.pl.P) continue;
-        const bool first = t == 0, last = t + 1 == j.pl.P;
-        if (((first ? 1 : 0) | (last ? 2 : 0)) != mode) continue;
-        PassArgs a;
-        std::memset(&a, 0, sizeof(a));
-        const Plan& pl = j.pl;
-        unsigned long long* status = reinterpret_cast<unsigned long long*>(j.ws + pl.off_status);
-        a.x_in = j.in;
-        a.out = j.start;
-        a.rec_in = j.ws + pl.off_rec[(t + 1) & 1];
-        a.tag_in = reinterpret_cast<const uint32_t*>(j.ws + pl.off_tag[(t + 1) & 1]);
-        a.rec_out = j.ws + pl.off_rec[t & 1];
-        a.tag_out = reinterpret_cast<uint32_t*>(j.ws + pl.off_tag[t & 1]);
-        a.status = status;
-        a.ticket = reinterpret_cast<uint32_t*>(status + 1);
-        a.scan = status + 2;
-        a.n = pl.n;
-        a.buckets = pl.B;
-        a.seed = j.seed;
-        a.z = pl.Z;
-        a.lz = pl.lz;
-        a.levels = pl.L;
-        a.level0 = pl.lev0[t];
-        a.klev = pl.klev[t];
-        a.attempt = 0;
-        a.fin = 1;
-        segs.push_back(a);
-        starts.push_back(blocks);
-        blocks += uint32_t(pl.B >> pl.klev[t]);
-        threads = std::max(threads, uint32_t((pl.Z << pl.klev[t]) >> 4));
-        lds = std::max(lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false));
+      for (uint32_t lz = 4; lz <= 11; ++lz) {
+        std::vector<PassArgs> segs;
+        std::vector<uint32_t> starts;
+        uint32_t blocks = 0, threads = 64, lds = 0;
+        for (const BatchJob& j : b->jobs) {
+          if (!j.n || j.special || t >= j.pl.P || j.pl.lz != lz) continue;
+          const bool first = t == 0, last = t + 1 == j.pl.P;
+          if (((first ? 1 : 0) | (last ? 2 : 0)) != mode) continue;
+          PassArgs a;
+          std::memset(&a, 0, sizeof(a));
+          const Plan& pl = j.pl;
+          unsigned long long* status = reinterpret_cast<unsigned long long*>(j.ws + pl.off_status);
+          a.x_in = j.in;
+          a.out = j.start;
+          a.rec_in = j.ws + pl.off_rec[(t + 1) & 1];
+          a.tag_in = reinterpret_cast<const uint32_t*>(j.ws + pl.off_tag[(t + 1) & 1]);
+          a.rec_out = j.ws + pl.off_rec[t & 1];
+          a.tag_out = reinterpret_cast<uint32_t*>(j.ws + pl.off_tag[t & 1]);
+          a.status = status;
+          a.ticket = reinterpret_cast<uint32_t*>(status + 1);
+          a.scan = status + 2;
+          a.n = pl.n;
+          a.buckets = pl.B;
+          a.seed = j.seed;
+          a.z = pl.Z;
+          a.lz = pl.lz;
+          a.levels = pl.L;
+          a.level0 = pl.lev0[t];
+          a.klev = pl.klev[t];
+          a.attempt = 0;
+          a.fin = 1;
+          segs.push_back(a);
+          starts.push_back(blocks);
+          blocks += uint32_t(pl.B >> pl.klev[t]);
+          threads = std::max(threads, uint32_t((pl.Z << pl.klev[t]) >> 4));
+          lds = std::max(lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false));
+        }
+        if (segs.empty()) continue;
+        BLaunch l;
+        l.kind = 1;
+        l.mode = mode;
+        l.lz = lz;
+        l.nsegs = uint32_t(segs.size());
+        l.blocks = blocks;
+        l.threads = threads;
+        l.lds = lds;
+        l.tab = push_table(tab, segs);
+        l.aux = push_table(tab, starts);
+        b->launches.push_back(l);
       }
-      if (segs.empty()) continue;
-      BLaunch l;
-      l.kind = 1;
-      l.mode = mode;
-      l.nsegs = uint32_t(segs.size());
-      l.blocks = blocks;
-      l.threads = threads;
-      l.lds = lds;
-      l.tab = push_table(tab, segs);
-      l.aux = push_table(tab, starts);
-      b->launches.push_back(l);
     }
   }
   for (uint32_t i = 0; i < count; ++i)
@@ -511,25 +574,25 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
       l.job = i;
       b->launches.push_back(l);
     }
-  // 2. tile sort
-  const uint64_t T = kDefaultTile;
-  {
+  // 2. tile sort, one launch per tile size
+  for (uint32_t T : {4096u, 2048u, 1024u}) {
     std::vector<SortSeg> segs;
     uint32_t tiles = 0;
     for (const BatchJob& j : b->jobs) {
-      if (j.n <= 1) continue;
+      if (j.n <= 1 || j.pl.tile != T) continue;
       const uint32_t c = uint32_t((j.n + T - 1) / T);
       segs.push_back(SortSeg{j.start, nullptr, j.n, 0, nullptr, tiles, c});
       tiles += c;
     }
     BLaunch l;
     l.kind = 2;
+    l.tile = T;
     l.nsegs = uint32_t(segs.size());
     l.total = tiles;
     l.tab = push_table(tab, segs);
     if (l.nsegs) b->launches.push_back(l);
   }
-  // 3. merge passes
+  // 3. merge passes (runs of width tile << pass, merge tiles of kMergeTile)
   uint32_t maxM = 0;
   for (const BatchJob& j : b->jobs) maxM = std::max(maxM, j.merges);
   for (uint32_t pass = 0; pass < maxM; ++pass) {
@@ -537,10 +600,11 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     uint32_t tiles = 0;
     for (const BatchJob& j : b->jobs) {
       if (pass >= j.merges) continue;
-      const uint32_t c = uint32_t((j.n + T - 1) / T);
+      const uint32_t c = uint32_t((j.n + kMergeTile - 1) / kMergeTile);
       void* src = (pass % 2 == 0) ? j.start : j.other;
       void* dst = (pass % 2 == 0) ? j.other : j.start;
-      segs.push_back(SortSeg{src, dst, j.n, T << pass, reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), tiles, c});
+      segs.push_back(SortSeg{src, dst, j.n, uint64_t(j.pl.tile) << pass,
+                             reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), tiles, c});
       tiles += c;
     }
     BLaunch l;
@@ -574,18 +638,20 @@ hipError_t enqueue_batch(const Batch& b, char* tables, hipStream_t s, uint32_t* 
         e = launch_fill_status_batched(reinterpret_cast<const FillSeg*>(tables + l.tab), l.nsegs, s);
         break;
       case 1:
-        e = launch_route_batched(b.rec, b.lz, (l.mode & 1) != 0, (l.mode & 2) != 0,
+        e = launch_route_batched(b.rec, l.lz, (l.mode & 1) != 0, (l.mode & 2) != 0,
                                  reinterpret_cast<const PassArgs*>(tables + l.tab),
                                  reinterpret_cast<const uint32_t*>(tables + l.aux), l.nsegs, l.blocks, l.threads,
                                  l.lds, s);
         break;
       case 2:
-        e = launch_sort_batched(b.rec, 0, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
+        e = launch_sort_batched(b.rec, 0, l.tile, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total,
+                                s);
         break;
       case 3:
-        e = launch_sort_batched(b.rec, 1, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
+        e = launch_sort_batched(b.rec, 1, 0, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
         if (e == hipSuccess)
-          e = launch_sort_batched(b.rec, 2, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total, s);
+          e = launch_sort_batched(b.rec, 2, 0, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total,
+                                  s);
         break;
       case 4:
         e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(tables + l.tab), d_status, l.nsegs, s);
@@ -620,7 +686,13 @@ std::string batch_key(const Batch& b, const bos_params& q, const char* tables, c
   add(&q.k, 4);
   add(&tables, sizeof(tables));
   add(&d_status, sizeof(d_status));
-  for (const BatchJob& j : b.jobs) add(&j.n, 8);
+  for (const BatchJob& j : b.jobs) {
+    add(&j.n, 8);
+    add(&j.pl.Z, 4);
+    add(&j.pl.tile, 4);
+    add(&j.pl.P, 4);
+    add(j.pl.klev, sizeof(uint32_t) * j.pl.P);
+  }
   // jobs whose routing is launched directly carry their pointers in kernel
   // arguments, not in the tables
   for (const BatchJob& j : b.jobs)
@@ -802,10 +874,14 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
   if (st != BOS_OK) return st;
   if (!ws || ws_bytes < b.total) return BOS_ERR_WORKSPACE;
   if (rep) {
+    // Z, k and tile when every instance shares them, else 0
     std::memset(rep, 0, sizeof(*rep));
-    rep->z = q.z;
-    rep->k = q.k;
-    rep->tile = kDefaultTile;
+    for (uint32_t i = 0; i < count; ++i) {
+      const Plan& pl = b.jobs[i].pl;
+      rep->z = (i == 0 || rep->z == pl.Z) ? pl.Z : 0;
+      rep->k = (i == 0 || rep->k == pl.k) ? pl.k : 0;
+      rep->tile = (i == 0 || rep->tile == pl.tile) ? pl.tile : 0;
+    }
     rep->first_overflow_level = -1;
     rep->first_overflow_pair = -1;
   }
@@ -880,7 +956,9 @@ constexpr uint64_t kStepFixed = 1ull << 17;    // launch overhead, in records
 constexpr uint64_t kStepMinQuantum = 1ull << 21;
 
 size_t step_round_bytes(uint32_t count) {
-  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + 2 * sizeof(SortSeg)) + 12 * kAlign;
+  // every job adds at most one entry of each kind; each table starts aligned
+  // (fill, 2 per route group of at most 4 kinds x 8 Z, 3 tile sizes, merge)
+  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + 2 * sizeof(SortSeg)) + 72 * kAlign;
 }
 
 size_t bos_step_workspace_bytes(uint32_t count) {
@@ -896,7 +974,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (count == 0) return BOS_OK;
   if (!step_ws || step_ws_bytes < bos_step_workspace_bytes(count)) return BOS_ERR_WORKSPACE;
-  const bool batched_z = !(q.flags & BOS_GENERIC_ROUTING) && (q.z == 32 || q.z == 256 || q.z == 512 || q.z == 1024);
+  const bool batchable = !(q.flags & BOS_GENERIC_ROUTING);
   std::vector<Plan> plans(count);
   std::vector<uint32_t> merges(count, 0), allowed(count, 0);
   std::vector<char> routed(count, 0);  // finished an attempt's routing in this step
@@ -945,26 +1023,30 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
   auto other_buf = [&](uint32_t i) -> void* { return (merges[i] % 2 == 0) ? tmp_buf(i) : jobs[i].out; };
 
   // Build every sub-round's tables on the host, then upload them at once.
+  // route launches of a round: one per (pass kind, log2 Z); tile sorts: one
+  // per tile size (index 0, 1, 2 = 4096, 2048, 1024)
+  struct RouteGroup {
+    std::vector<PassArgs> args;
+    std::vector<uint32_t> starts;
+    size_t o_args = 0, o_starts = 0;
+    uint32_t blocks = 0, threads = 64, lds = 0, items0 = 0;
+  };
   struct Round {
-    size_t o_fill = 0, o_route[4] = {0, 0, 0, 0}, o_start[4] = {0, 0, 0, 0}, o_tile = 0, o_merge = 0;
-    uint32_t nfill = 0, nroute[4] = {0, 0, 0, 0}, ntile = 0, nmerge = 0;
-    uint32_t rblocks[4] = {0, 0, 0, 0}, rthreads[4] = {64, 64, 64, 64}, rlds[4] = {0, 0, 0, 0}, rlz[4] = {0, 0, 0, 0};
-    uint32_t tiles = 0, mtiles = 0;
-    PassArgs single[4];
-    uint32_t single_items[4] = {0, 0, 0, 0};
+    size_t o_fill = 0, o_tile[3] = {0, 0, 0}, o_merge = 0;
+    uint32_t nfill = 0, ntile[3] = {0, 0, 0}, nmerge = 0;
+    uint32_t tiles[3] = {0, 0, 0}, mtiles = 0;
+    std::map<uint32_t, RouteGroup> route;  // key: mode * 16 + lz
     std::vector<uint32_t> whole;  // jobs routed by the per-job path in this round
   };
+  const uint32_t kTiles[3] = {4096, 2048, 1024};
   std::vector<Round> rounds;
   std::vector<char> tab;
   std::vector<uint32_t> phase(count);
   for (uint32_t i = 0; i < count; ++i) phase[i] = jobs[i].phase;
-  const uint64_t T = kDefaultTile;
   for (uint32_t r = 0; r < kStepRounds; ++r) {
     Round rd;
     std::vector<FillSeg> fills;
-    std::vector<PassArgs> route[4];
-    std::vector<uint32_t> starts[4];
-    std::vector<SortSeg> tiles, mseg;
+    std::vector<SortSeg> tiles[3], mseg;
     bool any = false;
     for (uint32_t i = 0; i < count; ++i) {
       if (phase[i] == BOS_PHASE_DONE || allowed[i] <= r) continue;
@@ -974,7 +1056,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       any = true;
       const uint32_t ph = phase[i];
       if (ph < pl.P) {
-        if (pl.L == 0 || !batched_z || !use_route_kernel(pl, ph)) {
+        if (pl.L == 0 || !batchable || !batched_lz(pl.lz) || !use_route_kernel(pl, ph)) {
           if (ph != 0) return BOS_ERR_INVALID_ARG;  // per-job routing runs a whole attempt at once
           rd.whole.push_back(i);
           phase[i] = pl.P;
@@ -1007,14 +1089,13 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
         a.attempt = j.attempt;
         a.fin = 1;
         const uint32_t items = uint32_t(pl.B >> pl.klev[ph]);
-        rd.single[mode] = a;
-        rd.single_items[mode] = items;
-        route[mode].push_back(a);
-        starts[mode].push_back(rd.rblocks[mode]);
-        rd.rblocks[mode] += items;
-        rd.rthreads[mode] = std::max(rd.rthreads[mode], uint32_t((pl.Z << pl.klev[ph]) >> 4));
-        rd.rlds[mode] = std::max(rd.rlds[mode], pass_lds_bytes(R, pl.Z, pl.klev[ph], false));
-        rd.rlz[mode] = pl.lz;
+        RouteGroup& g = rd.route[uint32_t(mode) * 16u + pl.lz];
+        if (g.args.empty()) g.items0 = items;
+        g.args.push_back(a);
+        g.starts.push_back(g.blocks);
+        g.blocks += items;
+        g.threads = std::max(g.threads, uint32_t((pl.Z << pl.klev[ph]) >> 4));
+        g.lds = std::max(g.lds, pass_lds_bytes(R, pl.Z, pl.klev[ph], false));
         if (last) {
           phase[i] = pl.P;  // on to the tile sort; the check is at the end of the step
           routed[i] = 1;
@@ -1022,16 +1103,20 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
           ++phase[i];
         }
       } else if (ph == pl.P) {
+        const uint32_t ti = pl.tile == 4096 ? 0u : pl.tile == 2048 ? 1u : 2u, T = pl.tile;
         const uint32_t c = uint32_t((j.n + T - 1) / T);
-        if (j.n > 1) tiles.push_back(SortSeg{start_buf(i), nullptr, j.n, 0, nullptr, rd.tiles, c});
-        if (j.n > 1) rd.tiles += c;
+        if (j.n > 1) {
+          tiles[ti].push_back(SortSeg{start_buf(i), nullptr, j.n, 0, nullptr, rd.tiles[ti], c});
+          rd.tiles[ti] += c;
+        }
         phase[i] = merges[i] == 0 ? BOS_PHASE_DONE : pl.P + 1;
       } else {
         const uint32_t pass = ph - (pl.P + 1);
-        const uint32_t c = uint32_t((j.n + T - 1) / T);
+        const uint32_t c = uint32_t((j.n + kMergeTile - 1) / kMergeTile);
         void* src = (pass % 2 == 0) ? start_buf(i) : other_buf(i);
         void* dst = (pass % 2 == 0) ? other_buf(i) : start_buf(i);
-        mseg.push_back(SortSeg{src, dst, j.n, T << pass, reinterpret_cast<uint64_t*>(w + pl.off_split), rd.mtiles, c});
+        mseg.push_back(SortSeg{src, dst, j.n, uint64_t(pl.tile) << pass, reinterpret_cast<uint64_t*>(w + pl.off_split),
+                               rd.mtiles, c});
         rd.mtiles += c;
         phase[i] = pass + 1 >= merges[i] ? BOS_PHASE_DONE : ph + 1;
       }
@@ -1039,13 +1124,14 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
     if (!any) break;
     rd.nfill = uint32_t(fills.size());
     rd.o_fill = push_table(tab, fills);
-    for (int m = 0; m < 4; ++m) {
-      rd.nroute[m] = uint32_t(route[m].size());
-      rd.o_route[m] = push_table(tab, route[m]);
-      rd.o_start[m] = push_table(tab, starts[m]);
+    for (auto& kv : rd.route) {
+      kv.second.o_args = push_table(tab, kv.second.args);
+      kv.second.o_starts = push_table(tab, kv.second.starts);
     }
-    rd.ntile = uint32_t(tiles.size());
-    rd.o_tile = push_table(tab, tiles);
+    for (int ti = 0; ti < 3; ++ti) {
+      rd.ntile[ti] = uint32_t(tiles[ti].size());
+      rd.o_tile[ti] = push_table(tab, tiles[ti]);
+    }
     rd.nmerge = uint32_t(mseg.size());
     rd.o_merge = push_table(tab, mseg);
     rounds.push_back(std::move(rd));
@@ -1073,22 +1159,26 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       e = enqueue_routing(plans[i], jobs[i].in, start_buf(i), jobs[i].seed, jobs[i].attempt, 1,
                           static_cast<char*>(jobs[i].ws), s);
     }
-    for (int m : {3, 1, 0, 2}) {
-      if (e != hipSuccess || rd.nroute[m] == 0) continue;
-      if (rd.nroute[m] == 1)  // one job: the persistent kernel of the single-sort path
-        e = launch_route(R, rd.single[m], (m & 1) != 0, (m & 2) != 0, rd.single_items[m], num_cus(), s);
+    for (const auto& kv : rd.route) {
+      if (e != hipSuccess) break;
+      const int m = int(kv.first / 16u);
+      const uint32_t lz = kv.first % 16u;
+      const RouteGroup& g = kv.second;
+      if (g.args.size() == 1)  // one job: the persistent kernel of the single-sort path
+        e = launch_route(R, g.args[0], (m & 1) != 0, (m & 2) != 0, g.items0, num_cus(), s);
       else
-        e = launch_route_batched(R, rd.rlz[m], (m & 1) != 0, (m & 2) != 0,
-                                 reinterpret_cast<const PassArgs*>(dtab + rd.o_route[m]),
-                                 reinterpret_cast<const uint32_t*>(dtab + rd.o_start[m]), rd.nroute[m], rd.rblocks[m],
-                                 rd.rthreads[m], rd.rlds[m], s);
+        e = launch_route_batched(R, lz, (m & 1) != 0, (m & 2) != 0, reinterpret_cast<const PassArgs*>(dtab + g.o_args),
+                                 reinterpret_cast<const uint32_t*>(dtab + g.o_starts), uint32_t(g.args.size()),
+                                 g.blocks, g.threads, g.lds, s);
     }
-    if (e == hipSuccess && rd.ntile)
-      e = launch_sort_batched(R, 0, reinterpret_cast<const SortSeg*>(dtab + rd.o_tile), rd.ntile, rd.tiles, s);
+    for (int ti = 0; ti < 3; ++ti)
+      if (e == hipSuccess && rd.ntile[ti])
+        e = launch_sort_batched(R, 0, kTiles[ti], reinterpret_cast<const SortSeg*>(dtab + rd.o_tile[ti]), rd.ntile[ti],
+                                rd.tiles[ti], s);
     if (e == hipSuccess && rd.nmerge) {
-      e = launch_sort_batched(R, 1, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
+      e = launch_sort_batched(R, 1, 0, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
       if (e == hipSuccess)
-        e = launch_sort_batched(R, 2, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
+        e = launch_sort_batched(R, 2, 0, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
     }
   }
   std::vector<uint32_t> st_host(st_ptr.size(), 0);
@@ -1139,6 +1229,29 @@ bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, 
   uint64_t N = kBitonicTile;
   while (N < n) N <<= 1;
   return hip_status(launch_bitonic(int(rec), in, out, n, ws, N, kBitonicTile, static_cast<hipStream_t>(stream)));
+}
+
+bos_status bos_set_tuning(const bos_tune_entry* entries, uint32_t count) {
+  if (count && !entries) return BOS_ERR_INVALID_ARG;
+  for (uint32_t i = 0; i < count; ++i) {
+    const bos_tune_entry& e = entries[i];
+    const bool zok = e.z == 0 || (e.z >= 8 && e.z <= 2048 && (e.z & (e.z - 1)) == 0);
+    if ((e.rec != 8 && e.rec != 16) || e.log2n > 40 || !zok || e.k > 12 || (e.tile && !tile_ok(e.tile)))
+      return BOS_ERR_INVALID_ARG;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.assign(entries, entries + count);
+  }
+  bos_release_cache();  // captured batches were planned with the old table
+  return BOS_OK;
+}
+
+uint32_t bos_get_tuning(bos_tune_entry* out, uint32_t cap) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const uint32_t cnt = uint32_t(g_tune.size());
+  for (uint32_t i = 0; i < cnt && i < cap && out; ++i) out[i] = g_tune[i];
+  return cnt;
 }
 
 void bos_release_cache(void) {

@@ -10,6 +10,7 @@ namespace bos {
 constexpr uint32_t kDummyTag = 0xFFFFFFFFu;  // tag of a dummy slot; real tags are labels < 2^31
 constexpr uint64_t kNoOverflow = ~0ull;      // status word when no MergeSplit overflowed
 constexpr int kMaxThreads = 512;             // threads per routing block
+constexpr uint32_t kMergeTile = 4096;        // outputs per workgroup of a merge pass
 
 // Record of BOS_REC_U32U32 (8 bytes) or BOS_REC_U64U64 (16 bytes).
 template <int R> struct RecOf;
@@ -104,7 +105,7 @@ struct SortSeg {
   uint64_t w;        // merge pass: run width
   uint64_t* split;   // merge pass: this instance's split array
   uint32_t first;    // first block (and first partition thread) of the segment in the launch
-  uint32_t count;    // 4096-record tiles of the instance
+  uint32_t count;    // blocks of the instance in the launch (tiles of the tile sort or merge)
 };
 
 // One instance's status words to initialise before its first routing pass.

@@ -59,33 +59,34 @@ __device__ __forceinline__ uint64_t merge_path(const T* A, uint64_t la, const T*
 
 // ---- register-resident tile sort and partitioned merge passes -------------
 
-constexpr uint32_t kRegTileLog = 12, kRegTile = 1u << kRegTileLog;  // 4096 records per tile
-constexpr uint32_t kRegTileThreads = kRegTile / 16;
+// Tiles of 2^TLOG records (TLOG = 10, 11 or 12), 16 records per thread.
+template <uint32_t TLOG>
+constexpr uint32_t tile_threads() { return (1u << TLOG) / 16u; }
 
-// Sort one tile of 4096 records of buf in place with the register bitonic
+// Sort one tile of 2^TLOG records of buf in place with the register bitonic
 // network of the per-bin finish (record order; slots past n sort last as the
 // maximal record).
-template <int R>
+template <int R, uint32_t TLOG>
 __device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t tile) {
   using T = typename RecOf<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   T* srec = reinterpret_cast<T*>(smem);
   T* B = static_cast<T*>(buf);
   const uint32_t lq = threadIdx.x;
-  const uint64_t base = tile * kRegTile + 16u * lq;
+  const uint64_t base = (tile << TLOG) + 16u * lq;
   ElemR<T> v[16];
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
   const LdsR<T> lds{srec};
-  bin_bitonic<kRegTileLog>(v, lds, 0u, lq, true);
+  bin_bitonic<TLOG>(v, lds, 0u, lq, true);
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e)
     if (base + e < n) B[base + e] = v[e].r;
 }
 
-template <int R>
-__global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel(void* buf, uint64_t n) {
-  tile_sort_one<R>(buf, n, blockIdx.x);
+template <int R, uint32_t TLOG>
+__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel(void* buf, uint64_t n) {
+  tile_sort_one<R, TLOG>(buf, n, blockIdx.x);
 }
 
 // Segment holding launch index x (largest s with segs[s].first <= x).
@@ -101,13 +102,14 @@ __device__ __forceinline__ uint32_t find_seg(const SortSeg* segs, uint32_t nsegs
   return lo;
 }
 
-template <int R>
-__global__ __launch_bounds__(kRegTileThreads) void tile_sort_reg_kernel_b(const SortSeg* segs, uint32_t nsegs) {
+template <int R, uint32_t TLOG>
+__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel_b(const SortSeg* segs,
+                                                                              uint32_t nsegs) {
   const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
-  tile_sort_one<R>(sg.src, sg.n, blockIdx.x - sg.first);
+  tile_sort_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first);
 }
 
-constexpr uint32_t kMTile = 4096, kMThreads = 256, kMItems = kMTile / kMThreads;
+constexpr uint32_t kMTile = kMergeTile, kMThreads = 256, kMItems = kMTile / kMThreads;
 
 // Merge-path split of output tile boundary b of one merge pass (runs of width
 // w merged in pairs): absolute start of the tile's part of the left and the
@@ -139,9 +141,36 @@ __global__ void merge_partition_kernel_b(const SortSeg* segs, uint32_t nsegs, ui
   merge_partition_one<R>(sg.src, sg.n, sg.w, sg.split, x - sg.first);
 }
 
-// One output tile of a merge pass: load the two parts into LDS, every thread
-// merges kMItems outputs (merge path inside the tile), outputs are staged in
-// LDS and written coalesced.
+// Merge kMItems outputs of the stable merge of SA[0..na) and SB[0..nb) (A wins
+// ties), starting at output dd, by a merge-path search and a serial merge.
+template <typename T>
+__device__ __forceinline__ void merge_items(const T* SA, uint32_t na, const T* SB, uint32_t nb, uint32_t dd,
+                                            T (&out)[kMItems]) {
+  uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
+  while (l < h) {
+    const uint32_t md = (l + h) >> 1;
+    if (!rec_less(SB[dd - md - 1], SA[md]))
+      l = md + 1;
+    else
+      h = md;
+  }
+  uint32_t ia = l, ib = dd - l;
+#pragma unroll
+  for (uint32_t k = 0; k < kMItems; ++k) {
+    const bool take_a = ia < na && (ib >= nb || !rec_less(SB[ib], SA[ia]));
+    const T va = SA[ia < na ? ia : 0], vb = SB[ib < nb ? ib : 0];
+    out[k] = take_a ? va : vb;
+    ia += take_a ? 1u : 0u;
+    ib += take_a ? 0u : 1u;
+  }
+}
+
+// One output tile of a merge pass: load the tile's inputs into LDS, every
+// thread merges kMItems outputs, outputs are staged in LDS and written
+// coalesced.  When run pairs (2w records) are at least a tile long, the tile
+// takes the two parts of one pair that the partition kernel found; shorter
+// pairs (first passes after a tile sort of fewer than kMTile records) lie
+// whole inside the tile, which then merges each of them.
 template <int R>
 __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uint64_t n, uint64_t w,
                                                const uint64_t* split, uint64_t b) {
@@ -151,12 +180,23 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
   const T* src = static_cast<const T*>(src_);
   T* dst = static_cast<T*>(dst_);
   const uint64_t o0 = b * kMTile;
-  const uint64_t lo = (o0 / (2 * w)) * (2 * w);
-  const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
-  const uint64_t o1 = o0 + kMTile < hi ? o0 + kMTile : hi;
-  const uint64_t a0 = split[2 * b], b0 = split[2 * b + 1];
-  const uint64_t a1 = o1 == hi ? mid : split[2 * b + 2], b1 = o1 == hi ? hi : split[2 * b + 3];
-  const uint32_t na = uint32_t(a1 - a0), nb = uint32_t(b1 - b0), cnt = na + nb;
+  const bool whole_pairs = 2 * w < kMTile;
+  uint64_t a0 = o0, b0 = o0;
+  uint32_t na = 0, nb = 0, cnt = 0;
+  if (whole_pairs) {
+    cnt = uint32_t((o0 + kMTile < n ? o0 + kMTile : n) - o0);
+    na = cnt;  // the tile is read as one contiguous range
+  } else {
+    const uint64_t lo = (o0 / (2 * w)) * (2 * w);
+    const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
+    const uint64_t o1 = o0 + kMTile < hi ? o0 + kMTile : hi;
+    a0 = split[2 * b];
+    b0 = split[2 * b + 1];
+    const uint64_t a1 = o1 == hi ? mid : split[2 * b + 2], b1 = o1 == hi ? hi : split[2 * b + 3];
+    na = uint32_t(a1 - a0);
+    nb = uint32_t(b1 - b0);
+    cnt = na + nb;
+  }
   {
     // issue every load of this thread before the first LDS store
     T in[kMItems];
@@ -175,24 +215,14 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
   const uint32_t dd = threadIdx.x * kMItems;
   T out[kMItems];
   if (dd < cnt) {
-    uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
-    const T* SA = s;
-    const T* SB = s + na;
-    while (l < h) {
-      const uint32_t md = (l + h) >> 1;
-      if (!rec_less(SB[dd - md - 1], SA[md]))
-        l = md + 1;
-      else
-        h = md;
-    }
-    uint32_t ia = l, ib = dd - l;
-#pragma unroll
-    for (uint32_t k = 0; k < kMItems; ++k) {
-      const bool take_a = ia < na && (ib >= nb || !rec_less(SB[ib], SA[ia]));
-      const T va = SA[ia < na ? ia : 0], vb = SB[ib < nb ? ib : 0];
-      out[k] = take_a ? va : vb;
-      ia += take_a ? 1u : 0u;
-      ib += take_a ? 0u : 1u;
+    if (whole_pairs) {
+      // this thread's outputs lie in one pair (2w is a multiple of kMItems)
+      const uint32_t w32 = uint32_t(w), pb = (dd / (2 * w32)) * (2 * w32);
+      const uint32_t pa = cnt - pb < w32 ? cnt - pb : w32;
+      const uint32_t pbn = cnt - pb - pa < w32 ? cnt - pb - pa : w32;
+      merge_items(s + pb, pa, s + pb + pa, pbn, dd - pb, out);
+    } else {
+      merge_items(s, na, s + na, nb, dd, out);
     }
   }
   __syncthreads();
@@ -337,32 +367,48 @@ static hipError_t allow_lds(K kernel) {
 
 uint32_t tile_lds_bytes(int rec, uint32_t ts) { return (ts + (ts >> 5)) * uint32_t(rec); }
 
+// LDS of the tile sort of 2^TLOG records (padded slots).
+template <int R, uint32_t TLOG>
+constexpr uint32_t tile_sort_lds() { return ((1u << TLOG) + (1u << TLOG) / 16u) * uint32_t(R); }
+
+template <int R, uint32_t TLOG>
+static hipError_t launch_tile_sort_t(void* buf, uint64_t n, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = allow_lds(tile_sort_reg_kernel<R, TLOG>);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const uint64_t tiles = (n + (1ull << TLOG) - 1) >> TLOG;
+  const uint32_t threads = tile_threads<TLOG>(), lds = tile_sort_lds<R, TLOG>();
+  hipLaunchKernelGGL((tile_sort_reg_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n);
+  return hipGetLastError();
+}
+
 template <int R>
 static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                     hipStream_t s, void** result) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = allow_lds(tile_sort_reg_kernel<R>);
-    if (e == hipSuccess) e = allow_lds(merge_tile_kernel<R>);
+    const hipError_t e = allow_lds(merge_tile_kernel<R>);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  (void)ts;
+  if (ts != 1024 && ts != 2048 && ts != 4096) return hipErrorInvalidValue;
   *result = buf0;
   if (n <= 1) return hipSuccess;
-  const uint64_t tiles = (n + kRegTile - 1) / kRegTile;
-  const uint32_t tile_lds = (kRegTile + (kRegTile >> 4)) * uint32_t(R);
   prof_begin(BOS_K_SORT_TILE, 0, 2 * n * R, s);
-  hipLaunchKernelGGL(tile_sort_reg_kernel<R>, dim3(uint32_t(tiles)), dim3(kRegTileThreads), tile_lds, s, buf0, n);
+  hipError_t e = ts == 4096 ? launch_tile_sort_t<R, 12>(buf0, n, s)
+                 : ts == 2048 ? launch_tile_sort_t<R, 11>(buf0, n, s)
+                              : launch_tile_sort_t<R, 10>(buf0, n, s);
   prof_end(s);
-  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* src = buf0;
   void* dst = buf1;
   uint32_t pass = 0;
   const uint64_t mtiles = (n + kMTile - 1) / kMTile;
   const uint32_t merge_lds = (kMTile + (kMTile >> 4)) * uint32_t(R);
-  for (uint64_t w = kRegTile; w < n; w *= 2) {
+  for (uint64_t w = ts; w < n; w *= 2) {
     prof_begin(BOS_K_SORT_MERGE, pass++, 2 * n * R, s);
     // boundaries 0..mtiles-1 (the end of the last tile is the end of its run pair)
     hipLaunchKernelGGL(merge_partition_kernel<R>, dim3(uint32_t((mtiles + 255) / 256)), dim3(256), 0, s, src, n, w,
@@ -382,10 +428,9 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
 
 // Number of merge passes the comparison sort runs for n records and tile ts.
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts) {
-  (void)ts;
   uint32_t c = 0;
   if (n <= 1) return 0;
-  for (uint64_t w = kRegTile; w < n; w *= 2) ++c;
+  for (uint64_t w = ts; w < n; w *= 2) ++c;
   return c;
 }
 
@@ -445,20 +490,34 @@ static hipError_t bitonic_t(const void* in, void* out, uint64_t n, void* ws, uin
   return hipMemcpyAsync(out, ws, n * R, hipMemcpyDeviceToDevice, s);
 }
 
-template <int R>
-static hipError_t batched_sort_launch_t(int kind, const SortSeg* segs, uint32_t nsegs, uint32_t total,
-                                        hipStream_t s) {
+template <int R, uint32_t TLOG>
+static hipError_t batched_tile_sort_t(const SortSeg* segs, uint32_t nsegs, uint32_t total, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = allow_lds(tile_sort_reg_kernel_b<R>);
-    if (e == hipSuccess) e = allow_lds(merge_tile_kernel_b<R>);
+    const hipError_t e = allow_lds(tile_sort_reg_kernel_b<R, TLOG>);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const uint32_t threads = tile_threads<TLOG>(), lds = tile_sort_lds<R, TLOG>();
+  hipLaunchKernelGGL((tile_sort_reg_kernel_b<R, TLOG>), dim3(total), dim3(threads), lds, s, segs, nsegs);
+  return hipGetLastError();
+}
+
+template <int R>
+static hipError_t batched_sort_launch_t(int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs,
+                                        uint32_t total, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = allow_lds(merge_tile_kernel_b<R>);
     if (e != hipSuccess) return e;
     attr = true;
   }
   if (total == 0) return hipSuccess;
   if (kind == 0) {
-    const uint32_t lds = (kRegTile + (kRegTile >> 4)) * uint32_t(R);
-    hipLaunchKernelGGL(tile_sort_reg_kernel_b<R>, dim3(total), dim3(kRegTileThreads), lds, s, segs, nsegs);
+    if (tile == 4096) return batched_tile_sort_t<R, 12>(segs, nsegs, total, s);
+    if (tile == 2048) return batched_tile_sort_t<R, 11>(segs, nsegs, total, s);
+    if (tile == 1024) return batched_tile_sort_t<R, 10>(segs, nsegs, total, s);
+    return hipErrorInvalidValue;
   } else if (kind == 1) {
     hipLaunchKernelGGL(merge_partition_kernel_b<R>, dim3((total + 255) / 256), dim3(256), 0, s, segs, nsegs, total);
   } else {
@@ -468,12 +527,13 @@ static hipError_t batched_sort_launch_t(int kind, const SortSeg* segs, uint32_t 
   return hipGetLastError();
 }
 
-// Batched comparison-sort launch: kind 0 = tile sort, 1 = merge partition,
-// 2 = merge tiles; `total` = tiles summed over the segments.
-hipError_t launch_sort_batched(int rec, int kind, const SortSeg* segs, uint32_t nsegs, uint32_t total,
-                               hipStream_t s) {
-  return rec == 8 ? batched_sort_launch_t<8>(kind, segs, nsegs, total, s)
-                  : batched_sort_launch_t<16>(kind, segs, nsegs, total, s);
+// Batched comparison-sort launch: kind 0 = tile sort (tiles of `tile`
+// records), 1 = merge partition, 2 = merge tiles; `total` = tiles summed over
+// the segments.
+hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs,
+                               uint32_t total, hipStream_t s) {
+  return rec == 8 ? batched_sort_launch_t<8>(kind, tile, segs, nsegs, total, s)
+                  : batched_sort_launch_t<16>(kind, tile, segs, nsegs, total, s);
 }
 
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s) {
