@@ -244,7 +244,8 @@ typedef enum {
   BOS_K_BITONIC_TILE = 7, /* bitonic baseline: local phases */
   BOS_K_BITONIC_GLOBAL = 8,
   BOS_K_BITONIC_TAIL = 9,
-  BOS_K_OTHER = 10
+  BOS_K_OTHER = 10,
+  BOS_K_STRIP = 11        /* scan of the bin loads and strip after a split last pass */
 } bos_kernel_kind;
 typedef struct {
   uint32_t kind;     /* bos_kernel_kind */

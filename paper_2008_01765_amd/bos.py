@@ -67,7 +67,8 @@ class LaunchTime(C.Structure):
 
 
 KERNEL_KINDS = {1: "route_first", 2: "route_mid", 3: "route_last", 4: "route_single", 5: "sort_tile",
-                6: "sort_merge", 7: "bitonic_tile", 8: "bitonic_global", 9: "bitonic_tail", 10: "other"}
+                6: "sort_merge", 7: "bitonic_tile", 8: "bitonic_global", 9: "bitonic_tail", 10: "other",
+                11: "strip"}
 
 EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "bos_batched_workspace_bytes",
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",

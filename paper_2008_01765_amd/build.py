@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbos.so")
-SOURCES = (["orp_kernels.hip", "route_kernels.hip", "sort_kernels.hip", "bos_api.hip"]
+SOURCES = (["orp_kernels.hip", "route_kernels.hip", "sort_kernels.hip", "strip_kernels.hip", "bos_api.hip"]
            + ["route_r%d_z%d.hip" % (r, z) for r in (8, 16) for z in range(4, 12)])
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

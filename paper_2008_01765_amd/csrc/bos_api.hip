@@ -25,7 +25,9 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long 
 hipError_t launch_labels(uint32_t* out, uint64_t n, uint32_t L, uint64_t seed, uint32_t attempt, hipStream_t s);
 hipError_t launch_pass(int rec, const PassArgs& a, bool first, bool last, uint32_t nblocks, hipStream_t s);
 hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
-                        hipStream_t s);
+                        hipStream_t s, bool split);
+hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
+                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, hipStream_t s);
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                   hipStream_t s, void** result);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
@@ -103,7 +105,8 @@ struct Plan {
   int rec = 8;
   uint32_t Z = 512, lz = 9, L = 0, P = 1, k = 0, tile = kDefaultTile;
   uint32_t klev[kMaxPasses] = {0}, lev0[kMaxPasses] = {0};
-  size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_scan = 0, off_split = 0, total = 0;
+  size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_scan = 0, off_split = 0, off_loads = 0;
+  size_t total = 0;
   uint32_t nblocks_last = 1;
   bool generic = false;
 };
@@ -280,6 +283,8 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   off = align_up(off + 16 + size_t(pl->nblocks_last) * 8);
   pl->off_split = off;   // merge-path splits of the comparison sort
   off = align_up(off + comparison_sort_split_bytes(n));
+  pl->off_loads = off;   // split last pass: real count of every final bin
+  off = align_up(off + size_t(B) * 4);
   pl->total = off;
   return BOS_OK;
 }
@@ -314,9 +319,16 @@ bool use_route_kernel(const Plan& pl, uint32_t t) {
   return !pl.generic && pl.lz >= 4 && pl.lz <= 11 && pl.klev[t] >= 1;
 }
 
+// The split form of the last pass (persistent last pass that leaves the sorted
+// bins in slot array (P + 1) & 1, then scan + strip) applies to bos_sort's
+// plans of two or more passes routed by the register-resident kernel.
+bool split_last(const Plan& pl) { return pl.P >= 2 && pl.L > 0 && use_route_kernel(pl, pl.P - 1); }
+
 // Enqueue one attempt of the routing phase; `out` receives the stripped bins.
+// split: last pass in split form (requires split_last(pl); `out` must not be
+// slot array (P + 1) & 1, which holds the bins until the strip).
 hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t seed, uint32_t attempt,
-                           uint32_t fin, char* ws, hipStream_t s, int stop_after = -1) {
+                           uint32_t fin, char* ws, hipStream_t s, int stop_after = -1, bool split = false) {
   unsigned long long* status = reinterpret_cast<unsigned long long*>(ws + pl.off_status);
   hipError_t e = launch_fill_u64(status, 2 + pl.nblocks_last, 0, s);
   if (e != hipSuccess) return e;
@@ -346,6 +358,8 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
     a.klev = pl.klev[t];
     a.attempt = attempt;
     a.fin = fin;
+    const bool split_pass = split && last;
+    if (split_pass) a.loads = reinterpret_cast<uint32_t*>(ws + pl.off_loads);
     const uint64_t slot_bytes = pl.B * pl.Z * (uint64_t(pl.rec) + 4), rec_bytes = pl.n * pl.rec;
     const uint32_t kind = first && last ? BOS_K_ROUTE_SINGLE
                           : first       ? BOS_K_ROUTE_FIRST
@@ -355,11 +369,17 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
     prof_begin(kind, t, bytes, s);
     const uint32_t nitems = uint32_t(pl.B >> pl.klev[t]);
     if (use_route_kernel(pl, t))
-      e = launch_route(pl.rec, a, first, last, nitems, num_cus(), s);
+      e = launch_route(pl.rec, a, first, last, nitems, num_cus(), s, split_pass);
     else
       e = launch_pass(pl.rec, a, first, last, nitems, s);
     prof_end(s);
     if (e != hipSuccess) return e;
+    if (split_pass) {
+      prof_begin(BOS_K_STRIP, 0, 2 * rec_bytes, s);
+      e = launch_strip(pl.rec, a.rec_out, a.loads, a.scan, out, pl.n, nitems, pl.klev[t], pl.lz, s);
+      prof_end(s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -382,11 +402,11 @@ void fill_report(bos_report* rep, const Plan& pl, uint32_t attempts, uint64_t ov
 // Runs the routing phase with the retry loop; *attempts_out / *ovf_out report.
 bos_status run_routing(const Plan& pl, const bos_params& q, const void* in, void* out, uint32_t fin, char* ws,
                        hipStream_t s, uint32_t* attempts_out, uint64_t* ovf_out, uint32_t first_attempt = 0,
-                       uint64_t prev_ovf = kNoOverflow) {
+                       uint64_t prev_ovf = kNoOverflow, bool split = false) {
   uint64_t last_ovf = prev_ovf;
   const uint32_t tries = (q.flags & BOS_SYNC) ? q.max_retries + 1 : 1;
   for (uint32_t att = first_attempt; att < tries; ++att) {
-    hipError_t e = enqueue_routing(pl, in, out, q.seed, att, fin, ws, s);
+    hipError_t e = enqueue_routing(pl, in, out, q.seed, att, fin, ws, s, -1, split);
     if (e != hipSuccess) return BOS_ERR_HIP;
     *attempts_out = att + 1;
     if (!(q.flags & BOS_SYNC)) {
@@ -822,17 +842,20 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
   if (!ws || ws_bytes < pl.total) return BOS_ERR_WORKSPACE;
   char* w = static_cast<char*>(ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // The comparison sort ping-pongs between `out` and slot array 0 (free once
-  // the routing phase is over); the routing output goes where the sort must
-  // start so that the result lands in `out`.
+  // The comparison sort ping-pongs between `out` and a free region of the
+  // workspace; the routing output goes where the sort must start so that the
+  // result lands in `out`.  The free region: with the split last pass, the
+  // two tag arrays (2 B Z 4 >= n R bytes; the bins sit in slot array
+  // (P + 1) & 1 until the strip); otherwise slot array (P + 1) & 1 itself (the
+  // last pass reads slot array P & 1).
   const uint32_t passes = comparison_sort_passes(n, pl.tile);
-  // the last routing pass reads slot array P & 1; the other one is free
-  void* tmp = w + pl.off_rec[(pl.P + 1) & 1];
+  const bool split = split_last(pl);
+  void* tmp = split ? static_cast<void*>(w + pl.off_tag[0]) : static_cast<void*>(w + pl.off_rec[(pl.P + 1) & 1]);
   void* start = (passes % 2 == 0) ? out : tmp;
   void* other = (passes % 2 == 0) ? tmp : out;
   uint32_t attempts = 0;
   uint64_t ovf = kNoOverflow;
-  st = run_routing(pl, q, in, start, 1, w, s, &attempts, &ovf);
+  st = run_routing(pl, q, in, start, 1, w, s, &attempts, &ovf, 0, kNoOverflow, split);
   if (st != BOS_OK) {
     fill_report(rep, pl, attempts, ovf, 0);
     return st;
@@ -1165,7 +1188,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       const uint32_t lz = kv.first % 16u;
       const RouteGroup& g = kv.second;
       if (g.args.size() == 1)  // one job: the persistent kernel of the single-sort path
-        e = launch_route(R, g.args[0], (m & 1) != 0, (m & 2) != 0, g.items0, num_cus(), s);
+        e = launch_route(R, g.args[0], (m & 1) != 0, (m & 2) != 0, g.items0, num_cus(), s, false);
       else
         e = launch_route_batched(R, lz, (m & 1) != 0, (m & 2) != 0, reinterpret_cast<const PassArgs*>(dtab + g.o_args),
                                  reinterpret_cast<const uint32_t*>(dtab + g.o_starts), uint32_t(g.args.size()),

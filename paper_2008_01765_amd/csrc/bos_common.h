@@ -95,6 +95,8 @@ struct PassArgs {
   uint32_t level0, klev;      // first level of this pass, levels in this pass
   uint32_t attempt;
   uint32_t fin;               // last pass: 0 = random permutation of each bin, 1 = sort each bin
+  uint32_t pad;
+  uint32_t* loads;            // split last pass: real count of every final bin
 };
 
 // One instance of a batched comparison-sort launch (tile sort or merge pass).

@@ -357,29 +357,25 @@ __device__ __forceinline__ void bin_bitonic(E (&v)[16], const V& lds, uint32_t b
   bitonic_phase<LZ, 1>(v, lds, bl);
 }
 
-// Finish of the last pass: sort (or randomly permute) every bin, then strip
-// the dummies and write the bins' reals to their place in the output, found
-// with a decoupled look-back over the blocks (block index = ticket order).
-template <int R, int LZ>
-__device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uint32_t klev,
-                                            typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
-                                            uint16_t* saux, uint32_t* sload, uint32_t* soff) {
+// Per-bin finish of the last pass (Section 3.2): every final bin (LDS bucket
+// S, padded slots) is sorted in record order with its dummies (maximal
+// record) last, and for fin == 0 then permuted uniformly: the p-th real of
+// global bin gb gets the key r(gb*Z + p), word (g mod 4) of Philox block g/4
+// with key (seed, 1), and the bin is sorted by (key, p).  On return outr holds
+// this lane's 16 slots of its bin (slots 16 lq .. 16 lq + 15) and `load` the
+// bin's real count; reals occupy the bin's first `load` slots.  FIN: 0 =
+// choose by a.fin at run time, 1 = sort only, 2 = sort and permute.
+template <int R, int LZ, int FIN>
+__device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint32_t klev,
+                                          typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
+                                          uint16_t* saux, const uint32_t* sload, typename RecOf<R>::T (&outr)[16],
+                                          uint32_t* load_out) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, ZP = Z + (Z >> 4), HL = Z >> 4;
   const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
   const bool active = tid < (m >> 4);
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   const uint32_t bbase = S * ZP;
-  // The bin loads (sload, written by the last level) are known before the
-  // bins are sorted: publish the block's aggregate now so that later blocks'
-  // look-back does not wait for this block's sort.
-  uint64_t agg = 0;
-  if (tid == 0) {
-    for (uint32_t b = 0; b < NB; ++b) agg += sload[b];
-    __hip_atomic_store(&a.scan[blk], ((blk == 0 ? 2ull : 1ull) << 62) | agg, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
-
   // record order, dummies (maximal record) last
   const LdsR<T> lr{srec};
   ElemR<T> v[16];
@@ -390,12 +386,10 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
   }
   bin_bitonic<LZ>(v, lr, bbase, lq, active);
   const uint32_t load = active ? sload[S] : 0u;
-
-  T outr[16];
-  if (a.fin == 0) {
-    // random permutation: the p-th real (record order) of global bin gb gets
-    // key r(gb*Z + p), word (g mod 4) of Philox block g/4 with key (seed, 1)
-    const uint64_t gb = uint64_t(blk) * NB + brev_k(S, klev);
+  *load_out = load;
+  const bool permute = FIN == 2 || (FIN == 0 && a.fin == 0);
+  if (FIN != 1 && permute) {
+    const uint64_t gb = blk * NB + brev_k(S, klev);
     ElemRK<T> w[16];
 #pragma unroll
     for (uint32_t e4 = 0; e4 < 4; ++e4) {
@@ -418,6 +412,68 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
 #pragma unroll
     for (uint32_t e = 0; e < 16; ++e) outr[e] = v[e].r;
   }
+}
+
+// Last pass, split form: after the per-bin finish, global bin gb keeps its
+// reals in slots gb*Z .. gb*Z + load - 1 of rec_out, its real count in
+// loads[gb] and the block's total in scan[blk]; a scan and a strip kernel then
+// concatenate the bins (the addresses of both depend on the loads only, which
+// the method reveals).
+template <int R, int LZ, int FIN>
+__device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, uint32_t klev,
+                                             typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
+                                             uint16_t* saux, const uint32_t* sload) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t Z = 1u << LZ, HL = Z >> 4;
+  const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
+  const bool active = tid < (m >> 4);
+  const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
+  if (tid == 0) {
+    uint64_t agg = 0;
+    for (uint32_t b = 0; b < NB; ++b) agg += sload[b] < Z ? sload[b] : Z;
+    a.scan[blk] = agg;
+  }
+  T outr[16];
+  uint32_t load = 0;
+  sort_bins<R, LZ, FIN>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
+  if (active) {
+    // a bin holds at most Z reals (an overflowing attempt is discarded)
+    const uint32_t kept = load < Z ? load : Z;
+    const uint64_t gb = uint64_t(blk) * NB + brev_k(S, klev);
+    T* BO = static_cast<T*>(a.rec_out);
+    if (lq == 0) a.loads[gb] = kept;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint32_t p = 16u * lq + e;
+      if (p < kept) BO[(gb << LZ) + p] = outr[e];
+    }
+  }
+}
+
+// Last pass, fused form: sort (or randomly permute) every bin, then strip the
+// dummies and write the bins' reals to their place in the output, found with
+// a decoupled look-back over the blocks (block index = ticket order).
+template <int R, int LZ>
+__device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uint32_t klev,
+                                            typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
+                                            uint16_t* saux, uint32_t* sload, uint32_t* soff) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t Z = 1u << LZ, HL = Z >> 4;
+  const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
+  const bool active = tid < (m >> 4);
+  const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
+  // The bin loads (sload, written by the last level) are known before the
+  // bins are sorted: publish the block's aggregate now so that later blocks'
+  // look-back does not wait for this block's sort.
+  uint64_t agg = 0;
+  if (tid == 0) {
+    for (uint32_t b = 0; b < NB; ++b) agg += sload[b];
+    __hip_atomic_store(&a.scan[blk], ((blk == 0 ? 2ull : 1ull) << 62) | agg, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  T outr[16];
+  uint32_t load = 0;
+  sort_bins<R, LZ, 0>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
   // look back for the block's output offset (reals occupy the first slots of
   // every sorted bin).  Wave 0 inspects 64 predecessors per step: it sums
   // their aggregates back to the nearest one whose inclusive prefix is known.
@@ -469,14 +525,21 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
   }
 }
 
-// R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last.
+// R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last,
+// bit 2 = split form of the last pass (persistent, bins sorted and written to
+// rec_out; bos_sort only).
 // Body of one routing launch.  BATCH = false: a persistent workgroup walks
 // over items blockIdx.x, + gridDim.x, ... (last pass: tickets).  BATCH = true:
 // the workgroup runs the single item `item0` of one instance of a batch.
 template <int R, int LZ, int MODE, bool BATCH>
 __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, uint32_t item0) {
   using T = typename RecOf<R>::T;
-  constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0;
+  constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0, SPLIT = (MODE & 4) != 0;
+  static_assert(!SPLIT || (LAST && !FIRST && !BATCH), "the split form is a persistent last pass");
+  // the split form sorts its bins (bos_sort); bos_orp's permuting finish
+  // keeps the fused form, whose one-block-per-workgroup launch has the
+  // registers it needs
+  constexpr int SPLIT_FIN = 1;
   constexpr uint32_t Z = 1u << LZ, LQ = LZ + 1, TPM = 1u << (LQ - 4), ZP = Z + (Z >> 4);
   constexpr bool HAS_B = LQ > 6;
   constexpr uint32_t HALF_LANES = TPM / 2;  // lanes per bucket in layout A
@@ -857,7 +920,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       finish_load(item0, tv);
     }
     process(item0);
-  } else if constexpr (!LAST) {
+  } else if constexpr (!LAST || SPLIT) {
     // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...
     uint32_t item = item0;
     if (item >= nitems) return;
@@ -874,6 +937,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         if (has_next && !(FIRST && !aligned)) issue_load(next, pf_rv, pf_tv);
       }
       process(item);
+      if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN>(a, item, klev, srec, stag, srhi, saux, sload);
       if (!has_next) break;
       item = next;
       lds_barrier();  // LDS of the previous block is no longer read

@@ -21,10 +21,13 @@ hipError_t launch_route_r16_z9(const PassArgs& a, int mode, uint32_t nitems, uin
 hipError_t launch_route_r16_z10(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
 hipError_t launch_route_r16_z11(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s);
 
-// Routing pass with the register-resident kernel (Z in [16, 2048], klev >= 1).
+// Routing pass with the register-resident kernel (Z in [16, 2048], klev >= 1);
+// split: the split form of a last pass that is not also the first (sorting
+// finish only).
 hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
-                        hipStream_t s) {
-  const int mode = (first ? 1 : 0) | (last ? 2 : 0);
+                        hipStream_t s, bool split) {
+  if (split && (first || !last || a.fin == 0)) return hipErrorInvalidValue;
+  const int mode = (first ? 1 : 0) | (last ? 2 : 0) | (split ? 4 : 0);
   if (rec == 8) {
     switch (a.lz) {
     case 4: return launch_route_r8_z4(a, mode, nitems, grid, s);

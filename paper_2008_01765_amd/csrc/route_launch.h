@@ -27,7 +27,10 @@ hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hip
     occ_blocks = uint32_t(nb);
   }
   const uint32_t persistent = grid * occ_blocks;
-  const uint32_t g = (MODE & 2) ? nitems : (persistent < nitems ? persistent : nitems);
+  // the fused last pass runs one workgroup per block (ticket order); every
+  // other pass is a persistent walk over the blocks
+  const bool ticketed = (MODE & 2) && !(MODE & 4);
+  const uint32_t g = ticketed ? nitems : (persistent < nitems ? persistent : nitems);
   hipLaunchKernelGGL((route_kernel<R, LZ, MODE>), dim3(g), dim3(threads), lds, s, a, nitems);
   return hipGetLastError();
 }
@@ -65,6 +68,7 @@ hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t
     case 0: return launch_route_t<R, LZ, 0>(a, nitems, grid, s);
     case 1: return launch_route_t<R, LZ, 1>(a, nitems, grid, s);
     case 2: return launch_route_t<R, LZ, 2>(a, nitems, grid, s);
+    case 6: return launch_route_t<R, LZ, 6>(a, nitems, grid, s);
     default: return launch_route_t<R, LZ, 3>(a, nitems, grid, s);
   }
 }

@@ -227,3 +227,24 @@ def test_duplicate_keys_workload_orp_sampled_bins():
         r = cf.shuffle_keys(1, att, int(b) * Z, idx.size)
         want = a[ordered[np.lexsort((np.arange(idx.size), r))]]
         np.testing.assert_array_equal(o[off[b]:off[b + 1]], want)
+
+
+def test_sort_uses_split_last_pass_orp_fused():
+    # bos_sort of a multi-pass plan runs the split last pass (persistent last
+    # pass, then scan + strip); bos_orp keeps the fused last pass.  Both stay
+    # bit-exact against the oracle.
+    import oracle
+    oracle.build(force=False)
+    h = inputs.records(1 << 17, 8, 77)
+    t = bos.from_numpy(h)
+    bos.profile_enable(True)
+    bos.profile_read()
+    out = bos.sort(t, seed=5, min_security_bits=0)
+    kinds_sort = [l["kind"] for l in bos.profile_read()]
+    orp = bos.orp(t, seed=5, min_security_bits=0)
+    kinds_orp = [l["kind"] for l in bos.profile_read()]
+    bos.profile_enable(False)
+    assert "strip" in kinds_sort and "route_last" in kinds_sort
+    assert "strip" not in kinds_orp and "route_last" in kinds_orp
+    np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(h))
+    np.testing.assert_array_equal(bos.to_numpy(orp), oracle.orp(h, 5)["out"])
