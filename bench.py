@@ -51,6 +51,10 @@ def parse():
                     help="requests of the serving workload (log-uniform 2^12..2^24, 16 B, Poisson); 0 skips")
     ap.add_argument("--serving-load", type=float, default=0.7,
                     help="offered load as a fraction of the sequential server's capacity")
+    ap.add_argument("--sweep-steps", type=int, default=2,
+                    help="steps per (Z, k) point of the n=2^28 sweep; 0 skips the sweep")
+    ap.add_argument("--sweep-seeds", type=int, default=100,
+                    help="ORP seeds per Z for the overflow-retry count")
     ap.add_argument("--tuning", default="",
                     help="tuning table for the batched and serving legs (default: the stored table)")
     return ap.parse_args()
@@ -78,6 +82,75 @@ def traffic_from_profile(kind, config_tag):
     if not m_src or not m_b or m_src.group(1) != kernel_source_digest():
         return None
     return float(m_b.group(1))
+
+
+def per_kind(launches, steps):
+    kinds = {}
+    for l in launches:
+        d = kinds.setdefault(l["kind"], [0, 0.0, 0])
+        d[0] += 1
+        d[1] += l["ms"]
+        d[2] += l["bytes"]
+    return {k: {"ms_per_step": round(v[1] / steps, 3), "avg_ms": round(v[1] / v[0], 4),
+                "GB/s": round(v[2] / v[1] / 1e6, 1), "frac_of_peak": round(v[2] / v[1] / 1e6 / HBM_PEAK_GBS, 4)}
+            for k, v in kinds.items()}
+
+
+def bench_sweep(args, torch, bos, x, out):
+    """Z in {256, 512, 1024} x k in {2, 3, 4} at the resident input: ms per
+    bos_sort and per bos_orp, per-pass GB/s; then bos_orp over seeds 1..S per Z
+    with the retries they needed.  Z = 256 is below the 80-bit floor at this n
+    (Lemma 3.2 gives about 2^-36), so the sweep runs with the floor off."""
+    stream = torch.cuda.current_stream()
+    res = {"points": [], "overflow": []}
+    n = x.shape[0]
+    for z in (256, 512, 1024):
+        for k in (2, 3, 4):
+            pt = {"z": z, "k": k}
+            for mode, fn in (("sort", bos.sort), ("orp", bos.orp)):
+                try:
+                    fn(x, seed=args.seed, z=z, k=k, out=out, min_security_bits=0)
+                except bos.BosError as e:
+                    pt[mode] = {"error": str(e)}
+                    continue
+                torch.cuda.synchronize()
+                bos.profile_enable(True)
+                bos.profile_read()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                reps = []
+                for _ in range(args.sweep_steps):
+                    reps.append(fn(x, seed=args.seed, z=z, k=k, out=out, min_security_bits=0, report=True)[1])
+                e1.record(stream)
+                torch.cuda.synchronize()
+                kinds = per_kind(bos.profile_read(), args.sweep_steps)
+                bos.profile_enable(False)
+                ms = e0.elapsed_time(e1) / args.sweep_steps
+                pt[mode] = {"ms": round(ms, 3), "Melem/s": round(n / ms / 1e3, 1), "passes": reps[-1]["passes"],
+                            "k_used": reps[-1]["k"], "kernels": kinds}
+            res["points"].append(pt)
+            print("sweep: %s" % json.dumps({"z": z, "k": k, "sort_ms": pt.get("sort", {}).get("ms"),
+                                            "orp_ms": pt.get("orp", {}).get("ms")}), file=sys.stderr, flush=True)
+    for z in (256, 512, 1024):
+        retries = failed = 0
+        t0 = time.perf_counter()
+        for sd in range(1, args.sweep_seeds + 1):
+            try:
+                _, rep = bos.orp(x, seed=sd, z=z, out=out, min_security_bits=0, max_retries=3, report=True)
+                retries += rep["attempts"] - 1
+            except bos.BosError:
+                failed += 1
+        res["overflow"].append({"z": z, "seeds": args.sweep_seeds, "retries": retries, "failed": failed,
+                                "log2_eps_bound": round(log2_eps(n, z), 1), "s": round(time.perf_counter() - t0, 1)})
+    return res
+
+
+def log2_eps(n, z):
+    L = 0
+    while (1 << L) * z < 2 * n:
+        L += 1
+    import math
+    return L + math.log2(L) - z / (6.0 * math.log(2.0)) if L else float("-inf")
 
 
 def install_tuning(args, bos):
@@ -324,6 +397,10 @@ def main():
                "speedup_of_bucket_sort": round(bms / ms_per_step, 3)}
         del bout
 
+    sweep = None
+    if args.sweep_steps > 0 and args.mode == "sort" and args.log2n == 28 and args.rec == 8:
+        sweep = bench_sweep(args, torch, bos, x, out)
+
     del x, out
     bos.release_workspaces()
     torch.cuda.empty_cache()
@@ -370,7 +447,7 @@ def main():
                    "n": n, "rec_bytes": args.rec, "z": rep["z"], "k": rep["k"], "levels": rep["levels"],
                    "passes": rep["passes"], "tile": rep["tile"], "parallelism": "1 GPU"},
         "attempts": rep["attempts"], "correct": ok,
-        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "batched": batched, "serving": served,
+        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "batched": batched, "serving": served, "sweep": sweep,
         "kernels": kern,
         "kernel_sources": kernel_source_digest(),
     }

@@ -236,7 +236,9 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   pl->L = L;
   const uint32_t kmid = max_klev(rec, Z, false), klast = max_klev(rec, Z, shuffle_last);
   if (kmid == 0 || klast == 0) return BOS_ERR_UNSUPPORTED;
-  const uint32_t kreq = q.k ? q.k : (tuned && te.k && te.z == Z ? te.k : 4u);
+  // default: 3 levels per pass (a block of 2^3 Z slots leaves LDS for three
+  // workgroups per CU at Z = 512, which outruns fewer, larger passes)
+  const uint32_t kreq = q.k ? q.k : (tuned && te.k && te.z == Z ? te.k : 3u);
   const uint32_t k = std::min(kreq, kmid);
   pl->k = k;
   pl->tile = q.tile ? q.tile : (tuned && te.tile ? te.tile : kDefaultTile);

@@ -364,8 +364,9 @@ __device__ __forceinline__ void bin_bitonic(E (&v)[16], const V& lds, uint32_t b
 // with key (seed, 1), and the bin is sorted by (key, p).  On return outr holds
 // this lane's 16 slots of its bin (slots 16 lq .. 16 lq + 15) and `load` the
 // bin's real count; reals occupy the bin's first `load` slots.  FIN: 0 =
-// choose by a.fin at run time, 1 = sort only, 2 = sort and permute.
-template <int R, int LZ, int FIN>
+// choose by a.fin at run time, 1 = sort only, 2 = sort and permute.  FULL:
+// every lane of the workgroup holds slots (no lane guards).
+template <int R, int LZ, int FIN, bool FULL>
 __device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint32_t klev,
                                           typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
                                           uint16_t* saux, const uint32_t* sload, typename RecOf<R>::T (&outr)[16],
@@ -373,7 +374,7 @@ __device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint3
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, ZP = Z + (Z >> 4), HL = Z >> 4;
   const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
-  const bool active = tid < (m >> 4);
+  const bool active = FULL || tid < (m >> 4);
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   const uint32_t bbase = S * ZP;
   // record order, dummies (maximal record) last
@@ -419,14 +420,14 @@ __device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint3
 // loads[gb] and the block's total in scan[blk]; a scan and a strip kernel then
 // concatenate the bins (the addresses of both depend on the loads only, which
 // the method reveals).
-template <int R, int LZ, int FIN>
+template <int R, int LZ, int FIN, bool FULL>
 __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, uint32_t klev,
                                              typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
                                              uint16_t* saux, const uint32_t* sload) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, HL = Z >> 4;
   const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
-  const bool active = tid < (m >> 4);
+  const bool active = FULL || tid < (m >> 4);
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   if (tid == 0) {
     uint64_t agg = 0;
@@ -435,7 +436,7 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
   }
   T outr[16];
   uint32_t load = 0;
-  sort_bins<R, LZ, FIN>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
+  sort_bins<R, LZ, FIN, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
   if (active) {
     // a bin holds at most Z reals (an overflowing attempt is discarded)
     const uint32_t kept = load < Z ? load : Z;
@@ -453,14 +454,14 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
 // Last pass, fused form: sort (or randomly permute) every bin, then strip the
 // dummies and write the bins' reals to their place in the output, found with
 // a decoupled look-back over the blocks (block index = ticket order).
-template <int R, int LZ>
+template <int R, int LZ, bool FULL>
 __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uint32_t klev,
                                             typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
                                             uint16_t* saux, uint32_t* sload, uint32_t* soff) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, HL = Z >> 4;
   const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
-  const bool active = tid < (m >> 4);
+  const bool active = FULL || tid < (m >> 4);
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   // The bin loads (sload, written by the last level) are known before the
   // bins are sorted: publish the block's aggregate now so that later blocks'
@@ -473,7 +474,7 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
   }
   T outr[16];
   uint32_t load = 0;
-  sort_bins<R, LZ, 0>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
+  sort_bins<R, LZ, 0, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
   // look back for the block's output offset (reals occupy the first slots of
   // every sorted bin).  Wave 0 inspects 64 predecessors per step: it sums
   // their aggregates back to the nearest one whose inclusive prefix is known.
@@ -527,7 +528,8 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
 
 // R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last,
 // bit 2 = split form of the last pass (persistent, bins sorted and written to
-// rec_out; bos_sort only).
+// rec_out; bos_sort only), bit 4 = the launch has exactly Z 2^klev / 16 lanes
+// (all of them hold slots, so no lane needs a guard).
 // Body of one routing launch.  BATCH = false: a persistent workgroup walks
 // over items blockIdx.x, + gridDim.x, ... (last pass: tickets).  BATCH = true:
 // the workgroup runs the single item `item0` of one instance of a batch.
@@ -535,6 +537,7 @@ template <int R, int LZ, int MODE, bool BATCH>
 __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, uint32_t item0) {
   using T = typename RecOf<R>::T;
   constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0, SPLIT = (MODE & 4) != 0;
+  constexpr bool FULL = (MODE & 16) != 0;  // every lane holds slots: no lane guards
   static_assert(!SPLIT || (LAST && !FIRST && !BATCH), "the split form is a persistent last pass");
   // the split form sorts its bins (bos_sort); bos_orp's permuting finish
   // keeps the fused form, whose one-block-per-workgroup launch has the
@@ -559,7 +562,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint64_t n = a.n, B = a.buckets;
   const uint32_t L = a.levels, i0 = a.level0;
-  const bool active = tid < (m >> 4);
+  const bool active = FULL || tid < (m >> 4);
   const uint32_t ms = active ? tid / TPM : 0u, lt = active ? tid % TPM : 0u;
   const T* RI = static_cast<const T*>(a.rec_in);
   const T* X = static_cast<const T*>(a.x_in);
@@ -937,7 +940,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         if (has_next && !(FIRST && !aligned)) issue_load(next, pf_rv, pf_tv);
       }
       process(item);
-      if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN>(a, item, klev, srec, stag, srhi, saux, sload);
+      if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item, klev, srec, stag, srhi, saux, sload);
       if (!has_next) break;
       item = next;
       lds_barrier();  // LDS of the previous block is no longer read
@@ -971,7 +974,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     }
     process(blk);
     // every final bin (LDS bucket S) now sits in LDS with padded slots
-    finish_bins<R, LZ>(a, blk, klev, srec, stag, srhi, saux, sload, soff);
+    finish_bins<R, LZ, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, soff);
   }
   (void)nitems;
 }

@@ -64,12 +64,20 @@ hipError_t launch_route_bm(const PassArgs* segs, const uint32_t* blk_start, uint
 
 template <int R, int LZ>
 hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
-  switch (mode) {
+  // blocks of at least 1024 slots fill whole waves: the unguarded kernels
+  const bool full = ((uint32_t(1u << LZ) << a.klev) >> 4) >= 64u;
+  switch (mode | (full ? 16 : 0)) {
     case 0: return launch_route_t<R, LZ, 0>(a, nitems, grid, s);
     case 1: return launch_route_t<R, LZ, 1>(a, nitems, grid, s);
     case 2: return launch_route_t<R, LZ, 2>(a, nitems, grid, s);
+    case 3: return launch_route_t<R, LZ, 3>(a, nitems, grid, s);
     case 6: return launch_route_t<R, LZ, 6>(a, nitems, grid, s);
-    default: return launch_route_t<R, LZ, 3>(a, nitems, grid, s);
+    case 16: return launch_route_t<R, LZ, 16>(a, nitems, grid, s);
+    case 17: return launch_route_t<R, LZ, 17>(a, nitems, grid, s);
+    case 18: return launch_route_t<R, LZ, 18>(a, nitems, grid, s);
+    case 19: return launch_route_t<R, LZ, 19>(a, nitems, grid, s);
+    case 22: return launch_route_t<R, LZ, 22>(a, nitems, grid, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
