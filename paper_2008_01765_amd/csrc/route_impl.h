@@ -17,9 +17,10 @@
 //     remaining stages pair registers again.  Each level therefore moves the
 //     data through LDS twice: A -> B, and B -> next level's A (whose MergeSplits
 //     pair other buckets).
-//   * Blocks are persistent: a workgroup walks over several blocks of buckets
-//     and issues the HBM loads of its next block before computing the current
-//     one; barriers wait for LDS traffic only, so those loads stay in flight.
+//   * Blocks are persistent: a workgroup walks over several blocks of buckets,
+//     and several workgroups share a CU (three at 2^3 Z = 4096 slots of 8-byte
+//     records), so one workgroup's HBM loads overlap the others' networks.
+//     Barriers wait for LDS traffic only.
 //
 // Obliviousness: every HBM and LDS address is a function of (n, Z, klev,
 // level, block, lane, register) only; labels and records steer register
@@ -577,10 +578,6 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   const uint32_t sb_load = 16u * (lt % HALF_LANES);
   T rv[16];
   uint32_t tv[16];
-  // 16-byte records leave no registers for a second block: no prefetch there
-  constexpr bool PREFETCH = R == 8;
-  T pf_rv[PREFETCH ? 16 : 1];
-  uint32_t pf_tv[PREFETCH ? 16 : 1];
 
   auto issue_load = [&](uint32_t item, T* dr, uint32_t* dt) {
     const uint64_t r = uint64_t(item) & ((1ull << i0) - 1ull), h = uint64_t(item) >> i0;
@@ -924,7 +921,11 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     }
     process(item0);
   } else if constexpr (!LAST || SPLIT) {
-    // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...
+    // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...  The
+    // next block's loads are issued after the current one is done: with no
+    // prefetch registers a pass runs three workgroups per CU at 2^3 Z slots
+    // per block, and their interleaving hides the loads better than a
+    // register prefetch with fewer workgroups did.
     uint32_t item = item0;
     if (item >= nitems) return;
     if (FIRST && !aligned) {
@@ -936,9 +937,6 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     for (;;) {
       const uint32_t next = item + gridDim.x;
       const bool has_next = next < nitems;
-      if constexpr (PREFETCH) {
-        if (has_next && !(FIRST && !aligned)) issue_load(next, pf_rv, pf_tv);
-      }
       process(item);
       if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item, klev, srec, stag, srhi, saux, sload);
       if (!has_next) break;
@@ -947,15 +945,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       if (FIRST && !aligned) {
         staged_first_load(item);
       } else {
-        if constexpr (PREFETCH) {
-#pragma unroll
-          for (uint32_t e = 0; e < 16; ++e) {
-            rv[e] = pf_rv[e];
-            tv[e] = pf_tv[e];
-          }
-        } else {
-          issue_load(item, rv, tv);
-        }
+        issue_load(item, rv, tv);
         finish_load(item, tv);
       }
     }
