@@ -65,8 +65,9 @@ typedef struct {
                                  paper's choice) */
   uint32_t k;                 /* butterfly levels fused per pass; 0 = the tuning
                                  table's, else the planner's choice (3) */
-  uint32_t tile;              /* records per tile of the final sort: 1024, 2048 or
-                                 4096; 0 = the tuning table's, else 4096 */
+  uint32_t tile;              /* records per tile of the final sort: 1024, 2048,
+                                 4096, 8192 or (8-byte records) 16384; 0 = the
+                                 tuning table's, else 4096 */
   uint32_t max_retries;       /* extra attempts after an overflow (default 3) */
   uint32_t min_security_bits; /* reject Z when log2(B log2 B e^(-Z/6)) > -bits;
                                  0 disables the check (default 80) */
@@ -180,7 +181,7 @@ bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, 
 
 /* One autotuner result: for records of `rec` bytes and n in size class
  * `log2n` (the smallest c with 2^c >= n), use bucket capacity z, k levels per
- * pass and comparison-sort tile `tile` (1024, 2048 or 4096).  A zero field
+ * pass and comparison-sort tile `tile` (as in bos_params).  A zero field
  * leaves the library default (Z = 512, k = 3, tile = 4096). */
 typedef struct {
   uint32_t rec;

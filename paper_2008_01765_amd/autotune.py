@@ -6,7 +6,7 @@ GPU and keeps the fastest:
   Z     bucket capacity (Algorithm 3.1); only values whose overflow bound of
         Lemma 3.2 meets the security floor at that n are tried;
   k     butterfly levels fused per HBM pass;
-  tile  records per tile of the comparison sort's first phase.
+  tile  records per tile of the comparison sort's first phase (1024 .. 16384).
 
 Small classes are timed as batches of equal-size instances through
 bos_sort_batched (the way many small sorts run), large ones as single
@@ -28,7 +28,13 @@ DEFAULT_TABLE = os.path.join(HERE, "tuning", "mi355x.json")
 
 Z_CANDIDATES = (256, 512, 1024)
 K_CANDIDATES = (2, 3, 4)
-TILE_CANDIDATES = (1024, 2048, 4096)
+TILE_CANDIDATES = (1024, 2048, 4096, 8192, 16384)
+
+
+def tile_candidates(rec):
+    """Tile sizes of the comparison sort for this record size (a workgroup's LDS
+    holds 16384 records of 8 bytes but only 8192 of 16)."""
+    return tuple(t for t in TILE_CANDIDATES if not (rec == 16 and t == 16384))
 
 
 def log2_eps(n, z):
@@ -102,7 +108,7 @@ def tune(classes_by_rec=None, min_security_bits=80, reps=3, log=print):
             w = Workload(rec, c)
             zk = [((z, k), w.seconds_per_record(z, k, 4096, reps)) for z in zs for k in K_CANDIDATES]
             z, k = best(zk)
-            tl = [(t, w.seconds_per_record(z, k, t, reps)) for t in TILE_CANDIDATES]
+            tl = [(t, w.seconds_per_record(z, k, t, reps)) for t in tile_candidates(rec)]
             tile = best(tl)
             ns = min(v for _, v in tl) * 1e9
             entry = {"rec": rec, "log2n": c, "z": z, "k": k, "tile": tile, "ns_per_record": round(ns, 4),

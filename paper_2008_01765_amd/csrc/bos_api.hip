@@ -38,6 +38,7 @@ hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, con
 hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs, uint32_t total,
                                hipStream_t s);
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
+bool sort_tile_ok(int rec, uint32_t t);
 hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s);
 hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
                           hipStream_t s);
@@ -187,7 +188,6 @@ uint32_t max_klev(int rec, uint32_t z, bool last_shuffle) {
   return best;
 }
 
-bool tile_ok(uint32_t t) { return t == 1024 || t == 2048 || t == 4096; }
 
 // Lemma 3.2: overflow probability <= B log2 B e^(-Z/6) (B = 2^L)
 bool insecure(uint32_t L, uint32_t Z, uint32_t bits) {
@@ -242,7 +242,7 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   const uint32_t k = std::min(kreq, kmid);
   pl->k = k;
   pl->tile = q.tile ? q.tile : (tuned && te.tile ? te.tile : kDefaultTile);
-  if (!tile_ok(pl->tile)) return BOS_ERR_INVALID_ARG;
+  if (!sort_tile_ok(rec, pl->tile)) return BOS_ERR_INVALID_ARG;
   if (L == 0) {
     pl->P = 1;
     pl->klev[0] = 0;
@@ -597,7 +597,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
       b->launches.push_back(l);
     }
   // 2. tile sort, one launch per tile size
-  for (uint32_t T : {4096u, 2048u, 1024u}) {
+  for (uint32_t T : {16384u, 8192u, 4096u, 2048u, 1024u}) {
     std::vector<SortSeg> segs;
     uint32_t tiles = 0;
     for (const BatchJob& j : b->jobs) {
@@ -982,8 +982,8 @@ constexpr uint64_t kStepMinQuantum = 1ull << 21;
 
 size_t step_round_bytes(uint32_t count) {
   // every job adds at most one entry of each kind; each table starts aligned
-  // (fill, 2 per route group of at most 4 kinds x 8 Z, 3 tile sizes, merge)
-  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + 2 * sizeof(SortSeg)) + 72 * kAlign;
+  // (fill, 2 per route group of at most 4 kinds x 8 Z, 5 tile sizes, merge)
+  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + 2 * sizeof(SortSeg)) + 74 * kAlign;
 }
 
 size_t bos_step_workspace_bytes(uint32_t count) {
@@ -1049,7 +1049,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
 
   // Build every sub-round's tables on the host, then upload them at once.
   // route launches of a round: one per (pass kind, log2 Z); tile sorts: one
-  // per tile size (index 0, 1, 2 = 4096, 2048, 1024)
+  // per tile size (index 0..4 = 4096, 2048, 1024, 8192, 16384)
   struct RouteGroup {
     std::vector<PassArgs> args;
     std::vector<uint32_t> starts;
@@ -1057,13 +1057,13 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
     uint32_t blocks = 0, threads = 64, lds = 0, items0 = 0;
   };
   struct Round {
-    size_t o_fill = 0, o_tile[3] = {0, 0, 0}, o_merge = 0;
-    uint32_t nfill = 0, ntile[3] = {0, 0, 0}, nmerge = 0;
-    uint32_t tiles[3] = {0, 0, 0}, mtiles = 0;
+    size_t o_fill = 0, o_tile[5] = {0, 0, 0, 0, 0}, o_merge = 0;
+    uint32_t nfill = 0, ntile[5] = {0, 0, 0, 0, 0}, nmerge = 0;
+    uint32_t tiles[5] = {0, 0, 0, 0, 0}, mtiles = 0;
     std::map<uint32_t, RouteGroup> route;  // key: mode * 16 + lz
     std::vector<uint32_t> whole;  // jobs routed by the per-job path in this round
   };
-  const uint32_t kTiles[3] = {4096, 2048, 1024};
+  const uint32_t kTiles[5] = {4096, 2048, 1024, 8192, 16384};
   std::vector<Round> rounds;
   std::vector<char> tab;
   std::vector<uint32_t> phase(count);
@@ -1071,7 +1071,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
   for (uint32_t r = 0; r < kStepRounds; ++r) {
     Round rd;
     std::vector<FillSeg> fills;
-    std::vector<SortSeg> tiles[3], mseg;
+    std::vector<SortSeg> tiles[5], mseg;
     bool any = false;
     for (uint32_t i = 0; i < count; ++i) {
       if (phase[i] == BOS_PHASE_DONE || allowed[i] <= r) continue;
@@ -1128,7 +1128,9 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
           ++phase[i];
         }
       } else if (ph == pl.P) {
-        const uint32_t ti = pl.tile == 4096 ? 0u : pl.tile == 2048 ? 1u : 2u, T = pl.tile;
+        uint32_t ti = 0;
+        while (kTiles[ti] != pl.tile) ++ti;  // the plan's tile is one of kTiles
+        const uint32_t T = pl.tile;
         const uint32_t c = uint32_t((j.n + T - 1) / T);
         if (j.n > 1) {
           tiles[ti].push_back(SortSeg{start_buf(i), nullptr, j.n, 0, nullptr, rd.tiles[ti], c});
@@ -1153,7 +1155,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       kv.second.o_args = push_table(tab, kv.second.args);
       kv.second.o_starts = push_table(tab, kv.second.starts);
     }
-    for (int ti = 0; ti < 3; ++ti) {
+    for (int ti = 0; ti < 5; ++ti) {
       rd.ntile[ti] = uint32_t(tiles[ti].size());
       rd.o_tile[ti] = push_table(tab, tiles[ti]);
     }
@@ -1196,7 +1198,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
                                  reinterpret_cast<const uint32_t*>(dtab + g.o_starts), uint32_t(g.args.size()),
                                  g.blocks, g.threads, g.lds, s);
     }
-    for (int ti = 0; ti < 3; ++ti)
+    for (int ti = 0; ti < 5; ++ti)
       if (e == hipSuccess && rd.ntile[ti])
         e = launch_sort_batched(R, 0, kTiles[ti], reinterpret_cast<const SortSeg*>(dtab + rd.o_tile[ti]), rd.ntile[ti],
                                 rd.tiles[ti], s);
@@ -1261,7 +1263,8 @@ bos_status bos_set_tuning(const bos_tune_entry* entries, uint32_t count) {
   for (uint32_t i = 0; i < count; ++i) {
     const bos_tune_entry& e = entries[i];
     const bool zok = e.z == 0 || (e.z >= 8 && e.z <= 2048 && (e.z & (e.z - 1)) == 0);
-    if ((e.rec != 8 && e.rec != 16) || e.log2n > 40 || !zok || e.k > 12 || (e.tile && !tile_ok(e.tile)))
+    if ((e.rec != 8 && e.rec != 16) || e.log2n > 40 || !zok || e.k > 12 ||
+        (e.tile && !sort_tile_ok(int(e.rec), e.tile)))
       return BOS_ERR_INVALID_ARG;
   }
   {

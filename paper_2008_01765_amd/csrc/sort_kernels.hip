@@ -238,6 +238,65 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
   }
 }
 
+// Tiles of 2^TLOG records for TLOG = 13 or 14: 2^(TLOG - 12) register tiles of
+// 4096 records are sorted side by side (256 lanes each, one padded LDS region
+// each), then merged pairwise in LDS up to the whole tile, which saves as
+// many merge passes over HBM.
+template <int R, uint32_t TLOG>
+__device__ __forceinline__ void tile_sort_big_one(void* buf, uint64_t n, uint64_t tile) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t kSub = 4096, kSubPad = kSub + kSub / 16, TILE = 1u << TLOG;
+  static_assert(TLOG == 13 || TLOG == 14, "two or four register tiles");
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s = reinterpret_cast<T*>(smem);
+  T* B = static_cast<T*>(buf);
+  const uint32_t tid = threadIdx.x, sub = tid / 256u, lq = tid % 256u, o = 16u * tid;
+  const uint64_t t0 = tile << TLOG;
+  {
+    const uint64_t base = t0 + uint64_t(sub) * kSub + 16u * lq;
+    ElemR<T> v[16];
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
+    const LdsR<T> lds{s};
+    bin_bitonic<12>(v, lds, sub * kSubPad, lq, true);
+    __syncthreads();  // every register tile has left its padded region
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) s[o + e] = v[e].r;  // runs of 4096, unpadded
+  }
+  __syncthreads();
+  T out[kMItems];
+  for (uint32_t w = kSub; w < TILE; w *= 2) {
+    const uint32_t pb = (o / (2 * w)) * (2 * w);
+    merge_items(s + pb, w, s + pb + w, w, o - pb, out);
+    __syncthreads();
+    if (2 * w < TILE) {
+#pragma unroll
+      for (uint32_t k = 0; k < kMItems; ++k) s[o + k] = out[k];
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kMItems; ++k) s[o + k + (o >> 4)] = out[k];  // staged, one pad slot per 16
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < kMItems; ++k) {
+    const uint32_t t = tid + k * (TILE / 16u);
+    if (t0 + t < n) B[t0 + t] = s[t + (t >> 4)];
+  }
+}
+
+template <int R, uint32_t TLOG>
+__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel(void* buf, uint64_t n) {
+  tile_sort_big_one<R, TLOG>(buf, n, blockIdx.x);
+}
+
+template <int R, uint32_t TLOG>
+__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel_b(const SortSeg* segs,
+                                                                              uint32_t nsegs) {
+  const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
+  tile_sort_big_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first);
+}
+
 template <int R>
 __global__ __launch_bounds__(kMThreads) void merge_tile_kernel(const void* src, void* dst, uint64_t n, uint64_t w,
                                                                const uint64_t* split) {
@@ -371,17 +430,28 @@ uint32_t tile_lds_bytes(int rec, uint32_t ts) { return (ts + (ts >> 5)) * uint32
 template <int R, uint32_t TLOG>
 constexpr uint32_t tile_sort_lds() { return ((1u << TLOG) + (1u << TLOG) / 16u) * uint32_t(R); }
 
+// Tile sizes the comparison sort offers for records of `rec` bytes (the LDS
+// of a workgroup holds at most 8192 + 512 slots of 16 bytes).
+bool sort_tile_ok(int rec, uint32_t t) {
+  return t == 1024 || t == 2048 || t == 4096 || t == 8192 || (t == 16384 && rec == 8);
+}
+
 template <int R, uint32_t TLOG>
 static hipError_t launch_tile_sort_t(void* buf, uint64_t n, hipStream_t s) {
+  constexpr bool BIG = TLOG > 12;
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = allow_lds(tile_sort_reg_kernel<R, TLOG>);
+    const hipError_t e = BIG ? allow_lds(tile_sort_big_kernel<R, BIG ? TLOG : 13>)
+                             : allow_lds(tile_sort_reg_kernel<R, BIG ? 12 : TLOG>);
     if (e != hipSuccess) return e;
     attr = true;
   }
   const uint64_t tiles = (n + (1ull << TLOG) - 1) >> TLOG;
   const uint32_t threads = tile_threads<TLOG>(), lds = tile_sort_lds<R, TLOG>();
-  hipLaunchKernelGGL((tile_sort_reg_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n);
+  if constexpr (BIG)
+    hipLaunchKernelGGL((tile_sort_big_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n);
+  else
+    hipLaunchKernelGGL((tile_sort_reg_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n);
   return hipGetLastError();
 }
 
@@ -394,13 +464,20 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
     if (e != hipSuccess) return e;
     attr = true;
   }
-  if (ts != 1024 && ts != 2048 && ts != 4096) return hipErrorInvalidValue;
+  if (!sort_tile_ok(R, ts)) return hipErrorInvalidValue;
   *result = buf0;
   if (n <= 1) return hipSuccess;
   prof_begin(BOS_K_SORT_TILE, 0, 2 * n * R, s);
-  hipError_t e = ts == 4096 ? launch_tile_sort_t<R, 12>(buf0, n, s)
-                 : ts == 2048 ? launch_tile_sort_t<R, 11>(buf0, n, s)
-                              : launch_tile_sort_t<R, 10>(buf0, n, s);
+  hipError_t e = hipErrorInvalidValue;
+  switch (ts) {
+    case 1024: e = launch_tile_sort_t<R, 10>(buf0, n, s); break;
+    case 2048: e = launch_tile_sort_t<R, 11>(buf0, n, s); break;
+    case 4096: e = launch_tile_sort_t<R, 12>(buf0, n, s); break;
+    case 8192: e = launch_tile_sort_t<R, 13>(buf0, n, s); break;
+    default:
+      if constexpr (R == 8) e = launch_tile_sort_t<R, 14>(buf0, n, s);
+      break;
+  }
   prof_end(s);
   if (e != hipSuccess) return e;
   void* src = buf0;
@@ -492,14 +569,19 @@ static hipError_t bitonic_t(const void* in, void* out, uint64_t n, void* ws, uin
 
 template <int R, uint32_t TLOG>
 static hipError_t batched_tile_sort_t(const SortSeg* segs, uint32_t nsegs, uint32_t total, hipStream_t s) {
+  constexpr bool BIG = TLOG > 12;
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = allow_lds(tile_sort_reg_kernel_b<R, TLOG>);
+    const hipError_t e = BIG ? allow_lds(tile_sort_big_kernel_b<R, BIG ? TLOG : 13>)
+                             : allow_lds(tile_sort_reg_kernel_b<R, BIG ? 12 : TLOG>);
     if (e != hipSuccess) return e;
     attr = true;
   }
   const uint32_t threads = tile_threads<TLOG>(), lds = tile_sort_lds<R, TLOG>();
-  hipLaunchKernelGGL((tile_sort_reg_kernel_b<R, TLOG>), dim3(total), dim3(threads), lds, s, segs, nsegs);
+  if constexpr (BIG)
+    hipLaunchKernelGGL((tile_sort_big_kernel_b<R, TLOG>), dim3(total), dim3(threads), lds, s, segs, nsegs);
+  else
+    hipLaunchKernelGGL((tile_sort_reg_kernel_b<R, TLOG>), dim3(total), dim3(threads), lds, s, segs, nsegs);
   return hipGetLastError();
 }
 
@@ -514,9 +596,12 @@ static hipError_t batched_sort_launch_t(int kind, uint32_t tile, const SortSeg* 
   }
   if (total == 0) return hipSuccess;
   if (kind == 0) {
+    if (!sort_tile_ok(R, tile)) return hipErrorInvalidValue;
     if (tile == 4096) return batched_tile_sort_t<R, 12>(segs, nsegs, total, s);
     if (tile == 2048) return batched_tile_sort_t<R, 11>(segs, nsegs, total, s);
     if (tile == 1024) return batched_tile_sort_t<R, 10>(segs, nsegs, total, s);
+    if (tile == 8192) return batched_tile_sort_t<R, 13>(segs, nsegs, total, s);
+    if constexpr (R == 8) return batched_tile_sort_t<R, 14>(segs, nsegs, total, s);
     return hipErrorInvalidValue;
   } else if (kind == 1) {
     hipLaunchKernelGGL(merge_partition_kernel_b<R>, dim3((total + 255) / 256), dim3(256), 0, s, segs, nsegs, total);

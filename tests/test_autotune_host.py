@@ -40,3 +40,9 @@ def test_table_round_trip(tmp_path):
     p = tmp_path / "t.json"
     autotune.save(tab, str(p), "gpu")
     assert autotune.load(str(p)) == tab
+
+
+def test_tile_candidates_fit_lds():
+    # 16384 records of 16 bytes would need 256 KiB of LDS per workgroup
+    assert autotune.tile_candidates(8) == (1024, 2048, 4096, 8192, 16384)
+    assert autotune.tile_candidates(16) == (1024, 2048, 4096, 8192)

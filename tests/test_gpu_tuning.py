@@ -99,9 +99,32 @@ def test_step_mixed_tuned_plans(table):
         np.testing.assert_array_equal(bos.to_numpy(f.result()), cf.sorted_records(h))
 
 
-@pytest.mark.parametrize("tile", [1024, 2048, 4096])
-@pytest.mark.parametrize("n", [1, 1000, 1024, 1025, 2049, 4097, 10000, 1 << 15])
-def test_tile_sizes(tile, n):
-    h = inputs.records(n, 16, 33 + n, key_bits=12)
+@pytest.mark.parametrize("rec", [8, 16])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096, 8192, 16384])
+@pytest.mark.parametrize("n", [1, 1000, 1024, 1025, 2049, 4097, 8193, 10000, 16385, 1 << 15, 100003])
+def test_tile_sizes(rec, tile, n):
+    h = inputs.records(n, rec, 33 + n, key_bits=12)
+    if rec == 16 and tile == 16384:
+        # a 16384-record tile of 16-byte records does not fit a workgroup's LDS
+        with pytest.raises(bos.BosError) as e:
+            bos.sort(bos.from_numpy(h), seed=1, tile=tile, min_security_bits=0)
+        assert e.value.status == bos.INVALID_ARG
+        return
     out = bos.sort(bos.from_numpy(h), seed=1, tile=tile, min_security_bits=0)
     np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(h))
+
+
+@pytest.mark.parametrize("tile", [8192, 16384])
+def test_big_tiles_batched_and_step(table, tile):
+    bos.set_tuning([{"rec": 8, "log2n": c, "z": 512, "k": 3, "tile": tile} for c in (12, 16, 20)])
+    sizes = [5000, 1 << 16, 70000, 1 << 20, 3, 16385]
+    hosts = [inputs.records(n, 8, 900 + i) for i, n in enumerate(sizes)]
+    outs = bos.sort_batched([bos.from_numpy(h) for h in hosts], [1 + i for i in range(len(hosts))],
+                            min_security_bits=0)
+    for h, o in zip(hosts, outs):
+        np.testing.assert_array_equal(bos.to_numpy(o), cf.sorted_records(h))
+    srv = serving.Server(hbm_budget_bytes=1 << 34, min_security_bits=0)
+    futs = [srv.submit(bos.from_numpy(h), seed=i) for i, h in enumerate(hosts)]
+    srv.run_until_idle()
+    for h, f in zip(hosts, futs):
+        np.testing.assert_array_equal(bos.to_numpy(f.result()), cf.sorted_records(h))
