@@ -321,14 +321,16 @@ def debug_labels(n, levels, seed, attempt=0, device="cuda"):
     return out[:n]
 
 
-def debug_levels(t, seed=0, z=0, k=0, attempt=0, min_security_bits=0, generic=False):
+def debug_levels(t, seed=0, z=512, k=0, attempt=0, min_security_bits=0, generic=False):
     """Slot arrays at every pass boundary of one attempt (host numpy arrays)."""
     import numpy as np
+    if not z:
+        raise ValueError("debug_levels needs an explicit z")
     rec = rec_bytes(t)
     n = t.shape[0]
     p = params(seed, z, k, 0, 0, min_security_bits, generic=generic)
     pl = plan(n, rec, z=z, k=k, min_security_bits=min_security_bits)
-    B, Z = pl["buckets"], (z or 512)
+    B, Z = pl["buckets"], z
     P = len(pl["passes"])
     dt = np.uint32 if rec == 8 else np.uint64
     recs = np.zeros((P + 1, B, Z, 2), dtype=dt)

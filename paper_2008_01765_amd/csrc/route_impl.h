@@ -342,6 +342,22 @@ __device__ __forceinline__ void bitonic_phase(E (&v)[16], const V& lds, const Bi
   }
 }
 
+// Ascending bitonic merge of every bin (phase LZ only: stages LZ-1 .. 0), for
+// bins that hold a bitonic sequence; v holds layout P on entry and exit.
+template <int LZ, typename E, typename V>
+__device__ __forceinline__ void bin_bitonic_merge(E (&v)[16], const V& lds, uint32_t bbase, uint32_t lq, bool active) {
+  BinLane bl;
+  bl.active = active;
+  bl.bbase = bbase;
+  bl.pbase = bbase + 17u * lq;
+  bl.lq = lq;
+  bl.lb0 = lq & 1u;
+  bl.lb1 = (lq >> 1) & 1u;
+  const uint32_t rest = lq >> 2;
+  bl.lowQ = LZ >= 11 ? ((bl.lb1 << (LZ - 5)) | (bl.lb0 << (LZ - 6)) | rest) : (LZ >= 6 ? lq : 0u);
+  bitonic_phase<LZ, LZ>(v, lds, bl);
+}
+
 template <int LZ, typename E, typename V>
 __device__ __forceinline__ void bin_bitonic(E (&v)[16], const V& lds, uint32_t bbase, uint32_t lq, bool active) {
   BinLane bl;

@@ -239,50 +239,59 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
 }
 
 // Tiles of 2^TLOG records for TLOG = 13 or 14: 2^(TLOG - 12) register tiles of
-// 4096 records are sorted side by side (256 lanes each, one padded LDS region
-// each), then merged pairwise in LDS up to the whole tile, which saves as
-// many merge passes over HBM.
+// 4096 records (256 lanes and one padded LDS region each) are sorted side by
+// side, then merged with the bitonic merge network: a compare-exchange across
+// two sorted runs, first element against last (which leaves two bitonic halves,
+// every element of the first at most every element of the second), then the
+// ascending half-cleaner stages inside each half.  It saves TLOG - 12 merge
+// passes over HBM.
 template <int R, uint32_t TLOG>
 __device__ __forceinline__ void tile_sort_big_one(void* buf, uint64_t n, uint64_t tile) {
   using T = typename RecOf<R>::T;
-  constexpr uint32_t kSub = 4096, kSubPad = kSub + kSub / 16, TILE = 1u << TLOG;
+  constexpr uint32_t kSub = 4096, kSubPad = kSub + kSub / 16;
   static_assert(TLOG == 13 || TLOG == 14, "two or four register tiles");
   extern __shared__ __align__(16) unsigned char smem[];
   T* s = reinterpret_cast<T*>(smem);
   T* B = static_cast<T*>(buf);
-  const uint32_t tid = threadIdx.x, sub = tid / 256u, lq = tid % 256u, o = 16u * tid;
-  const uint64_t t0 = tile << TLOG;
-  {
-    const uint64_t base = t0 + uint64_t(sub) * kSub + 16u * lq;
-    ElemR<T> v[16];
+  const uint32_t tid = threadIdx.x, sub = tid / 256u, lq = tid % 256u;
+  const uint64_t base = (tile << TLOG) + uint64_t(sub) * kSub + 16u * lq;
+  const LdsR<T> lds{s};
+  ElemR<T> v[16];
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
-    const LdsR<T> lds{s};
-    bin_bitonic<12>(v, lds, sub * kSubPad, lq, true);
-    __syncthreads();  // every register tile has left its padded region
+  for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
+  bin_bitonic<12>(v, lds, sub * kSubPad, lq, true);
+  // Compare-exchange of this lane's 16 records with those of sub-tile psub:
+  // lane 255 - lq, registers in reverse order when `mirror` (the first stage of
+  // a merge of two ascending runs), else the same lane and registers.  The
+  // lower sub-tile keeps the minima.
+  auto cross = [&](uint32_t psub, bool mirror) {
+    __syncthreads();  // the LDS regions are free (the last network stage read them)
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) s[o + e] = v[e].r;  // runs of 4096, unpadded
-  }
-  __syncthreads();
-  T out[kMItems];
-  for (uint32_t w = kSub; w < TILE; w *= 2) {
-    const uint32_t pb = (o / (2 * w)) * (2 * w);
-    merge_items(s + pb, w, s + pb + w, w, o - pb, out);
+    for (uint32_t e = 0; e < 16; ++e) s[sub * kSubPad + 17u * lq + e] = v[e].r;
     __syncthreads();
-    if (2 * w < TILE) {
+    const uint32_t plq = mirror ? 255u - lq : lq;
+    const bool keep_min = sub < psub;
 #pragma unroll
-      for (uint32_t k = 0; k < kMItems; ++k) s[o + k] = out[k];
-      __syncthreads();
+    for (uint32_t e = 0; e < 16; ++e) {
+      const ElemR<T> p{s[psub * kSubPad + 17u * plq + (mirror ? 15u - e : e)]};
+      const bool take = e_less(p, v[e]) == keep_min;
+      v[e] = e_sel(take, p, v[e]);
     }
+    __syncthreads();
+  };
+  // runs of 4096 -> 8192: sub-tiles 2j, 2j+1
+  cross(sub ^ 1u, true);
+  bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+  if constexpr (TLOG == 14) {
+    // runs of 8192 -> 16384: mirror across the two runs, then the stage of
+    // distance 4096 inside each run, then the stages inside every sub-tile
+    cross(3u - sub, true);
+    cross(sub ^ 1u, false);
+    bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
   }
 #pragma unroll
-  for (uint32_t k = 0; k < kMItems; ++k) s[o + k + (o >> 4)] = out[k];  // staged, one pad slot per 16
-  __syncthreads();
-#pragma unroll
-  for (uint32_t k = 0; k < kMItems; ++k) {
-    const uint32_t t = tid + k * (TILE / 16u);
-    if (t0 + t < n) B[t0 + t] = s[t + (t >> 4)];
-  }
+  for (uint32_t e = 0; e < 16; ++e)
+    if (base + e < n) B[base + e] = v[e].r;
 }
 
 template <int R, uint32_t TLOG>

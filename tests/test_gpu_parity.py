@@ -248,3 +248,27 @@ def test_sort_uses_split_last_pass_orp_fused():
     assert "strip" not in kinds_orp and "route_last" in kinds_orp
     np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(h))
     np.testing.assert_array_equal(bos.to_numpy(orp), oracle.orp(h, 5)["out"])
+
+
+def test_routing_pattern_independent_of_data():
+    # Two key sets of the duplicate-heavy shape, one seed: the tag array at
+    # every pass boundary (labels and dummy layout, which alone steer every
+    # swap of the networks, every address and the bin loads) is identical, and
+    # so is the sequence of launches with their byte counts.  The records
+    # themselves differ.
+    n = 1 << 20
+    a = inputs.records(n, 16, 42, key_bits=20)
+    b = inputs.records(n, 16, 43, key_bits=20)
+    da = bos.debug_levels(_gpu(a), seed=7, z=512, k=3)
+    db = bos.debug_levels(_gpu(b), seed=7, z=512, k=3)
+    assert da["rc"] == db["rc"] == bos.OK
+    np.testing.assert_array_equal(da["tags"], db["tags"])
+    assert not np.array_equal(da["recs"], db["recs"])
+    launches = []
+    for h in (a, b):
+        bos.profile_enable(True)
+        bos.profile_read()
+        bos.sort(_gpu(h), seed=7, z=512, k=3)
+        launches.append([(l["kind"], l["index"], l["bytes"]) for l in bos.profile_read()])
+        bos.profile_enable(False)
+    assert launches[0] == launches[1]

@@ -371,3 +371,17 @@ def test_sort_trace_depends_only_on_order_type(oracle_lib):
     rb = oracle_lib.sort(b, 6, z=z, max_retries=40)["report"]
     assert ra["digest_orp"] == rb["digest_orp"]
     assert ra["digest_sort"] == rb["digest_sort"]
+
+
+@pytest.mark.slow
+def test_orp_trace_identical_for_two_key_sets_at_full_size(oracle_lib):
+    # The duplicate-heavy workload at full size (n = 2^24, 16-byte records,
+    # keys uniform on [0, 2^20)) with data seeds 42 and 43 and one ORP seed:
+    # the access sequences of the ORP phase are identical (Section 3.2's
+    # obliviousness, counted by the oracle's trace digest), and so are the
+    # attempt counts.
+    from paper_2008_01765_amd import inputs
+    ra = oracle_lib.orp(inputs.workload_dup(42), 1)["report"]
+    rb = oracle_lib.orp(inputs.workload_dup(43), 1)["report"]
+    assert ra["digest_orp"] == rb["digest_orp"]
+    assert ra["attempts"] == rb["attempts"]
