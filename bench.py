@@ -101,6 +101,8 @@ def bench_sweep(args, torch, bos, x, out):
     bos_sort and per bos_orp, per-pass GB/s; then bos_orp over seeds 1..S per Z
     with the retries they needed.  Z = 256 is below the 80-bit floor at this n
     (Lemma 3.2 gives about 2^-36), so the sweep runs with the floor off."""
+    from paper_2008_01765_amd import autotune
+
     stream = torch.cuda.current_stream()
     res = {"points": [], "overflow": []}
     n = x.shape[0]
@@ -141,16 +143,9 @@ def bench_sweep(args, torch, bos, x, out):
             except bos.BosError:
                 failed += 1
         res["overflow"].append({"z": z, "seeds": args.sweep_seeds, "retries": retries, "failed": failed,
-                                "log2_eps_bound": round(log2_eps(n, z), 1), "s": round(time.perf_counter() - t0, 1)})
+                                "log2_eps_bound": round(autotune.log2_eps(n, z), 1),
+                                "s": round(time.perf_counter() - t0, 1)})
     return res
-
-
-def log2_eps(n, z):
-    L = 0
-    while (1 << L) * z < 2 * n:
-        L += 1
-    import math
-    return L + math.log2(L) - z / (6.0 * math.log(2.0)) if L else float("-inf")
 
 
 def install_tuning(args, bos):

@@ -614,7 +614,8 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     l.tab = push_table(tab, segs);
     if (l.nsegs) b->launches.push_back(l);
   }
-  // 3. merge passes (runs of width tile << pass, merge tiles of kMergeTile)
+  // 3. merge passes (runs of width tile << pass, merge tiles of
+  //    merge_tile_records(rec) outputs)
   uint32_t maxM = 0;
   for (const BatchJob& j : b->jobs) maxM = std::max(maxM, j.merges);
   for (uint32_t pass = 0; pass < maxM; ++pass) {
@@ -622,7 +623,8 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     uint32_t tiles = 0;
     for (const BatchJob& j : b->jobs) {
       if (pass >= j.merges) continue;
-      const uint32_t c = uint32_t((j.n + kMergeTile - 1) / kMergeTile);
+      const uint32_t mt = merge_tile_records(rec);
+      const uint32_t c = uint32_t((j.n + mt - 1) / mt);
       void* src = (pass % 2 == 0) ? j.start : j.other;
       void* dst = (pass % 2 == 0) ? j.other : j.start;
       segs.push_back(SortSeg{src, dst, j.n, uint64_t(j.pl.tile) << pass,
@@ -1139,7 +1141,8 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
         phase[i] = merges[i] == 0 ? BOS_PHASE_DONE : pl.P + 1;
       } else {
         const uint32_t pass = ph - (pl.P + 1);
-        const uint32_t c = uint32_t((j.n + kMergeTile - 1) / kMergeTile);
+        const uint32_t mt = merge_tile_records(R);
+        const uint32_t c = uint32_t((j.n + mt - 1) / mt);
         void* src = (pass % 2 == 0) ? start_buf(i) : other_buf(i);
         void* dst = (pass % 2 == 0) ? other_buf(i) : start_buf(i);
         mseg.push_back(SortSeg{src, dst, j.n, uint64_t(pl.tile) << pass, reinterpret_cast<uint64_t*>(w + pl.off_split),

@@ -10,12 +10,22 @@ namespace bos {
 constexpr uint32_t kDummyTag = 0xFFFFFFFFu;  // tag of a dummy slot; real tags are labels < 2^31
 constexpr uint64_t kNoOverflow = ~0ull;      // status word when no MergeSplit overflowed
 constexpr int kMaxThreads = 512;             // threads per routing block
-constexpr uint32_t kMergeTile = 4096;        // outputs per workgroup of a merge pass
+// Outputs per workgroup of a merge pass: 4096 records of 8 bytes, 2048 of 16
+// (the tile and its staging copy fit four workgroups' LDS per CU either way).
+__host__ __device__ constexpr uint32_t merge_tile_records(int rec) { return rec == 8 ? 4096u : 2048u; }
 
 // Record of BOS_REC_U32U32 (8 bytes) or BOS_REC_U64U64 (16 bytes).
 template <int R> struct RecOf;
 template <> struct RecOf<8> { using T = uint2; };
 template <> struct RecOf<16> { using T = uint4; };
+
+// Native vector types of the records, for arrays that must stay in registers
+// (arrays of the uint2/uint4 structs can end up in scratch memory).
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+template <typename T> struct NativeOf;
+template <> struct NativeOf<uint2> { using V = v2u; };
+template <> struct NativeOf<uint4> { using V = v4u; };
 
 __device__ __forceinline__ uint64_t key_of(uint2 r) { return r.x; }
 __device__ __forceinline__ uint64_t pay_of(uint2 r) { return r.y; }
@@ -29,7 +39,7 @@ __device__ __forceinline__ bool rec_less(uint2 a, uint2 b) {
 }
 __device__ __forceinline__ bool rec_less(uint4 a, uint4 b) {
   const uint64_t ka = key_of(a), kb = key_of(b);
-  return ka < kb || (ka == kb && pay_of(a) < pay_of(b));
+  return (ka < kb) | ((ka == kb) & (pay_of(a) < pay_of(b)));  // no short-circuit branches
 }
 
 template <typename T> __device__ __forceinline__ T zero_rec();

@@ -109,7 +109,15 @@ __global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel_b(c
   tile_sort_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first);
 }
 
-constexpr uint32_t kMTile = kMergeTile, kMThreads = 256, kMItems = kMTile / kMThreads;
+// Merge tiles: kMTile outputs per workgroup of 256 threads, kMItems per thread
+// (16 records of 8 bytes or 8 of 16, so that a thread's loads and outputs stay
+// in registers).
+template <int R>
+constexpr uint32_t kMTile = merge_tile_records(R);
+template <int R>
+constexpr uint32_t kMItems = R == 8 ? 16u : 8u;
+template <int R>
+constexpr uint32_t kMThreads = kMTile<R> / kMItems<R>;
 
 // Merge-path split of output tile boundary b of one merge pass (runs of width
 // w merged in pairs): absolute start of the tile's part of the left and the
@@ -119,7 +127,7 @@ __device__ __forceinline__ void merge_partition_one(const void* src_, uint64_t n
                                                     uint64_t b) {
   using T = typename RecOf<R>::T;
   const T* src = static_cast<const T*>(src_);
-  const uint64_t o = b * kMTile;
+  const uint64_t o = b * kMTile<R>;
   const uint64_t lo = (o / (2 * w)) * (2 * w);
   const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
   const uint64_t a = merge_path(src + lo, mid - lo, src + mid, hi - mid, o - lo);
@@ -141,11 +149,11 @@ __global__ void merge_partition_kernel_b(const SortSeg* segs, uint32_t nsegs, ui
   merge_partition_one<R>(sg.src, sg.n, sg.w, sg.split, x - sg.first);
 }
 
-// Merge kMItems outputs of the stable merge of SA[0..na) and SB[0..nb) (A wins
+// Merge ITEMS outputs of the stable merge of SA[0..na) and SB[0..nb) (A wins
 // ties), starting at output dd, by a merge-path search and a serial merge.
-template <typename T>
+template <typename T, uint32_t ITEMS>
 __device__ __forceinline__ void merge_items(const T* SA, uint32_t na, const T* SB, uint32_t nb, uint32_t dd,
-                                            T (&out)[kMItems]) {
+                                            T (&out)[ITEMS]) {
   uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
   while (l < h) {
     const uint32_t md = (l + h) >> 1;
@@ -156,10 +164,10 @@ __device__ __forceinline__ void merge_items(const T* SA, uint32_t na, const T* S
   }
   uint32_t ia = l, ib = dd - l;
 #pragma unroll
-  for (uint32_t k = 0; k < kMItems; ++k) {
+  for (uint32_t k = 0; k < ITEMS; ++k) {
     const bool take_a = ia < na && (ib >= nb || !rec_less(SB[ib], SA[ia]));
     const T va = SA[ia < na ? ia : 0], vb = SB[ib < nb ? ib : 0];
-    out[k] = take_a ? va : vb;
+    out[k] = sel(take_a, va, vb);  // per word: a select of whole records goes through scratch
     ia += take_a ? 1u : 0u;
     ib += take_a ? 0u : 1u;
   }
@@ -179,17 +187,17 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
   T* s = reinterpret_cast<T*>(smem);
   const T* src = static_cast<const T*>(src_);
   T* dst = static_cast<T*>(dst_);
-  const uint64_t o0 = b * kMTile;
-  const bool whole_pairs = 2 * w < kMTile;
+  const uint64_t o0 = b * kMTile<R>;
+  const bool whole_pairs = 2 * w < kMTile<R>;
   uint64_t a0 = o0, b0 = o0;
   uint32_t na = 0, nb = 0, cnt = 0;
   if (whole_pairs) {
-    cnt = uint32_t((o0 + kMTile < n ? o0 + kMTile : n) - o0);
+    cnt = uint32_t((o0 + kMTile<R> < n ? o0 + kMTile<R> : n) - o0);
     na = cnt;  // the tile is read as one contiguous range
   } else {
     const uint64_t lo = (o0 / (2 * w)) * (2 * w);
     const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
-    const uint64_t o1 = o0 + kMTile < hi ? o0 + kMTile : hi;
+    const uint64_t o1 = o0 + kMTile<R> < hi ? o0 + kMTile<R> : hi;
     a0 = split[2 * b];
     b0 = split[2 * b + 1];
     const uint64_t a1 = o1 == hi ? mid : split[2 * b + 2], b1 = o1 == hi ? hi : split[2 * b + 3];
@@ -198,42 +206,50 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
     cnt = na + nb;
   }
   {
-    // issue every load of this thread before the first LDS store
-    T in[kMItems];
+    // issue every load of this thread before the first LDS store (native
+    // vectors, so the array stays in registers; lanes past the tile reload a
+    // valid record)
+    using V = typename NativeOf<T>::V;
+    const V* srcv = reinterpret_cast<const V*>(src);
+    V* sv = reinterpret_cast<V*>(s);
+    V in[kMItems<R>];
 #pragma unroll
-    for (uint32_t k = 0; k < kMItems; ++k) {
-      const uint32_t t = threadIdx.x + k * kMThreads;
-      if (t < cnt) in[k] = t < na ? src[a0 + t] : src[b0 + t - na];
+    for (uint32_t k = 0; k < kMItems<R>; ++k) {
+      const uint32_t t = threadIdx.x + k * kMThreads<R>;
+      const uint64_t gi = t < na ? a0 + t : b0 + t - na;
+      in[k] = srcv[t < cnt ? gi : a0];
     }
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the stores
 #pragma unroll
-    for (uint32_t k = 0; k < kMItems; ++k) {
-      const uint32_t t = threadIdx.x + k * kMThreads;
-      if (t < cnt) s[t] = in[k];
+    for (uint32_t k = 0; k < kMItems<R>; ++k) {
+      const uint32_t t = threadIdx.x + k * kMThreads<R>;
+      if (t < cnt) sv[t] = in[k];
     }
   }
   __syncthreads();
-  const uint32_t dd = threadIdx.x * kMItems;
-  T out[kMItems];
+  const uint32_t dd = threadIdx.x * kMItems<R>;
+  T out[kMItems<R>];
   if (dd < cnt) {
+    // the two runs this thread merges from, and its first output among theirs
+    uint32_t pb = 0, pa = na, pbn = nb;
     if (whole_pairs) {
-      // this thread's outputs lie in one pair (2w is a multiple of kMItems)
-      const uint32_t w32 = uint32_t(w), pb = (dd / (2 * w32)) * (2 * w32);
-      const uint32_t pa = cnt - pb < w32 ? cnt - pb : w32;
-      const uint32_t pbn = cnt - pb - pa < w32 ? cnt - pb - pa : w32;
-      merge_items(s + pb, pa, s + pb + pa, pbn, dd - pb, out);
-    } else {
-      merge_items(s, na, s + na, nb, dd, out);
+      // this thread's outputs lie in one pair (2w is a multiple of kMItems<R>)
+      const uint32_t w32 = uint32_t(w);
+      pb = (dd / (2 * w32)) * (2 * w32);
+      pa = cnt - pb < w32 ? cnt - pb : w32;
+      pbn = cnt - pb - pa < w32 ? cnt - pb - pa : w32;
     }
+    merge_items(s + pb, pa, s + pb + pa, pbn, dd - pb, out);
   }
   __syncthreads();
   if (dd < cnt) {
 #pragma unroll
-    for (uint32_t k = 0; k < kMItems; ++k) s[dd + k + (dd >> 4)] = out[k];  // one pad slot per 16
+    for (uint32_t k = 0; k < kMItems<R>; ++k) s[dd + k + (dd >> 4)] = out[k];  // one pad slot per 16
   }
   __syncthreads();
 #pragma unroll
-  for (uint32_t k = 0; k < kMItems; ++k) {
-    const uint32_t t = threadIdx.x + k * kMThreads;
+  for (uint32_t k = 0; k < kMItems<R>; ++k) {
+    const uint32_t t = threadIdx.x + k * kMThreads<R>;
     if (t < cnt) dst[o0 + t] = s[t + (t >> 4)];
   }
 }
@@ -307,13 +323,13 @@ __global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel_b(c
 }
 
 template <int R>
-__global__ __launch_bounds__(kMThreads) void merge_tile_kernel(const void* src, void* dst, uint64_t n, uint64_t w,
+__global__ __launch_bounds__(kMThreads<R>) void merge_tile_kernel(const void* src, void* dst, uint64_t n, uint64_t w,
                                                                const uint64_t* split) {
   merge_tile_one<R>(src, dst, n, w, split, blockIdx.x);
 }
 
 template <int R>
-__global__ __launch_bounds__(kMThreads) void merge_tile_kernel_b(const SortSeg* segs, uint32_t nsegs) {
+__global__ __launch_bounds__(kMThreads<R>) void merge_tile_kernel_b(const SortSeg* segs, uint32_t nsegs) {
   const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
   merge_tile_one<R>(sg.src, sg.dst, sg.n, sg.w, sg.split, blockIdx.x - sg.first);
 }
@@ -492,14 +508,14 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   void* src = buf0;
   void* dst = buf1;
   uint32_t pass = 0;
-  const uint64_t mtiles = (n + kMTile - 1) / kMTile;
-  const uint32_t merge_lds = (kMTile + (kMTile >> 4)) * uint32_t(R);
+  const uint64_t mtiles = (n + kMTile<R> - 1) / kMTile<R>;
+  const uint32_t merge_lds = (kMTile<R> + (kMTile<R> >> 4)) * uint32_t(R);
   for (uint64_t w = ts; w < n; w *= 2) {
     prof_begin(BOS_K_SORT_MERGE, pass++, 2 * n * R, s);
     // boundaries 0..mtiles-1 (the end of the last tile is the end of its run pair)
     hipLaunchKernelGGL(merge_partition_kernel<R>, dim3(uint32_t((mtiles + 255) / 256)), dim3(256), 0, s, src, n, w,
                        split, mtiles);
-    hipLaunchKernelGGL(merge_tile_kernel<R>, dim3(uint32_t(mtiles)), dim3(kMThreads), merge_lds, s, src, dst, n, w,
+    hipLaunchKernelGGL(merge_tile_kernel<R>, dim3(uint32_t(mtiles)), dim3(kMThreads<R>), merge_lds, s, src, dst, n, w,
                        split);
     prof_end(s);
     e = hipGetLastError();
@@ -521,7 +537,10 @@ uint32_t comparison_sort_passes(uint64_t n, uint32_t ts) {
 }
 
 // Bytes of the split array the merge passes need.
-size_t comparison_sort_split_bytes(uint64_t n) { return size_t((n + kMTile - 1) / kMTile + 2) * 16; }
+size_t comparison_sort_split_bytes(uint64_t n) {
+  constexpr uint64_t t = merge_tile_records(16);  // the smaller merge tile
+  return size_t((n + t - 1) / t + 2) * 16;
+}
 
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                   hipStream_t s, void** result) {
@@ -615,8 +634,8 @@ static hipError_t batched_sort_launch_t(int kind, uint32_t tile, const SortSeg* 
   } else if (kind == 1) {
     hipLaunchKernelGGL(merge_partition_kernel_b<R>, dim3((total + 255) / 256), dim3(256), 0, s, segs, nsegs, total);
   } else {
-    const uint32_t lds = (kMTile + (kMTile >> 4)) * uint32_t(R);
-    hipLaunchKernelGGL(merge_tile_kernel_b<R>, dim3(total), dim3(kMThreads), lds, s, segs, nsegs);
+    const uint32_t lds = (kMTile<R> + (kMTile<R> >> 4)) * uint32_t(R);
+    hipLaunchKernelGGL(merge_tile_kernel_b<R>, dim3(total), dim3(kMThreads<R>), lds, s, segs, nsegs);
   }
   return hipGetLastError();
 }

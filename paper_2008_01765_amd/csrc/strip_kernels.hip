@@ -61,30 +61,32 @@ __global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned
   __syncthreads();
   const uint32_t total = pre[NB];
   const uint64_t base = boff[blk];
+  using V = typename NativeOf<T>::V;  // native vectors stay in registers
+  const V* bv = reinterpret_cast<const V*>(binned);
+  V* ov = reinterpret_cast<V*>(out);
   for (uint32_t q0 = 0; q0 < total; q0 += kStripThreads * kStripItems) {
-    T v[kStripItems];
+    V v[kStripItems];
     uint64_t dst[kStripItems];
 #pragma unroll
     for (uint32_t k = 0; k < kStripItems; ++k) {
       const uint32_t q = q0 + k * kStripThreads + tid;
-      dst[k] = ~0ull;
-      if (q < total) {
-        // bin j: the last with pre[j] <= q
-        uint32_t lo = 0, hi = NB;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (pre[mid] <= q)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        v[k] = binned[((bin0 + lo) << lz) + (q - pre[lo])];
-        dst[k] = base + q;
+      // bin j: the last with pre[j] <= q (lanes past the end read bin 0's
+      // first slot and store nothing)
+      const uint32_t qq = q < total ? q : 0u;
+      uint32_t lo = 0, hi = NB;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= qq)
+          lo = mid;
+        else
+          hi = mid;
       }
+      v[k] = bv[((bin0 + lo) << lz) + (qq - pre[lo])];
+      dst[k] = q < total ? base + q : ~0ull;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kStripItems; ++k)
-      if (dst[k] < n) out[dst[k]] = v[k];
+      if (dst[k] < n) ov[dst[k]] = v[k];
   }
 }
 
