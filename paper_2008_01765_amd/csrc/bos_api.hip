@@ -34,7 +34,8 @@ uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
 size_t comparison_sort_split_bytes(uint64_t n);
 hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
                                 const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
-                                uint32_t lds, hipStream_t s);
+                                uint32_t lds, hipStream_t s, bool split);
+hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, uint32_t blocks, hipStream_t s);
 hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs, uint32_t total,
                                hipStream_t s);
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
@@ -321,10 +322,35 @@ bool use_route_kernel(const Plan& pl, uint32_t t) {
   return !pl.generic && pl.lz >= 4 && pl.lz <= 11 && pl.klev[t] >= 1;
 }
 
-// The split form of the last pass (persistent last pass that leaves the sorted
-// bins in slot array (P + 1) & 1, then scan + strip) applies to bos_sort's
-// plans of two or more passes routed by the register-resident kernel.
+// The split form of the last pass (a last pass that leaves the sorted bins in
+// slot array (P + 1) & 1, then scan + strip) applies to sorting plans of two
+// or more passes routed by the register-resident kernel.
 bool split_last(const Plan& pl) { return pl.P >= 2 && pl.L > 0 && use_route_kernel(pl, pl.P - 1); }
+
+// Where a sort's comparison phase ping-pongs besides `out`: with the split
+// last pass, the two tag arrays (2 B Z 4 >= n R bytes; the bins sit in slot
+// array (P + 1) & 1 until the strip); otherwise slot array (P + 1) & 1 itself
+// (the fused last pass reads slot array P & 1 and writes `out` directly).
+char* sort_tmp(const Plan& pl, char* ws) {
+  return ws + (split_last(pl) ? pl.off_tag[0] : pl.off_rec[(pl.P + 1) & 1]);
+}
+
+// One instance's entry of a batched strip after its split last pass.
+StripSeg strip_seg(const Plan& pl, char* ws, void* out, uint32_t first) {
+  const uint32_t t = pl.P - 1;
+  StripSeg g;
+  std::memset(&g, 0, sizeof(g));
+  g.binned = ws + pl.off_rec[t & 1];
+  g.loads = reinterpret_cast<const uint32_t*>(ws + pl.off_loads);
+  g.bsum = reinterpret_cast<unsigned long long*>(ws + pl.off_status) + 2;
+  g.out = out;
+  g.n = pl.n;
+  g.nblocks = pl.nblocks_last;
+  g.klev = pl.klev[t];
+  g.lz = pl.lz;
+  g.first = first;
+  return g;
+}
 
 // Enqueue one attempt of the routing phase; `out` receives the stripped bins.
 // split: last pass in split form (requires split_last(pl); `out` must not be
@@ -458,11 +484,12 @@ struct BatchJob {
   void* other = nullptr;
   uint32_t merges = 0;
   bool special = false;   // routed on its own (single bin, or a Z without batched kernels)
+  bool split = false;     // last pass in split form, then the batched strip
 };
 
 struct BLaunch {
-  int kind = 0;  // 0 fill, 1 route, 2 tile sort, 3 merge pass, 4 status, 5 plain routing of one job
-  int mode = 0;  // route: bit 0 first, bit 1 last
+  int kind = 0;  // 0 fill, 1 route, 2 tile sort, 3 merge pass, 4 status, 5 plain routing of one job, 6 strip
+  int mode = 0;  // route: bit 0 first, bit 1 last, bit 2 split last pass
   uint32_t lz = 0;    // route: log2 Z of the launch
   uint32_t tile = 0;  // tile sort: records per tile
   uint32_t nsegs = 0, blocks = 0, threads = 0, lds = 0, total = 0, job = 0;
@@ -506,10 +533,11 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     j.ws = ws ? ws + off : nullptr;
     off = align_up(off + j.pl.total);
     j.merges = comparison_sort_passes(j.n, j.pl.tile);
-    char* tmp = j.ws ? j.ws + j.pl.off_rec[(j.pl.P + 1) & 1] : nullptr;
+    char* tmp = j.ws ? sort_tmp(j.pl, j.ws) : nullptr;
     j.start = (j.merges % 2 == 0) ? j.out : static_cast<void*>(tmp);
     j.other = (j.merges % 2 == 0) ? static_cast<void*>(tmp) : j.out;
     j.special = j.pl.L == 0 || !use_route_kernel(j.pl, 0) || !batched_lz(j.pl.lz);
+    j.split = split_last(j.pl);
   }
   b->tab_base = align_up(off);
   if (!b->batched) {
@@ -536,7 +564,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
   for (const BatchJob& j : b->jobs)
     if (j.n && !j.special) maxP = std::max(maxP, j.pl.P);
   for (uint32_t t = 0; t < maxP; ++t) {
-    for (int mode : {3, 1, 0, 2}) {
+    for (int mode : {3, 1, 0, 2, 6}) {
       for (uint32_t lz = 4; lz <= 11; ++lz) {
         std::vector<PassArgs> segs;
         std::vector<uint32_t> starts;
@@ -544,7 +572,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
         for (const BatchJob& j : b->jobs) {
           if (!j.n || j.special || t >= j.pl.P || j.pl.lz != lz) continue;
           const bool first = t == 0, last = t + 1 == j.pl.P;
-          if (((first ? 1 : 0) | (last ? 2 : 0)) != mode) continue;
+          if (((first ? 1 : 0) | (last ? 2 : 0) | (last && j.split ? 4 : 0)) != mode) continue;
           PassArgs a;
           std::memset(&a, 0, sizeof(a));
           const Plan& pl = j.pl;
@@ -568,6 +596,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
           a.klev = pl.klev[t];
           a.attempt = 0;
           a.fin = 1;
+          if (last && j.split) a.loads = reinterpret_cast<uint32_t*>(j.ws + pl.off_loads);
           segs.push_back(a);
           starts.push_back(blocks);
           blocks += uint32_t(pl.B >> pl.klev[t]);
@@ -588,6 +617,22 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
         b->launches.push_back(l);
       }
     }
+  }
+  {
+    // strip after the split last passes (all of them are done by now)
+    std::vector<StripSeg> f;
+    uint32_t blocks = 0;
+    for (const BatchJob& j : b->jobs)
+      if (j.n && !j.special && j.split) {
+        f.push_back(strip_seg(j.pl, j.ws, j.start, blocks));
+        blocks += j.pl.nblocks_last;
+      }
+    BLaunch l;
+    l.kind = 6;
+    l.nsegs = uint32_t(f.size());
+    l.blocks = blocks;
+    l.tab = push_table(tab, f);
+    if (l.nsegs) b->launches.push_back(l);
   }
   for (uint32_t i = 0; i < count; ++i)
     if (b->jobs[i].n && b->jobs[i].special) {
@@ -665,7 +710,7 @@ hipError_t enqueue_batch(const Batch& b, char* tables, hipStream_t s, uint32_t* 
         e = launch_route_batched(b.rec, l.lz, (l.mode & 1) != 0, (l.mode & 2) != 0,
                                  reinterpret_cast<const PassArgs*>(tables + l.tab),
                                  reinterpret_cast<const uint32_t*>(tables + l.aux), l.nsegs, l.blocks, l.threads,
-                                 l.lds, s);
+                                 l.lds, s, (l.mode & 4) != 0);
         break;
       case 2:
         e = launch_sort_batched(b.rec, 0, l.tile, reinterpret_cast<const SortSeg*>(tables + l.tab), l.nsegs, l.total,
@@ -682,9 +727,12 @@ hipError_t enqueue_batch(const Batch& b, char* tables, hipStream_t s, uint32_t* 
         break;
       case 5: {
         const BatchJob& j = b.jobs[l.job];
-        e = enqueue_routing(j.pl, j.in, j.start, j.seed, 0, 1, j.ws, s);
+        e = enqueue_routing(j.pl, j.in, j.start, j.seed, 0, 1, j.ws, s, -1, j.split);
         break;
       }
+      case 6:
+        e = launch_strip_batched(b.rec, reinterpret_cast<const StripSeg*>(tables + l.tab), l.nsegs, l.blocks, s);
+        break;
     }
     if (e != hipSuccess) return e;
   }
@@ -847,14 +895,11 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
   char* w = static_cast<char*>(ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
   // The comparison sort ping-pongs between `out` and a free region of the
-  // workspace; the routing output goes where the sort must start so that the
-  // result lands in `out`.  The free region: with the split last pass, the
-  // two tag arrays (2 B Z 4 >= n R bytes; the bins sit in slot array
-  // (P + 1) & 1 until the strip); otherwise slot array (P + 1) & 1 itself (the
-  // last pass reads slot array P & 1).
+  // workspace (sort_tmp); the routing output goes where the sort must start
+  // so that the result lands in `out`.
   const uint32_t passes = comparison_sort_passes(n, pl.tile);
   const bool split = split_last(pl);
-  void* tmp = split ? static_cast<void*>(w + pl.off_tag[0]) : static_cast<void*>(w + pl.off_rec[(pl.P + 1) & 1]);
+  void* tmp = sort_tmp(pl, w);
   void* start = (passes % 2 == 0) ? out : tmp;
   void* other = (passes % 2 == 0) ? tmp : out;
   uint32_t attempts = 0;
@@ -937,7 +982,7 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
           return BOS_ERR_HIP;
         bos_params qi = q;
         qi.seed = inst[i].seed;
-        const bos_status rs = run_routing(j.pl, qi, j.in, j.start, 1, j.ws, s, &att, &ovf, 1, prev);
+        const bos_status rs = run_routing(j.pl, qi, j.in, j.start, 1, j.ws, s, &att, &ovf, 1, prev, j.split);
         if (rs == BOS_OK) {
           void* result = nullptr;
           if (launch_comparison_sort(j.pl.rec, j.start, j.other, j.n, j.pl.tile,
@@ -984,8 +1029,10 @@ constexpr uint64_t kStepMinQuantum = 1ull << 21;
 
 size_t step_round_bytes(uint32_t count) {
   // every job adds at most one entry of each kind; each table starts aligned
-  // (fill, 2 per route group of at most 4 kinds x 8 Z, 5 tile sizes, merge)
-  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + 2 * sizeof(SortSeg)) + 74 * kAlign;
+  // (fill, 2 per route group of at most 5 kinds x 8 Z, strip, 5 tile sizes,
+  // merge)
+  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + sizeof(StripSeg) + 2 * sizeof(SortSeg)) +
+         90 * kAlign;
 }
 
 size_t bos_step_workspace_bytes(uint32_t count) {
@@ -1043,9 +1090,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       left -= std::min(left, k * c);
     }
   }
-  auto tmp_buf = [&](uint32_t i) -> void* {
-    return static_cast<char*>(jobs[i].ws) + plans[i].off_rec[(plans[i].P + 1) & 1];
-  };
+  auto tmp_buf = [&](uint32_t i) -> void* { return sort_tmp(plans[i], static_cast<char*>(jobs[i].ws)); };
   auto start_buf = [&](uint32_t i) -> void* { return (merges[i] % 2 == 0) ? jobs[i].out : tmp_buf(i); };
   auto other_buf = [&](uint32_t i) -> void* { return (merges[i] % 2 == 0) ? tmp_buf(i) : jobs[i].out; };
 
@@ -1059,9 +1104,9 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
     uint32_t blocks = 0, threads = 64, lds = 0, items0 = 0;
   };
   struct Round {
-    size_t o_fill = 0, o_tile[5] = {0, 0, 0, 0, 0}, o_merge = 0;
-    uint32_t nfill = 0, ntile[5] = {0, 0, 0, 0, 0}, nmerge = 0;
-    uint32_t tiles[5] = {0, 0, 0, 0, 0}, mtiles = 0;
+    size_t o_fill = 0, o_strip = 0, o_tile[5] = {0, 0, 0, 0, 0}, o_merge = 0;
+    uint32_t nfill = 0, nstrip = 0, ntile[5] = {0, 0, 0, 0, 0}, nmerge = 0;
+    uint32_t sblocks = 0, tiles[5] = {0, 0, 0, 0, 0}, mtiles = 0;
     std::map<uint32_t, RouteGroup> route;  // key: mode * 16 + lz
     std::vector<uint32_t> whole;  // jobs routed by the per-job path in this round
   };
@@ -1073,6 +1118,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
   for (uint32_t r = 0; r < kStepRounds; ++r) {
     Round rd;
     std::vector<FillSeg> fills;
+    std::vector<StripSeg> strips;
     std::vector<SortSeg> tiles[5], mseg;
     bool any = false;
     for (uint32_t i = 0; i < count; ++i) {
@@ -1093,7 +1139,8 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
         unsigned long long* status = reinterpret_cast<unsigned long long*>(w + pl.off_status);
         if (ph == 0) fills.push_back(FillSeg{status, 2 + pl.nblocks_last, 0});
         const bool first = ph == 0, last = ph + 1 == pl.P;
-        const int mode = (first ? 1 : 0) | (last ? 2 : 0);
+        const bool split = last && split_last(pl);
+        const int mode = (first ? 1 : 0) | (last ? 2 : 0) | (split ? 4 : 0);
         PassArgs a;
         std::memset(&a, 0, sizeof(a));
         a.x_in = j.in;
@@ -1115,6 +1162,11 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
         a.klev = pl.klev[ph];
         a.attempt = j.attempt;
         a.fin = 1;
+        if (split) {
+          a.loads = reinterpret_cast<uint32_t*>(w + pl.off_loads);
+          strips.push_back(strip_seg(pl, w, start_buf(i), rd.sblocks));
+          rd.sblocks += pl.nblocks_last;
+        }
         const uint32_t items = uint32_t(pl.B >> pl.klev[ph]);
         RouteGroup& g = rd.route[uint32_t(mode) * 16u + pl.lz];
         if (g.args.empty()) g.items0 = items;
@@ -1154,6 +1206,8 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
     if (!any) break;
     rd.nfill = uint32_t(fills.size());
     rd.o_fill = push_table(tab, fills);
+    rd.nstrip = uint32_t(strips.size());
+    rd.o_strip = push_table(tab, strips);
     for (auto& kv : rd.route) {
       kv.second.o_args = push_table(tab, kv.second.args);
       kv.second.o_starts = push_table(tab, kv.second.starts);
@@ -1187,7 +1241,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
     for (uint32_t i : rd.whole) {
       if (e != hipSuccess) break;
       e = enqueue_routing(plans[i], jobs[i].in, start_buf(i), jobs[i].seed, jobs[i].attempt, 1,
-                          static_cast<char*>(jobs[i].ws), s);
+                          static_cast<char*>(jobs[i].ws), s, -1, split_last(plans[i]));
     }
     for (const auto& kv : rd.route) {
       if (e != hipSuccess) break;
@@ -1195,12 +1249,14 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       const uint32_t lz = kv.first % 16u;
       const RouteGroup& g = kv.second;
       if (g.args.size() == 1)  // one job: the persistent kernel of the single-sort path
-        e = launch_route(R, g.args[0], (m & 1) != 0, (m & 2) != 0, g.items0, num_cus(), s, false);
+        e = launch_route(R, g.args[0], (m & 1) != 0, (m & 2) != 0, g.items0, num_cus(), s, (m & 4) != 0);
       else
         e = launch_route_batched(R, lz, (m & 1) != 0, (m & 2) != 0, reinterpret_cast<const PassArgs*>(dtab + g.o_args),
                                  reinterpret_cast<const uint32_t*>(dtab + g.o_starts), uint32_t(g.args.size()),
-                                 g.blocks, g.threads, g.lds, s);
+                                 g.blocks, g.threads, g.lds, s, (m & 4) != 0);
     }
+    if (e == hipSuccess && rd.nstrip)
+      e = launch_strip_batched(R, reinterpret_cast<const StripSeg*>(dtab + rd.o_strip), rd.nstrip, rd.sblocks, s);
     for (int ti = 0; ti < 5; ++ti)
       if (e == hipSuccess && rd.ntile[ti])
         e = launch_sort_batched(R, 0, kTiles[ti], reinterpret_cast<const SortSeg*>(dtab + rd.o_tile[ti]), rd.ntile[ti],

@@ -120,6 +120,17 @@ struct SortSeg {
   uint32_t count;    // blocks of the instance in the launch (tiles of the tile sort or merge)
 };
 
+// One instance of a batched scan + strip after a split last pass.
+struct StripSeg {
+  const void* binned;            // bin gb's reals in slots gb*Z .. (the last pass's rec_out)
+  const uint32_t* loads;         // real count per bin
+  unsigned long long* bsum;      // real count per routing block; scanned in place
+  void* out;
+  uint64_t n;
+  uint32_t nblocks, klev, lz;
+  uint32_t first;                // first strip workgroup of the segment in the launch
+};
+
 // One instance's status words to initialise before its first routing pass.
 struct FillSeg {
   unsigned long long* p;  // status word, ticket, look-back words

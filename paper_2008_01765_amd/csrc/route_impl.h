@@ -555,7 +555,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   using T = typename RecOf<R>::T;
   constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0, SPLIT = (MODE & 4) != 0;
   constexpr bool FULL = (MODE & 16) != 0;  // every lane holds slots: no lane guards
-  static_assert(!SPLIT || (LAST && !FIRST && !BATCH), "the split form is a persistent last pass");
+  static_assert(!SPLIT || (LAST && !FIRST), "the split form is a last pass that is not also the first");
   // the split form sorts its bins (bos_sort); bos_orp's permuting finish
   // keeps the fused form, whose one-block-per-workgroup launch has the
   // registers it needs
@@ -928,7 +928,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     }
   };
 
-  if constexpr (!LAST && BATCH) {
+  if constexpr (BATCH && (!LAST || SPLIT)) {
     if (FIRST && !aligned) {
       staged_first_load(item0);
     } else {
@@ -936,6 +936,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       finish_load(item0, tv);
     }
     process(item0);
+    if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item0, klev, srec, stag, srhi, saux, sload);
   } else if constexpr (!LAST || SPLIT) {
     // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...  The
     // next block's loads are issued after the current one is done: with no

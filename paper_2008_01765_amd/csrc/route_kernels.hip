@@ -63,10 +63,12 @@ hipError_t launch_route_b_r16_z10(const PassArgs* segs, const uint32_t* blk_star
 
 // Batched routing pass (all segments share record size, Z and mode); batches
 // are built for Z in {256, 512, 1024} and, for tests of the overflow path, 32.
+// split: the split form of a last pass that is not also the first.
 hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
                                 const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
-                                uint32_t lds, hipStream_t s) {
-  const int mode = (first ? 1 : 0) | (last ? 2 : 0);
+                                uint32_t lds, hipStream_t s, bool split) {
+  if (split && (first || !last)) return hipErrorInvalidValue;
+  const int mode = (first ? 1 : 0) | (last ? 2 : 0) | (split ? 4 : 0);
   if (rec == 8) {
     switch (lz) {
       case 5: return launch_route_b_r8_z5(segs, blk_start, nsegs, blocks, threads, lds, mode, s);

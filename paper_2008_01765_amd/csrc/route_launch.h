@@ -58,6 +58,7 @@ hipError_t launch_route_bm(const PassArgs* segs, const uint32_t* blk_start, uint
     case 0: return launch_route_bt<R, LZ, 0>(segs, blk_start, nsegs, blocks, threads, lds, s);
     case 1: return launch_route_bt<R, LZ, 1>(segs, blk_start, nsegs, blocks, threads, lds, s);
     case 2: return launch_route_bt<R, LZ, 2>(segs, blk_start, nsegs, blocks, threads, lds, s);
+    case 6: return launch_route_bt<R, LZ, 6>(segs, blk_start, nsegs, blocks, threads, lds, s);
     default: return launch_route_bt<R, LZ, 3>(segs, blk_start, nsegs, blocks, threads, lds, s);
   }
 }

@@ -18,7 +18,7 @@ constexpr uint32_t kStripThreads = 256, kStripItems = 8;
 // In-place exclusive scan of v[0..count) by one workgroup: each thread sums a
 // contiguous chunk, the chunk sums are scanned in LDS, then each thread
 // rewrites its chunk.
-__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(unsigned long long* v, uint32_t count) {
+__device__ __forceinline__ void scan_blocks(unsigned long long* v, uint32_t count) {
   __shared__ unsigned long long part[kScanThreads];
   const uint32_t t = threadIdx.x;
   const uint32_t per = (count + kScanThreads - 1) / kScanThreads;
@@ -41,17 +41,21 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(unsigned long
   }
 }
 
+__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(unsigned long long* v, uint32_t count) {
+  scan_blocks(v, count);
+}
+
 // One routing block's bins (NB = 2^klev of them) to out[boff[blk] ..).
 template <int R>
-__global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned_, const uint32_t* loads,
-                                                              const unsigned long long* boff, void* out_, uint64_t n,
-                                                              uint32_t klev, uint32_t lz) {
+__device__ __forceinline__ void strip_block(const void* binned_, const uint32_t* loads,
+                                            const unsigned long long* boff, void* out_, uint64_t n, uint32_t klev,
+                                            uint32_t lz, uint64_t blk) {
   using T = typename RecOf<R>::T;
   __shared__ uint32_t pre[513];  // NB <= 512: a block has at most 8192 slots, Z >= 16
   const T* binned = static_cast<const T*>(binned_);
   T* out = static_cast<T*>(out_);
   const uint32_t tid = threadIdx.x, NB = 1u << klev;
-  const uint64_t blk = blockIdx.x, bin0 = blk << klev;
+  const uint64_t bin0 = blk << klev;
   for (uint32_t j = tid; j < NB; j += kStripThreads) pre[j + 1] = loads[bin0 + j];
   __syncthreads();
   if (tid == 0) {
@@ -88,6 +92,48 @@ __global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned
     for (uint32_t k = 0; k < kStripItems; ++k)
       if (dst[k] < n) ov[dst[k]] = v[k];
   }
+}
+
+template <int R>
+__global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned, const uint32_t* loads,
+                                                              const unsigned long long* boff, void* out, uint64_t n,
+                                                              uint32_t klev, uint32_t lz) {
+  strip_block<R>(binned, loads, boff, out, n, klev, lz, blockIdx.x);
+}
+
+// Batched forms: one scan workgroup per instance; the strip workgroups of
+// instance s are blockIdx.x in [segs[s].first, segs[s].first + nblocks).
+__global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel_b(const StripSeg* segs) {
+  const StripSeg sg = segs[blockIdx.x];
+  scan_blocks(sg.bsum, sg.nblocks);
+}
+
+template <int R>
+__global__ __launch_bounds__(kStripThreads) void strip_kernel_b(const StripSeg* segs, uint32_t nsegs) {
+  uint32_t lo = 0, hi = nsegs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segs[mid].first <= blockIdx.x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const StripSeg sg = segs[lo];
+  strip_block<R>(sg.binned, sg.loads, sg.bsum, sg.out, sg.n, sg.klev, sg.lz, blockIdx.x - sg.first);
+}
+
+// Batched scan + strip over nsegs instances (device table segs, `blocks` strip
+// workgroups in all).
+hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, uint32_t blocks, hipStream_t s) {
+  if (nsegs == 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_blocks_kernel_b, dim3(nsegs), dim3(kScanThreads), 0, s, segs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || blocks == 0) return e;
+  if (rec == 8)
+    hipLaunchKernelGGL(strip_kernel_b<8>, dim3(blocks), dim3(kStripThreads), 0, s, segs, nsegs);
+  else
+    hipLaunchKernelGGL(strip_kernel_b<16>, dim3(blocks), dim3(kStripThreads), 0, s, segs, nsegs);
+  return hipGetLastError();
 }
 
 hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
