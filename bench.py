@@ -47,9 +47,11 @@ def parse():
     ap.add_argument("--batched-count", type=int, default=4096,
                     help="instances of the batched workload (log-uniform 2^10..2^20, 16 B, total <= 2^28); 0 skips")
     ap.add_argument("--batched-steps", type=int, default=3)
-    ap.add_argument("--serving-requests", type=int, default=1024,
-                    help="requests of the serving workload (log-uniform 2^12..2^24, 16 B, Poisson); 0 skips")
-    ap.add_argument("--serving-load", type=float, default=0.7,
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="measured requests of the serving workload (log-uniform 2^12..2^24, 16 B, Poisson); 0 skips")
+    ap.add_argument("--serving-warmup", type=int, default=200,
+                    help="requests before the measured ones in every serving trace (not counted)")
+    ap.add_argument("--serving-loads", default="0.5,0.7,0.9",
                     help="offered load as a fraction of the sequential server's capacity")
     ap.add_argument("--sweep-steps", type=int, default=2,
                     help="steps per (Z, k) point of the n=2^28 sweep; 0 skips the sweep")
@@ -224,18 +226,21 @@ def bench_batched(args, torch, bos, inputs):
 def bench_serving(args, torch, bos, inputs):
     """Poisson arrivals of sort requests (log-uniform 2^12..2^24 records of
     16 B) served by the continuous-batching server and by a first-come
-    first-served loop of single sorts, at the same offered load."""
+    first-served loop of single sorts, on the same arrival trace, at each
+    offered load (a fraction of the sequential capacity).  Every trace has
+    `serving_warmup` requests before the `serving_requests` measured ones."""
     import numpy as np
 
     from paper_2008_01765_amd import serving
 
     dev = torch.device("cuda", 0)
-    sizes = inputs.request_sizes(args.serving_requests, 12, 24, seed=7)
+    total_req = args.serving_warmup + args.serving_requests
+    sizes = inputs.request_sizes(total_req, 12, 24, seed=7)
     master_n = 1 << 25
     master = bos.from_numpy(inputs.records(master_n, 16, args.data_seed + 2), dev)
     starts = (inputs.splitmix64(99, 0, len(sizes)) % np.uint64(master_n - (1 << 24) + 1)).astype(np.int64)
     reqs = [master[int(s0):int(s0) + int(n)] for s0, n in zip(starts, sizes)]
-    # service time of each request alone (warm), to set the arrival rate
+    # sequential capacity: every request sorted alone, back to back (warm)
     big = int(np.argmax(sizes))
     bos.sort(reqs[big], seed=0)
     torch.cuda.synchronize()
@@ -244,30 +249,53 @@ def bench_serving(args, torch, bos, inputs):
         bos.sort(r, seed=i)
     torch.cuda.synchronize()
     busy = time.perf_counter() - t0
-    rate = args.serving_load * len(reqs) / busy
-    arr = serving.poisson_arrivals(len(reqs), rate, seed=11)
+    # closed loop: every request submitted at once (this also warms the
+    # allocator for the server's outputs and workspaces)
     srv = serving.Server(hbm_budget_bytes=64 << 30)
-    w = srv.submit(reqs[big], seed=0)  # warm the server's allocations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    futs = [srv.submit(r, seed=i) for i, r in enumerate(reqs)]
     srv.run_until_idle()
-    srv = serving.Server(hbm_budget_bytes=64 << 30)
-    futs = serving.run_trace(srv, reqs, arr)
-    lat_b = [f.latency for f in futs]
-    span_b = max(f.finished for f in futs) - min(f.arrival for f in futs)
-    ok = all(f.status == bos.OK for f in futs) and w.status == bos.OK
-    lat_s, _ = serving.run_trace_sequential(reqs, arr)
-    span_s = max(a + l for a, l in zip(arr, lat_s))
-    total = int(sizes.sum())
-    res = {"requests": len(reqs), "rec_bytes": 16, "sizes": "log-uniform 2^12..2^24", "tuning": args.tuning_used,
-           "arrivals": "Poisson, %.1f req/s (%.0f%% of the sequential capacity)" % (rate, 100 * args.serving_load),
-           "hbm_budget_GiB": 64, "steps": srv.steps, "peak_resident_GiB": round(srv.peak_used / 2 ** 30, 2),
-           "batching": {"p50_ms": round(serving.percentile(lat_b, 50) * 1e3, 3),
-                        "p99_ms": round(serving.percentile(lat_b, 99) * 1e3, 3),
-                        "Melem/s": round(total / span_b / 1e6, 1)},
-           "sequential": {"p50_ms": round(serving.percentile(lat_s, 50) * 1e3, 3),
-                          "p99_ms": round(serving.percentile(lat_s, 99) * 1e3, 3),
-                          "Melem/s": round(total / span_s / 1e6, 1)},
-           "correct": ok}
-    del reqs, master, futs, srv
+    torch.cuda.synchronize()
+    closed = time.perf_counter() - t0
+    ok = all(f.status == bos.OK for f in futs)
+    closed_steps = srv.steps
+    del futs, srv
+    meas = slice(args.serving_warmup, total_req)
+    measured_records = int(sizes[meas].sum())
+
+    def summary(lat, fin, arr):
+        span = max(fin[meas]) - min(arr[meas])
+        return {"p50_ms": round(serving.percentile(lat[meas], 50) * 1e3, 3),
+                "p99_ms": round(serving.percentile(lat[meas], 99) * 1e3, 3),
+                "Melem/s": round(measured_records / span / 1e6, 1)}
+
+    loads = {}
+    for rho in [float(v) for v in args.serving_loads.split(",") if v]:
+        rate = rho * len(reqs) / busy
+        arr = serving.poisson_arrivals(len(reqs), rate, seed=11)
+        srv = serving.Server(hbm_budget_bytes=64 << 30)
+        futs = serving.run_trace(srv, reqs, arr)
+        t_b = futs[0].arrival - arr[0]  # the trace's clock origin
+        lat_b = [f.latency for f in futs]
+        fin_b = [f.finished - t_b for f in futs]
+        ok = ok and all(f.status == bos.OK for f in futs)
+        steps, peak = srv.steps, srv.peak_used
+        del futs, srv  # the outputs
+        lat_s, _ = serving.run_trace_sequential(reqs, arr, keep_outputs=False)
+        fin_s = [a + l for a, l in zip(arr, lat_s)]
+        loads["%.2g" % rho] = {"rate_req_s": round(rate, 1), "steps": steps,
+                               "peak_resident_GiB": round(peak / 2 ** 30, 2),
+                               "batching": summary(lat_b, fin_b, arr), "sequential": summary(lat_s, fin_s, arr)}
+        bos.release_workspaces()
+    res = {"requests": args.serving_requests, "warmup_requests": args.serving_warmup, "rec_bytes": 16,
+           "sizes": "log-uniform 2^12..2^24", "tuning": args.tuning_used,
+           "arrivals": "Poisson at rho x the sequential capacity (%.1f req/s at rho = 1)" % (len(reqs) / busy),
+           "hbm_budget_GiB": 64,
+           "closed_loop": {"sequential_ms": round(busy * 1e3, 1), "batching_ms": round(closed * 1e3, 1),
+                           "batching_steps": closed_steps},
+           "loads": loads, "correct": ok}
+    del reqs, master
     bos.release_workspaces()
     torch.cuda.empty_cache()
     return res

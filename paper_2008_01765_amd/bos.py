@@ -248,12 +248,15 @@ def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_b
     return (outs, rep.as_dict()) if report else outs
 
 
-def sort_step(jobs, rec, p, step_ws, stream=None):
-    """Advance every unfinished Job in the ctypes array `jobs` by one phase
-    (bos_sort_step); returns the number of jobs still unfinished."""
+def sort_step(jobs, rec, p, step_ws, stream=None, count_left=True):
+    """Advance the unfinished Jobs in the ctypes array `jobs` by one step
+    (bos_sort_step); returns the number of jobs still unfinished (None with
+    count_left=False)."""
     count = len(jobs)
     _check(lib().bos_sort_step(jobs, count, rec, C.byref(p), C.c_void_p(step_ws.data_ptr()), step_ws.numel(),
                                _stream(stream)))
+    if not count_left:
+        return None
     return sum(1 for j in jobs if j.phase != PHASE_DONE)
 
 

@@ -14,6 +14,8 @@
 #include <map>
 #include <string>
 #include <mutex>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "bos.h"
@@ -150,6 +152,7 @@ bos_params resolve(const bos_params* p) {
 // the caller leaves z, k or tile at 0.
 std::mutex g_tune_mu;
 std::vector<bos_tune_entry> g_tune;
+uint64_t g_tune_gen = 0;  // bumped by every bos_set_tuning
 
 uint32_t size_class(uint64_t n) {
   uint32_t c = 0;
@@ -301,6 +304,49 @@ uint64_t routing_bytes(const Plan& pl) {
 }
 
 bos_status hip_status(hipError_t e) { return e == hipSuccess ? BOS_OK : BOS_ERR_HIP; }
+
+// Plans of the step engine, which re-plans every resident job on every step:
+// memoised on everything make_plan reads (size, record, the parameters it
+// uses and the tuning table's generation).
+struct PlanKey {
+  uint64_t n, gen;
+  uint32_t rec, z, k, tile, bits, flags;
+  bool operator==(const PlanKey& o) const {
+    return n == o.n && gen == o.gen && rec == o.rec && z == o.z && k == o.k && tile == o.tile && bits == o.bits &&
+           flags == o.flags;
+  }
+};
+struct PlanKeyHash {
+  size_t operator()(const PlanKey& x) const {
+    uint64_t h = x.n * 0x9E3779B97F4A7C15ull ^ x.gen;
+    for (uint32_t v : {x.rec, x.z, x.k, x.tile, x.bits, x.flags}) h = (h ^ v) * 0x100000001B3ull;
+    return size_t(h ^ (h >> 29));
+  }
+};
+std::mutex g_plan_mu;
+std::unordered_map<PlanKey, std::pair<bos_status, Plan>, PlanKeyHash> g_plans;
+
+bos_status make_plan_cached(uint64_t n, int rec, const bos_params& q, Plan* pl) {
+  uint64_t gen;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    gen = g_tune_gen;
+  }
+  const PlanKey key{n, gen, uint32_t(rec), q.z, q.k, q.tile, q.min_security_bits, q.flags};
+  {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      *pl = it->second.second;
+      return it->second.first;
+    }
+  }
+  const bos_status st = make_plan(n, rec, q, true, pl);
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  if (g_plans.size() >= 4096) g_plans.clear();  // bounded: a server sees a limited set of sizes at a time
+  g_plans.emplace(key, std::make_pair(st, *pl));
+  return st;
+}
 
 uint32_t g_num_cus = 0;
 uint32_t num_cus() {
@@ -1062,7 +1108,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       continue;
     }
     if (!j.in || !j.out || j.in == j.out) return BOS_ERR_INVALID_ARG;
-    const bos_status st = make_plan(j.n, R, q, true, &plans[i]);
+    const bos_status st = make_plan_cached(j.n, R, q, &plans[i]);
     if (st != BOS_OK) return st;
     if (!j.ws || j.ws_bytes < plans[i].total) return BOS_ERR_WORKSPACE;
     merges[i] = comparison_sort_passes(j.n, plans[i].tile);
@@ -1329,6 +1375,7 @@ bos_status bos_set_tuning(const bos_tune_entry* entries, uint32_t count) {
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune.assign(entries, entries + count);
+    ++g_tune_gen;
   }
   bos_release_cache();  // captured batches were planned with the old table
   return BOS_OK;

@@ -3,10 +3,11 @@
 Requests (record tensors already in HBM) queue up in arrival order.  Between
 scheduler steps the server admits queued requests while their HBM footprint
 (input + output + the sort's workspace) fits under the budget; each step then
-advances every resident request by one phase of its sort (a routing pass of the
-butterfly network of Section 3.2, the overflow check, the tile sort or a merge
-pass of the comparison sort that Section 3.3 applies to the permuted array)
-through one bos_sort_step call.  Requests of different sizes and phases share
+runs one bos_sort_step call over the resident requests: a budget of device
+work handed out in admission order, each request running as many phases of its
+sort as fit (a phase is a routing pass of the butterfly network of Section 3.2,
+the tile sort or a merge pass of the comparison sort that Section 3.3 applies
+to the permuted array; the overflow check closes the step).  Requests of different sizes and phases share
 the step's launches, and new requests start at the next step boundary
 (continuous batching).  A finished request frees its memory and records its
 completion time.
@@ -15,9 +16,11 @@ Every result is the one bos.sort gives for the same input alone: the sort's
 output is the sorted array whatever the seed, and each request keeps its own
 seed and attempt counter through the steps.
 """
+import ctypes
 import time
 from collections import deque
 
+import numpy as np
 import torch
 
 from . import bos
@@ -47,6 +50,13 @@ def percentile(values, q):
     return v[int(rank) - 1]
 
 
+# layout of bos.Job (bos_job in bos.h) for a numpy view of a job array
+_JOB_DTYPE = np.dtype([("in_", "<u8"), ("out", "<u8"), ("n", "<u8"), ("seed", "<u8"), ("ws", "<u8"),
+                       ("ws_bytes", "<u8"), ("phase", "<u4"), ("attempt", "<u4"), ("status", "<u4"),
+                       ("reserved", "<u4")])
+assert _JOB_DTYPE.itemsize == ctypes.sizeof(bos.Job)
+
+
 class Future:
     """Handle of one submitted request."""
 
@@ -66,6 +76,7 @@ class Future:
         self.footprint = 0
         self.phase = 0
         self._ws = None
+        self._step0 = 0
 
     def done(self):
         return self.finished is not None
@@ -108,6 +119,7 @@ class Server:
         self.steps = 0
         self._next_id = 0
         self._step_ws = None
+        self._jobs = None  # ctypes array of the resident requests' jobs, in self.active's order
         self.completed = []
 
     # ---- admission ---------------------------------------------------------
@@ -136,17 +148,39 @@ class Server:
         return f
 
     def _admit(self):
-        k = admit_prefix([f.footprint for f in self.queue], self.budget - self.used)
+        # lazily: admission stops at the first request that does not fit
+        k = admit_prefix((f.footprint for f in self.queue), self.budget - self.used)
+        if k == 0:
+            return 0
         now = self.clock()
+        new = []
         for _ in range(k):
             f = self.queue.popleft()
             f.admitted = now
+            f._step0 = self.steps
             f.out = torch.empty_like(f.input)
             if f.n:
                 f._ws = torch.empty(max(bos.workspace_bytes(f.n, self.rec, self.params), 256), dtype=torch.uint8,
                                     device=self.device)
             self.used += f.footprint
-            self.active.append(f)
+            new.append(f)
+        # job array: the resident jobs' entries (phase and attempt as the
+        # last step left them) followed by the new ones
+        old = len(self.active)
+        jobs = (bos.Job * (old + k))()
+        if old:
+            np.frombuffer(jobs, dtype=_JOB_DTYPE, count=old)[:] = np.frombuffer(self._jobs, dtype=_JOB_DTYPE,
+                                                                               count=old)
+        for i, f in enumerate(new):
+            j = jobs[old + i]
+            j.in_ = f.input.data_ptr()
+            j.out = f.out.data_ptr()
+            j.n = f.n
+            j.seed = f.seed & 0xFFFFFFFFFFFFFFFF
+            j.ws = f._ws.data_ptr() if f._ws is not None else None
+            j.ws_bytes = f._ws.numel() if f._ws is not None else 0
+        self._jobs = jobs
+        self.active.extend(new)
         self.peak_used = max(self.peak_used, self.used)
         return k
 
@@ -155,44 +189,42 @@ class Server:
         return not self.queue and not self.active
 
     def step(self):
-        """Admit what fits, advance every resident request by one phase and
-        retire the finished ones; returns the requests finished in this step."""
-        self._admit()
+        """Admit what fits, run one bos_sort_step over the resident requests
+        and retire the finished ones; returns the requests finished in this
+        step."""
+        if self.queue:
+            self._admit()
         if not self.active:
             return []
         cnt = len(self.active)
-        jobs = (bos.Job * cnt)()
-        for i, f in enumerate(self.active):
-            j = jobs[i]
-            j.in_ = f.input.data_ptr()
-            j.out = f.out.data_ptr()
-            j.n = f.n
-            j.seed = f.seed & 0xFFFFFFFFFFFFFFFF
-            j.ws = f._ws.data_ptr() if f._ws is not None else None
-            j.ws_bytes = f._ws.numel() if f._ws is not None else 0
-            j.phase = f.phase
-            j.attempt = f.attempts
-            j.status = 0
+        jobs = self._jobs  # bos_sort_step updates phase, attempt and status in place
         need = bos.step_workspace_bytes(cnt)
         if self._step_ws is None or self._step_ws.numel() < need:
             self._step_ws = torch.empty(2 * need, dtype=torch.uint8, device=self.device)
-        bos.sort_step(jobs, self.rec, self.params, self._step_ws, self.stream)
+        bos.sort_step(jobs, self.rec, self.params, self._step_ws, self.stream, count_left=False)
         self.steps += 1
         now = self.clock()
-        done, keep = [], []
-        for i, f in enumerate(self.active):
-            f.phase = jobs[i].phase
-            f.attempts = jobs[i].attempt
-            f.steps += 1
-            if jobs[i].phase == bos.PHASE_DONE:
-                f.finished = now
-                f.status = jobs[i].status
-                f._ws = None
-                self.used -= f.footprint
-                done.append(f)
-            else:
-                keep.append(f)
-        self.active = keep
+        view = np.frombuffer(jobs, dtype=_JOB_DTYPE, count=cnt)
+        fin = view["phase"] == bos.PHASE_DONE
+        if not fin.any():
+            return []
+        done = []
+        for i in np.flatnonzero(fin).tolist():
+            f = self.active[i]
+            f.phase = bos.PHASE_DONE
+            f.attempts = int(view["attempt"][i])
+            f.status = int(view["status"][i])
+            f.steps = self.steps - f._step0
+            f.finished = now
+            f._ws = None
+            self.used -= f.footprint
+            done.append(f)
+        keep = np.flatnonzero(~fin)
+        left = (bos.Job * len(keep))()
+        if len(keep):
+            np.frombuffer(left, dtype=_JOB_DTYPE, count=len(keep))[:] = view[keep]
+        self._jobs = left
+        self.active = [self.active[i] for i in keep.tolist()]
         self.completed.extend(done)
         return done
 
@@ -223,10 +255,11 @@ def run_trace(server, tensors, arrivals, seeds=None, spin=True):
     return futs
 
 
-def run_trace_sequential(tensors, arrivals, z=0, k=0, seeds=None, clock=time.perf_counter, stream=None):
+def run_trace_sequential(tensors, arrivals, z=0, k=0, seeds=None, clock=time.perf_counter, stream=None,
+                         keep_outputs=True):
     """First-come first-served baseline: each request sorted alone by bos.sort
     once it has arrived and the previous one has finished.  Returns
-    (latencies, outputs)."""
+    (latencies, outputs); outputs is None with keep_outputs=False."""
     t0 = clock()
     lat, outs = [], []
     for i, t in enumerate(tensors):
@@ -235,8 +268,10 @@ def run_trace_sequential(tensors, arrivals, z=0, k=0, seeds=None, clock=time.per
         o = bos.sort(t, seed=i if seeds is None else seeds[i], z=z, k=k, stream=stream)
         torch.cuda.synchronize()
         lat.append(clock() - t0 - arrivals[i])
-        outs.append(o)
-    return lat, outs
+        if keep_outputs:
+            outs.append(o)
+        del o
+    return lat, (outs if keep_outputs else None)
 
 
 def poisson_arrivals(count, rate_per_s, seed=11):
