@@ -171,6 +171,35 @@ size_t bos_step_workspace_bytes(uint32_t count);
 bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p, void* step_ws,
                          size_t step_ws_bytes, void* stream);
 
+/* Pipelined continuous batching.  A stepper (host object, one per request
+ * loop) lets each call enqueue its step and then wait for the PREVIOUS call's
+ * step, so the device runs one step while the host plans the next; the
+ * schedule, outputs and attempt counts are those of bos_sort_step.
+ *   - A job whose phases have all been enqueued shows phase P + 1 + M (M =
+ *     merge passes of its plan) until the call after its last step; it turns
+ *     BOS_PHASE_DONE once that step has completed and the overflow check of
+ *     its routing (run at the end of the step where the routing finished) has
+ *     passed.  An overflowed job goes back to phase 0 with attempt + 1, as in
+ *     bos_sort_step; phases already enqueued for the overflowed attempt still
+ *     run and their writes are redone.
+ *   - Jobs are matched across calls by their ws pointer: between calls the
+ *     caller may reorder the array, drop jobs that are BOS_PHASE_DONE and add
+ *     new ones (phase 0, attempt 0, reserved 0); it must not change a
+ *     resident job's fields.  `reserved` carries the library's state.
+ *   - Call until every job is BOS_PHASE_DONE (a call with nothing left to
+ *     enqueue only collects the previous step).  A job that ends with
+ *     BOS_ERR_OVERFLOW may still be read by the step in flight: reuse its
+ *     buffers only in stream order.
+ * step_ws: device, 2 x bos_step_workspace_bytes(count) bytes (the two steps
+ * in flight use one half each; it may be a different buffer on each call).
+ * The stepper holds two pinned host buffers and two events; it is not
+ * thread-safe.  Errors as bos_sort_step; INVALID_ARG for a null stepper. */
+typedef struct bos_stepper bos_stepper;
+bos_stepper* bos_stepper_create(void); /* NULL without a GPU or on allocation failure */
+void bos_stepper_destroy(bos_stepper* st); /* waits for a step in flight and drops its results */
+bos_status bos_sort_step_async(bos_stepper* st, bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p,
+                               void* step_ws, size_t step_ws_bytes, void* stream);
+
 /* Oblivious bitonic sort (Batcher) of the same records by (key, payload): the
  * GPU baseline the bucket sort is measured against.  ws: bos_bitonic_workspace_bytes. */
 size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec);

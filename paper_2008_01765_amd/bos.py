@@ -73,7 +73,8 @@ KERNEL_KINDS = {1: "route_first", 2: "route_mid", 3: "route_last", 4: "route_sin
 EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "bos_batched_workspace_bytes",
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
-           "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning"]
+           "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning",
+           "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async"]
 
 _lib = None
 
@@ -102,6 +103,12 @@ def lib():
         L.bos_step_workspace_bytes.restype = C.c_size_t
         L.bos_sort_step.argtypes = [C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
         L.bos_sort_step.restype = C.c_int
+        L.bos_stepper_create.argtypes = []
+        L.bos_stepper_create.restype = vp
+        L.bos_stepper_destroy.argtypes = [vp]
+        L.bos_stepper_destroy.restype = None
+        L.bos_sort_step_async.argtypes = [vp, C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
+        L.bos_sort_step_async.restype = C.c_int
         L.bos_set_tuning.argtypes = [C.POINTER(TuneEntry), u32]
         L.bos_set_tuning.restype = C.c_int
         L.bos_get_tuning.argtypes = [C.POINTER(TuneEntry), u32]
@@ -262,6 +269,34 @@ def sort_step(jobs, rec, p, step_ws, stream=None, count_left=True):
 
 def step_workspace_bytes(count):
     return lib().bos_step_workspace_bytes(count)
+
+
+class Stepper:
+    """A pipelined sequence of steps (bos_stepper): each step() call enqueues
+    one step and collects the previous one (bos_sort_step_async)."""
+
+    def __init__(self):
+        self._h = lib().bos_stepper_create()
+        if not self._h:
+            raise BosError(UNSUPPORTED, "libbos: bos_stepper_create failed")
+
+    def step(self, jobs, rec, p, step_ws, stream=None):
+        """One call of bos_sort_step_async over the ctypes Job array `jobs`;
+        step_ws must hold 2 * step_workspace_bytes(len(jobs)) bytes."""
+        _check(lib().bos_sort_step_async(self._h, jobs, len(jobs), rec, C.byref(p),
+                                         C.c_void_p(step_ws.data_ptr() if step_ws is not None else 0),
+                                         step_ws.numel() if step_ws is not None else 0, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().bos_stepper_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def set_tuning(entries):

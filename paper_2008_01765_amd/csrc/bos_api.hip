@@ -14,6 +14,7 @@
 #include <map>
 #include <string>
 #include <mutex>
+#include <new>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -1085,15 +1086,68 @@ size_t bos_step_workspace_bytes(uint32_t count) {
   return align_up(kStepRounds * step_round_bytes(count) + size_t(count) * 12 + 4 * kAlign);
 }
 
-bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p, void* step_ws,
-                         size_t step_ws_bytes, void* stream) {
+}  // extern "C"
+
+// State of a pipelined sequence of steps (bos_sort_step_async): the previous
+// step, still in flight when a call returns, and the pinned host buffers of
+// the two alternating steps.
+struct bos_stepper {
+  struct Routed {
+    void* ws;
+    uint32_t attempt, slot;  // slot: index in the step's status words
+  };
+  struct Finished {
+    void* ws;
+    uint32_t attempt;
+  };
+  struct Half {
+    char* tab = nullptr;  // pinned: the step's tables
+    size_t tab_cap = 0;
+    uint32_t* st = nullptr;  // pinned: the step's status words
+    size_t st_cap = 0;
+    hipEvent_t ev = nullptr;
+    std::vector<Routed> routed;
+    std::vector<Finished> finished;
+  };
+  Half half[2];
+  uint64_t calls = 0;
+  bool pending = false;  // the previous call's step is in flight
+  int device = -1;
+};
+
+namespace {
+
+// Grow a pinned host buffer (its previous contents are not kept).
+bool grow_pinned(void** p, size_t* cap, size_t need) {
+  if (*cap >= need) return true;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  const size_t n = std::max<size_t>(need + need / 2, 4096);
+  if (hipHostMalloc(p, n, hipHostMallocDefault) != hipSuccess) return false;
+  *cap = n;
+  return true;
+}
+
+// The last phase index of a job plus one: in a pipelined sequence, the phase
+// of a job whose every phase has been enqueued and whose result is not yet
+// known.
+uint32_t after_last_phase(const Plan& pl, uint32_t merges) { return pl.P + 1 + merges; }
+
+bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p, void* step_ws_arg,
+                     size_t step_ws_bytes_arg, void* stream, bos_stepper* ctx) {
   if (!has_gpu()) return BOS_ERR_UNSUPPORTED;
   if (count && !jobs) return BOS_ERR_INVALID_ARG;
   const bos_params q = resolve(p);
   const int R = int(rec);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (count == 0) return BOS_OK;
-  if (!step_ws || step_ws_bytes < bos_step_workspace_bytes(count)) return BOS_ERR_WORKSPACE;
+  if (count == 0 && !(ctx && ctx->pending)) return BOS_OK;
+  // a pipelined step uses one half of step_ws; the other may still be read
+  // by the step in flight
+  const uint32_t par = ctx ? uint32_t(ctx->calls & 1) : 0u;
+  const size_t step_ws_bytes = ctx ? (step_ws_bytes_arg / 2) & ~(kAlign - 1) : step_ws_bytes_arg;
+  void* step_ws = ctx && step_ws_arg ? static_cast<char*>(step_ws_arg) + par * step_ws_bytes : step_ws_arg;
+  if (count && (!step_ws || step_ws_bytes < bos_step_workspace_bytes(count))) return BOS_ERR_WORKSPACE;
   const bool batchable = !(q.flags & BOS_GENERIC_ROUTING);
   std::vector<Plan> plans(count);
   std::vector<uint32_t> merges(count, 0), allowed(count, 0);
@@ -1112,7 +1166,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
     if (st != BOS_OK) return st;
     if (!j.ws || j.ws_bytes < plans[i].total) return BOS_ERR_WORKSPACE;
     merges[i] = comparison_sort_passes(j.n, plans[i].tile);
-    if (j.phase > plans[i].P + merges[i]) return BOS_ERR_INVALID_ARG;
+    if (j.phase > plans[i].P + merges[i] + (ctx ? 1u : 0u)) return BOS_ERR_INVALID_ARG;
   }
   {
     bool head = true;
@@ -1122,6 +1176,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
       if (j.phase == BOS_PHASE_DONE) continue;
       const uint64_t c = j.n + kStepFixed;
       const uint64_t remaining = uint64_t(plans[i].P) + 1 + merges[i] - j.phase;
+      if (remaining == 0) continue;  // every phase enqueued (pipelined), awaiting its result
       uint64_t k;
       if (head) {
         quantum = std::max(quantum, c);
@@ -1161,6 +1216,14 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
   std::vector<char> tab;
   std::vector<uint32_t> phase(count);
   for (uint32_t i = 0; i < count; ++i) phase[i] = jobs[i].phase;
+  // a job's last phase: done (synchronous step), or enqueued with its result
+  // pending until the step has run (pipelined)
+  std::vector<uint32_t> finished;
+  auto finish = [&](uint32_t i) -> uint32_t {
+    if (!ctx) return BOS_PHASE_DONE;
+    finished.push_back(i);
+    return after_last_phase(plans[i], merges[i]);
+  };
   for (uint32_t r = 0; r < kStepRounds; ++r) {
     Round rd;
     std::vector<FillSeg> fills;
@@ -1236,7 +1299,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
           tiles[ti].push_back(SortSeg{start_buf(i), nullptr, j.n, 0, nullptr, rd.tiles[ti], c});
           rd.tiles[ti] += c;
         }
-        phase[i] = merges[i] == 0 ? BOS_PHASE_DONE : pl.P + 1;
+        phase[i] = merges[i] == 0 ? finish(i) : pl.P + 1;
       } else {
         const uint32_t pass = ph - (pl.P + 1);
         const uint32_t mt = merge_tile_records(R);
@@ -1246,7 +1309,7 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
         mseg.push_back(SortSeg{src, dst, j.n, uint64_t(pl.tile) << pass, reinterpret_cast<uint64_t*>(w + pl.off_split),
                                rd.mtiles, c});
         rd.mtiles += c;
-        phase[i] = pass + 1 >= merges[i] ? BOS_PHASE_DONE : ph + 1;
+        phase[i] = pass + 1 >= merges[i] ? finish(i) : ph + 1;
       }
     }
     if (!any) break;
@@ -1278,7 +1341,19 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
   const size_t o_sto = align_up(tab.size());
   if (o_sto + align_up(st_ptr.size() * 4) > step_ws_bytes) return BOS_ERR_WORKSPACE;
   char* dtab = static_cast<char*>(step_ws);
-  if (!tab.empty() && hipMemcpyAsync(dtab, tab.data(), tab.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+  bos_stepper::Half* hf = ctx ? &ctx->half[par] : nullptr;
+  const char* htab = tab.data();
+  if (hf) {
+    // the tables go through pinned memory so that the upload does not wait
+    // for the step in flight (this half's previous step has completed)
+    if (!grow_pinned(reinterpret_cast<void**>(&hf->tab), &hf->tab_cap, tab.size()) ||
+        !grow_pinned(reinterpret_cast<void**>(&hf->st), &hf->st_cap, st_ptr.size() * 4 + 4))
+      return BOS_ERR_HIP;
+    if (!tab.empty()) std::memcpy(hf->tab, tab.data(), tab.size());
+    htab = hf->tab;
+    if (!hf->ev && hipEventCreateWithFlags(&hf->ev, hipEventDisableTiming) != hipSuccess) return BOS_ERR_HIP;
+  }
+  if (!tab.empty() && hipMemcpyAsync(dtab, htab, tab.size(), hipMemcpyHostToDevice, s) != hipSuccess)
     return BOS_ERR_HIP;
   hipError_t e = hipSuccess;
   for (const Round& rd : rounds) {
@@ -1313,34 +1388,117 @@ bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_p
         e = launch_sort_batched(R, 2, 0, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
     }
   }
-  std::vector<uint32_t> st_host(st_ptr.size(), 0);
+  uint32_t* st_host_ptr = nullptr;
+  std::vector<uint32_t> st_host(ctx ? 0 : st_ptr.size(), 0);
   if (e == hipSuccess && !st_ptr.empty()) {
     uint32_t* d_out = reinterpret_cast<uint32_t*>(dtab + o_sto);
+    st_host_ptr = hf ? hf->st : st_host.data();
     e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(dtab + o_stp), d_out,
                             uint32_t(st_ptr.size()), s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(st_host.data(), d_out, st_host.size() * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st_host_ptr, d_out, st_ptr.size() * 4, hipMemcpyDeviceToHost, s);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return BOS_ERR_HIP;
-  for (uint32_t i = 0; i < count; ++i) {
-    if (jobs[i].phase == BOS_PHASE_DONE) continue;
-    jobs[i].phase = phase[i];
-    if (phase[i] == BOS_PHASE_DONE) jobs[i].status = BOS_OK;
-  }
-  for (size_t t = 0; t < st_job.size(); ++t) {
-    if (st_host[t] == 0) continue;
-    bos_job& j = jobs[st_job[t]];
+  auto overflowed = [&](bos_job& j) {
     if (j.attempt < q.max_retries) {
       ++j.attempt;
       j.phase = 0;
       j.status = BOS_OK;
+      j.reserved = 0;
     } else {
       j.phase = BOS_PHASE_DONE;
       j.status = BOS_ERR_OVERFLOW;
     }
+  };
+  if (!ctx) {
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return BOS_ERR_HIP;
+    for (uint32_t i = 0; i < count; ++i) {
+      if (jobs[i].phase == BOS_PHASE_DONE) continue;
+      jobs[i].phase = phase[i];
+      if (phase[i] == BOS_PHASE_DONE) jobs[i].status = BOS_OK;
+    }
+    for (size_t t = 0; t < st_job.size(); ++t)
+      if (st_host[t] != 0) overflowed(jobs[st_job[t]]);
+    return BOS_OK;
   }
+  // Pipelined: this step stays in flight; the previous one is waited for and
+  // its routing checks and completions are applied.  Jobs are found by their
+  // workspace, so the caller may reorder, drop finished or add jobs between
+  // calls.
+  const bool enqueued = !rounds.empty();
+  if (e == hipSuccess && enqueued) e = hipEventRecord(hf->ev, s);
+  if (e != hipSuccess) return BOS_ERR_HIP;
+  for (uint32_t i = 0; i < count; ++i)
+    if (jobs[i].phase != BOS_PHASE_DONE) jobs[i].phase = phase[i];
+  bos_stepper::Half& prev = ctx->half[par ^ 1u];
+  if (ctx->pending) {
+    if (hipEventSynchronize(prev.ev) != hipSuccess) return BOS_ERR_HIP;
+    std::unordered_map<void*, uint32_t> at;
+    at.reserve(count * 2);
+    for (uint32_t i = 0; i < count; ++i) at[jobs[i].ws] = i;
+    for (const bos_stepper::Routed& r : prev.routed) {
+      auto it = at.find(r.ws);
+      if (it == at.end()) continue;
+      bos_job& j = jobs[it->second];
+      if (j.phase == BOS_PHASE_DONE || j.attempt != r.attempt) continue;
+      if (prev.st[r.slot] != 0)
+        overflowed(j);
+      else
+        j.reserved = 1;  // this attempt's routing checked
+    }
+    for (const bos_stepper::Finished& f : prev.finished) {
+      auto it = at.find(f.ws);
+      if (it == at.end()) continue;
+      bos_job& j = jobs[it->second];
+      if (j.phase == BOS_PHASE_DONE || j.attempt != f.attempt || j.reserved != 1) continue;
+      j.phase = BOS_PHASE_DONE;
+      j.status = BOS_OK;
+    }
+    prev.routed.clear();
+    prev.finished.clear();
+  }
+  hf->routed.clear();
+  hf->finished.clear();
+  for (size_t t = 0; t < st_job.size(); ++t)
+    hf->routed.push_back({jobs[st_job[t]].ws, jobs[st_job[t]].attempt, uint32_t(t)});
+  for (uint32_t i : finished) hf->finished.push_back({jobs[i].ws, jobs[i].attempt});
+  ctx->pending = enqueued;
+  ++ctx->calls;
   return BOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bos_status bos_sort_step(bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p, void* step_ws,
+                         size_t step_ws_bytes, void* stream) {
+  return step_impl(jobs, count, rec, p, step_ws, step_ws_bytes, stream, nullptr);
+}
+
+bos_stepper* bos_stepper_create(void) {
+  if (!has_gpu()) return nullptr;
+  bos_stepper* st = new (std::nothrow) bos_stepper();
+  if (st && hipGetDevice(&st->device) != hipSuccess) st->device = -1;
+  return st;
+}
+
+void bos_stepper_destroy(bos_stepper* st) {
+  if (!st) return;
+  for (bos_stepper::Half& h : st->half) {
+    if (h.ev) {
+      (void)hipEventSynchronize(h.ev);
+      (void)hipEventDestroy(h.ev);
+    }
+    if (h.tab) (void)hipHostFree(h.tab);
+    if (h.st) (void)hipHostFree(h.st);
+  }
+  delete st;
+}
+
+bos_status bos_sort_step_async(bos_stepper* st, bos_job* jobs, uint32_t count, bos_rec rec, const bos_params* p,
+                               void* step_ws, size_t step_ws_bytes, void* stream) {
+  if (!st) return BOS_ERR_INVALID_ARG;
+  return step_impl(jobs, count, rec, p, step_ws, step_ws_bytes, stream, st);
 }
 
 size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec) {

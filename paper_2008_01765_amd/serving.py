@@ -18,6 +18,7 @@ seed and attempt counter through the steps.
 """
 import ctypes
 import time
+import weakref
 from collections import deque
 
 import numpy as np
@@ -61,7 +62,7 @@ class Future:
     """Handle of one submitted request."""
 
     def __init__(self, server, rid, tensor, seed, arrival):
-        self._server = server
+        self._server = weakref.ref(server)  # the server holds its resident futures, not the reverse
         self.id = rid
         self.input = tensor
         self.n = tensor.shape[0]
@@ -85,7 +86,10 @@ class Future:
         """Block (driving the server) until this request is done; returns its
         sorted tensor or raises BosError if every routing attempt overflowed."""
         while not self.done():
-            self._server.step()
+            server = self._server()
+            if server is None:
+                raise RuntimeError("the server of this request was discarded before it finished")
+            server.step()
         if self.status != bos.OK:
             raise bos.BosError(self.status, "libbos: " + bos.lib().bos_status_string(self.status).decode())
         return self.out
@@ -101,11 +105,14 @@ class Server:
     hbm_budget_bytes bounds the sum of the resident requests' footprints;
     z, k, max_retries and min_security_bits are shared by every request (the
     step entry point takes one parameter block).  All requests must use the
-    same record type.
+    same record type.  pipeline=True drives the steps through a stepper
+    (bos_sort_step_async): the device runs one step while the host plans the
+    next, and a request is reported finished one call after its last step
+    was enqueued, as soon as that step has completed.
     """
 
     def __init__(self, hbm_budget_bytes=64 << 30, z=0, k=0, max_retries=3, min_security_bits=80,
-                 device=None, stream=None, clock=time.perf_counter):
+                 device=None, stream=None, clock=time.perf_counter, pipeline=True):
         self.budget = int(hbm_budget_bytes)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
@@ -120,7 +127,8 @@ class Server:
         self._next_id = 0
         self._step_ws = None
         self._jobs = None  # ctypes array of the resident requests' jobs, in self.active's order
-        self.completed = []
+        self._stepper = bos.Stepper() if pipeline else None
+        self.completed = 0  # requests finished so far (their futures belong to the callers)
 
     # ---- admission ---------------------------------------------------------
     def footprint(self, n, rec):
@@ -197,11 +205,16 @@ class Server:
         if not self.active:
             return []
         cnt = len(self.active)
-        jobs = self._jobs  # bos_sort_step updates phase, attempt and status in place
-        need = bos.step_workspace_bytes(cnt)
+        jobs = self._jobs  # the step updates phase, attempt and status in place
+        need = bos.step_workspace_bytes(cnt) * (2 if self._stepper else 1)
         if self._step_ws is None or self._step_ws.numel() < need:
+            # a replaced buffer is released in stream order, after the step
+            # in flight that may still read it
             self._step_ws = torch.empty(2 * need, dtype=torch.uint8, device=self.device)
-        bos.sort_step(jobs, self.rec, self.params, self._step_ws, self.stream, count_left=False)
+        if self._stepper:
+            self._stepper.step(jobs, self.rec, self.params, self._step_ws, self.stream)
+        else:
+            bos.sort_step(jobs, self.rec, self.params, self._step_ws, self.stream, count_left=False)
         self.steps += 1
         now = self.clock()
         view = np.frombuffer(jobs, dtype=_JOB_DTYPE, count=cnt)
@@ -225,7 +238,7 @@ class Server:
             np.frombuffer(left, dtype=_JOB_DTYPE, count=len(keep))[:] = view[keep]
         self._jobs = left
         self.active = [self.active[i] for i in keep.tolist()]
-        self.completed.extend(done)
+        self.completed += len(done)
         return done
 
     def run_until_idle(self):

@@ -24,11 +24,11 @@ def _hosts(sizes, rec, data_seed):
             for i, n in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("rec,z", [(16, 512), (8, 512), (16, 256)])
-def test_mix_equals_alone(rec, z):
+@pytest.mark.parametrize("rec,z,pipeline", [(16, 512, True), (8, 512, True), (16, 256, True), (16, 512, False)])
+def test_mix_equals_alone(rec, z, pipeline):
     sizes = [4096, 1 << 16, 0, 1, 5000, 70000, 1 << 12, 333, 1 << 18, 9999]
     hosts = _hosts(sizes, rec, 300)
-    srv = serving.Server(hbm_budget_bytes=1 << 34, z=z, min_security_bits=0)
+    srv = serving.Server(hbm_budget_bytes=1 << 34, z=z, min_security_bits=0, pipeline=pipeline)
     futs = []
     ts = [bos.from_numpy(h) for h in hosts]
     # requests join while others are mid-flight
@@ -59,7 +59,7 @@ def test_budget_bounds_resident_footprint():
         assert srv.used <= srv.budget
         assert sum(f.footprint for f in srv.active) == srv.used
     assert srv.peak_used <= srv.budget
-    assert len(srv.completed) == len(futs)
+    assert srv.completed == len(futs)
     # first come, first served: admission times follow submission order
     adm = [f.admitted for f in futs]
     assert adm == sorted(adm)
@@ -67,7 +67,8 @@ def test_budget_bounds_resident_footprint():
         np.testing.assert_array_equal(bos.to_numpy(f.out), cf.sorted_records(h))
 
 
-def test_overflow_retries_in_mix_match_alone():
+@pytest.mark.parametrize("pipeline", [True, False])
+def test_overflow_retries_in_mix_match_alone(pipeline):
     # Z = 32 overflows often at these sizes; a job that overflows retries from
     # pass 0 with the next attempt, as bos_sort does.  The oracle fixes the
     # attempt count of every job.
@@ -76,7 +77,7 @@ def test_overflow_retries_in_mix_match_alone():
     sizes = [1 << 14, 9000, 1 << 13, 6000, 20000]
     hosts = _hosts(sizes, 8, 5)
     seeds = [11, 12, 13, 14, 15]
-    srv = serving.Server(hbm_budget_bytes=1 << 34, z=32, min_security_bits=0, max_retries=30)
+    srv = serving.Server(hbm_budget_bytes=1 << 34, z=32, min_security_bits=0, max_retries=30, pipeline=pipeline)
     futs = [srv.submit(bos.from_numpy(h), seed=s) for h, s in zip(hosts, seeds)]
     srv.run_until_idle()
     retried = 0
@@ -130,3 +131,101 @@ def test_request_over_budget_rejected():
     srv = serving.Server(hbm_budget_bytes=1 << 20, min_security_bits=0)
     with pytest.raises(bos.BosError):
         srv.submit(bos.from_numpy(inputs.records(1 << 16, 16, 1)))
+
+
+def test_server_freed_without_cycle_collector():
+    # futures refer to their server weakly: dropping the server frees it and
+    # its workspaces at once, while the futures keep their outputs
+    import gc
+    import weakref
+
+    hosts = _hosts([3000, 70000], 16, 41)
+    gc.disable()
+    try:
+        srv = serving.Server(hbm_budget_bytes=1 << 34, min_security_bits=0)
+        futs = [srv.submit(bos.from_numpy(h), seed=i) for i, h in enumerate(hosts)]
+        srv.run_until_idle()
+        assert srv.completed == 2
+        ref = weakref.ref(srv)
+        del srv
+        assert ref() is None
+    finally:
+        gc.enable()
+    for h, f in zip(hosts, futs):
+        np.testing.assert_array_equal(bos.to_numpy(f.out), cf.sorted_records(h))
+
+
+def _job(t, out, ws, seed):
+    j = bos.Job()
+    j.in_, j.out, j.n, j.seed = t.data_ptr(), out.data_ptr(), t.shape[0], seed
+    j.ws, j.ws_bytes = ws.data_ptr(), ws.numel()
+    return j
+
+
+def test_stepper_jobs_matched_by_workspace():
+    # the pipelined engine finds its jobs by workspace: the array is reversed
+    # after every call, a job joins mid-way and finished jobs leave; outputs
+    # and attempt counts equal bos_sort's (Z = 32 so that some attempts
+    # overflow and roll back)
+    import oracle
+    oracle.build(force=False)
+    sizes = [1 << 14, 9000, 1 << 13, 6000, 20000]
+    hosts = _hosts(sizes, 8, 5)
+    p = bos.params(0, 32, 0, 0, 30, 0)
+    ts = [bos.from_numpy(h) for h in hosts]
+    outs = [torch.empty_like(t) for t in ts]
+    wss = [torch.empty(bos.workspace_bytes(t.shape[0], 8, p), dtype=torch.uint8, device="cuda") for t in ts]
+    jobs = [_job(t, o, w, 11 + i) for i, (t, o, w) in enumerate(zip(ts, outs, wss))]
+    late = jobs.pop()  # joins after two calls
+    st = bos.Stepper()
+    sws = torch.empty(2 * bos.step_workspace_bytes(len(sizes)), dtype=torch.uint8, device="cuda")
+    done = {}
+    calls = 0
+    while jobs or late is not None:
+        arr = (bos.Job * len(jobs))(*jobs)
+        st.step(arr, 8, p, sws)
+        calls += 1
+        jobs = []
+        for j in arr:
+            if j.phase == bos.PHASE_DONE:
+                done[j.ws] = (j.status, j.attempt)
+            else:
+                jobs.append(j)
+        jobs.reverse()
+        if calls == 2 and late is not None:
+            jobs.append(late)
+            late = None
+        assert calls < 10000
+    st.close()
+    retried = 0
+    for i, (h, w) in enumerate(zip(hosts, wss)):
+        want = oracle.sort(h, 11 + i, z=32, max_retries=30)
+        status, attempt = done[w.data_ptr()]
+        assert status == bos.OK and attempt + 1 == want["report"]["attempts"]
+        retried += attempt > 0
+        np.testing.assert_array_equal(bos.to_numpy(outs[i]), want["out"])
+    assert retried > 0
+
+
+def test_stepper_rejects_null_and_small_workspace():
+    t = bos.from_numpy(inputs.records(5000, 16, 1))
+    out = torch.empty_like(t)
+    p = bos.params(0, 512, 0, 0, 3, 0)
+    ws = torch.empty(bos.workspace_bytes(5000, 16, p), dtype=torch.uint8, device="cuda")
+    arr = (bos.Job * 1)(_job(t, out, ws, 1))
+    one = bos.step_workspace_bytes(1)
+    rc = bos.lib().bos_sort_step_async(None, arr, 1, 16, bos.C.byref(p), bos.C.c_void_p(ws.data_ptr()), one, None)
+    assert rc == bos.INVALID_ARG
+    st = bos.Stepper()
+    small = torch.empty(one, dtype=torch.uint8, device="cuda")  # one half is too small
+    with pytest.raises(bos.BosError) as e:
+        st.step(arr, 16, p, small)
+    assert e.value.status == bos.WORKSPACE
+    sws = torch.empty(2 * one, dtype=torch.uint8, device="cuda")
+    for _ in range(1000):
+        st.step(arr, 16, p, sws)
+        if arr[0].phase == bos.PHASE_DONE:
+            break
+    assert arr[0].status == bos.OK
+    np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(bos.to_numpy(t)))
+    st.close()
