@@ -155,8 +155,9 @@ size_t bos_step_workspace_bytes(uint32_t count);
  * the tile sort and the merge passes of the comparison sort: phase values
  * 0..P-1, P, P+1.. (P = routing passes of the job's plan).  Array order is
  * priority: a step runs at least one phase of the first unfinished job and
- * hands a work budget of about twice that phase to the jobs after it, in
- * order, each running as many phases as fit (possibly none); jobs in the same
+ * hands a work budget of about twice that phase (at most 2^23 records'
+ * worth) to the jobs after it, in order, each running as many phases as fit
+ * (possibly none); jobs in the same
  * phase kind share launches, so requests admitted between steps run alongside
  * those already on the device.  The overflow check (Algorithm 3.1's abort) happens at the
  * end of the step in which a job's routing finished: an overflowed job goes

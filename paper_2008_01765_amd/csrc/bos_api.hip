@@ -1060,9 +1060,10 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
 // A step is a budget of device work, handed out in array order (the caller
 // puts its oldest job first).  The first unfinished job always runs at least
 // one phase (several if they are cheap: up to kStepMinQuantum); later jobs
-// backfill the rest of a budget of twice that, each as many phases as fit,
-// so small requests run several phases next to one phase of a large request
-// and large requests keep their order.  The phase cost model is
+// backfill a budget of twice that, capped at kStepBackfillCap, each as many
+// phases as fit, so small requests run several phases next to one phase of a
+// large request, large requests keep their order, and a large head request
+// keeps at least two thirds of the device (its latency sets the tail).  The phase cost model is
 // n + kStepFixed records (kStepFixed stands for the launch overhead of a
 // phase).  The overflow check of an attempt is
 // speculative: a job that finished its routing passes goes on to the
@@ -1073,6 +1074,7 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
 constexpr uint32_t kStepRounds = 32;           // sub-rounds per step at most
 constexpr uint64_t kStepFixed = 1ull << 17;    // launch overhead, in records
 constexpr uint64_t kStepMinQuantum = 1ull << 21;
+constexpr uint64_t kStepBackfillCap = 1ull << 23;
 
 size_t step_round_bytes(uint32_t count) {
   // every job adds at most one entry of each kind; each table starts aligned
@@ -1181,7 +1183,7 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
       if (head) {
         quantum = std::max(quantum, c);
         k = std::max<uint64_t>(1, kStepMinQuantum / c);
-        left = 2 * quantum;
+        left = std::min<uint64_t>(2 * quantum, kStepBackfillCap);
         head = false;
       } else {
         k = left / c;
