@@ -30,7 +30,7 @@ hipError_t launch_pass(int rec, const PassArgs& a, bool first, bool last, uint32
 hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
                         hipStream_t s, bool split);
 hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
-                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, hipStream_t s);
+                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, uint32_t tile, hipStream_t s);
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                   hipStream_t s, void** result);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
@@ -396,6 +396,7 @@ StripSeg strip_seg(const Plan& pl, char* ws, void* out, uint32_t first) {
   g.klev = pl.klev[t];
   g.lz = pl.lz;
   g.first = first;
+  g.tile = pl.tile;
   return g;
 }
 
@@ -451,7 +452,7 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
     if (e != hipSuccess) return e;
     if (split_pass) {
       prof_begin(BOS_K_STRIP, 0, 2 * rec_bytes, s);
-      e = launch_strip(pl.rec, a.rec_out, a.loads, a.scan, out, pl.n, nitems, pl.klev[t], pl.lz, s);
+      e = launch_strip(pl.rec, a.rec_out, a.loads, a.scan, out, pl.n, nitems, pl.klev[t], pl.lz, pl.tile, s);
       prof_end(s);
       if (e != hipSuccess) return e;
     }

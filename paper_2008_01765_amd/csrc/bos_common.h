@@ -129,6 +129,8 @@ struct StripSeg {
   uint64_t n;
   uint32_t nblocks, klev, lz;
   uint32_t first;                // first strip workgroup of the segment in the launch
+  uint32_t tile;                 // records per tile of the comparison sort's first phase
+  uint32_t pad;
 };
 
 // One instance's status words to initialise before its first routing pass.

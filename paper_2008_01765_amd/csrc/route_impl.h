@@ -432,15 +432,98 @@ __device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint3
   }
 }
 
+// Oblivious compaction of every final bin in LDS: the bin's reals move to
+// its first slots.  The last level leaves each bin's reals interleaved with
+// dummies; this is the tight compaction network a MergeSplit level runs
+// (conditional swaps at distances 1, 2, .., Z/2, each decided by swap_bit from
+// the prefix counts of the reals), over one bin of Z slots with the reals as
+// the marks.  Lane lq of the bin's Z/16 lanes holds slots 16 lq + e; stages at
+// distances below 16 pair registers, the others exchange through the bin's own
+// LDS slots.  On return rv holds this lane's 16 slots after the compaction.
+template <int R, int LZ, bool FULL>
+__device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* spfx,
+                                            uint32_t* swave, uint32_t klev, typename RecOf<R>::T (&rv)[16]) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t Z = 1u << LZ, ZP = Z + (Z >> 4), HL = Z >> 4;
+  const uint32_t tid = threadIdx.x, m = Z << klev;
+  const bool active = FULL || tid < (m >> 4);
+  const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
+  const uint32_t bbase = S * ZP;
+  uint32_t tv[16];
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) {
+    rv[e] = active ? srec[bbase + 17u * lq + e] : zero_rec<T>();
+    tv[e] = active ? stag[bbase + 17u * lq + e] : kDummyTag;
+  }
+  // prefix counts of the reals
+  uint32_t pm[16];
+  uint32_t run = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) {
+    pm[e] = run;
+    run += tv[e] != kDummyTag ? 1u : 0u;
+  }
+  uint32_t tot;
+  const uint32_t excl = seg_scan<HL>(active ? run : 0u, swave, &tot);
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) pm[e] += excl;
+  if (active) spfx[S * HL + lq] = pm[0];
+  // distances 1, 2, 4, 8: register pairs
+#pragma unroll
+  for (uint32_t eb = 0; eb < 4; ++eb) {
+    const uint32_t half = 1u << eb;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      if (e & half) continue;
+      const uint32_t e2 = e | half, es = e & ~(2u * half - 1u);
+      const bool b = swap_bit(pm[es], pm[es | half], half, e & (half - 1u));
+      const T r1 = rv[e], r2 = rv[e2];
+      const uint32_t t1 = tv[e], t2 = tv[e2];
+      rv[e] = sel(b, r2, r1);
+      rv[e2] = sel(b, r1, r2);
+      tv[e] = b ? t2 : t1;
+      tv[e2] = b ? t1 : t2;
+    }
+  }
+  // distances 16 .. Z/2: the partner lane is lq ^ (half / 16)
+  for (uint32_t half = 16; half < Z; half <<= 1) {
+    lds_group_sync<HL>();  // spfx written; the previous stage's reads are done
+    if (active) {
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        srec[bbase + 17u * lq + e] = rv[e];
+        stag[bbase + 17u * lq + e] = tv[e];
+      }
+    }
+    lds_group_sync<HL>();
+    const uint32_t hl = half >> 4;                   // lanes per half node
+    const uint32_t node0 = lq & ~(2u * hl - 1u);     // first lane of this lane's node
+    const uint32_t plq = lq ^ hl;
+    const uint32_t P0 = active ? spfx[S * HL + node0] : 0u, Ph = active ? spfx[S * HL + node0 + hl] : 0u;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint32_t i = 16u * (lq & (hl - 1u)) + e;  // index in the node's half
+      const bool b = active && swap_bit(P0, Ph, half, i);
+      const uint32_t pi = bbase + 17u * plq + e;
+      const T pr = active ? srec[pi] : zero_rec<T>();
+      const uint32_t pt = active ? stag[pi] : kDummyTag;
+      rv[e] = sel(b, pr, rv[e]);
+      tv[e] = b ? pt : tv[e];
+    }
+  }
+}
+
 // Last pass, split form: after the per-bin finish, global bin gb keeps its
 // reals in slots gb*Z .. gb*Z + load - 1 of rec_out, its real count in
 // loads[gb] and the block's total in scan[blk]; a scan and a strip kernel then
 // concatenate the bins (the addresses of both depend on the loads only, which
-// the method reveals).
+// the method reveals).  FIN = 3: the bins are compacted, not sorted (their
+// reals keep the order the last level left).
 template <int R, int LZ, int FIN, bool FULL>
 __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, uint32_t klev,
                                              typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
-                                             uint16_t* saux, const uint32_t* sload) {
+                                             uint16_t* saux, const uint32_t* sload, uint32_t* spfx,
+                                             uint32_t* swave) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, HL = Z >> 4;
   const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
@@ -453,7 +536,12 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
   }
   T outr[16];
   uint32_t load = 0;
-  sort_bins<R, LZ, FIN, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
+  if constexpr (FIN == 3) {
+    compact_bin<R, LZ, FULL>(srec, stag, spfx, swave, klev, outr);
+    load = active ? sload[S] : 0u;
+  } else {
+    sort_bins<R, LZ, FIN, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
+  }
   if (active) {
     // a bin holds at most Z reals (an overflowing attempt is discarded)
     const uint32_t kept = load < Z ? load : Z;
@@ -556,10 +644,11 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0, SPLIT = (MODE & 4) != 0;
   constexpr bool FULL = (MODE & 16) != 0;  // every lane holds slots: no lane guards
   static_assert(!SPLIT || (LAST && !FIRST), "the split form is a last pass that is not also the first");
-  // the split form sorts its bins (bos_sort); bos_orp's permuting finish
-  // keeps the fused form, whose one-block-per-workgroup launch has the
-  // registers it needs
-  constexpr int SPLIT_FIN = 1;
+  // the split form serves the sorts: it compacts its bins, and the strip puts
+  // in order the bins that straddle a tile of the comparison sort's first
+  // phase (the tile sort orders every other bin with its tile); bos_orp's
+  // permuting finish keeps the fused form
+  constexpr int SPLIT_FIN = 3;
   constexpr uint32_t Z = 1u << LZ, LQ = LZ + 1, TPM = 1u << (LQ - 4), ZP = Z + (Z >> 4);
   constexpr bool HAS_B = LQ > 6;
   constexpr uint32_t HALF_LANES = TPM / 2;  // lanes per bucket in layout A
@@ -936,7 +1025,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       finish_load(item0, tv);
     }
     process(item0);
-    if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item0, klev, srec, stag, srhi, saux, sload);
+    if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item0, klev, srec, stag, srhi, saux, sload, spfx, swave);
   } else if constexpr (!LAST || SPLIT) {
     // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...  The
     // next block's loads are issued after the current one is done: with no
@@ -955,7 +1044,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       const uint32_t next = item + gridDim.x;
       const bool has_next = next < nitems;
       process(item);
-      if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item, klev, srec, stag, srhi, saux, sload);
+      if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item, klev, srec, stag, srhi, saux, sload, spfx, swave);
       if (!has_next) break;
       item = next;
       lds_barrier();  // LDS of the previous block is no longer read

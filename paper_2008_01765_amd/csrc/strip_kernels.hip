@@ -8,6 +8,15 @@
 // copies each block's bins to their offsets.  Every address is a function of
 // the loads, which the method reveals (they are what a simulator of the
 // access pattern gets, Lemma 3.3).
+//
+// The bins arrive compacted but unsorted (reals in the order the last level
+// left them).  The comparison sort that follows (Section 3.3) starts with an
+// oblivious sort of fixed tiles of `tile` records: a bin inside one tile is
+// put in order with its tile, so its inner order never shows.  A bin that
+// straddles a tile boundary would hand the tiles a split that depends on the
+// input order, so the strip sorts such a bin (an oblivious network in LDS)
+// before writing it: its lower records go to the first tile.  Which bins
+// straddle depends on the loads only.
 #include "bos_common.h"
 
 namespace bos {
@@ -45,13 +54,36 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(unsigned long
   scan_blocks(v, count);
 }
 
-// One routing block's bins (NB = 2^klev of them) to out[boff[blk] ..).
+// Bitonic sort of sb[0..P2) by (key, payload) (P2 a power of two), by the
+// whole workgroup.
+template <typename T>
+__device__ __forceinline__ void lds_bitonic(T* sb, uint32_t P2) {
+  for (uint32_t size = 2; size <= P2; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = threadIdx.x; t < P2 / 2; t += kStripThreads) {
+        const uint32_t i = (t / stride) * 2 * stride + (t % stride), k = i + stride;
+        const bool asc = (i & size) == 0;
+        const T x = sb[i], y = sb[k];
+        const bool swap = asc ? rec_less(y, x) : rec_less(x, y);
+        sb[i] = sel(swap, y, x);
+        sb[k] = sel(swap, x, y);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One routing block's bins (NB = 2^klev of them) to out[boff[blk] ..); bins
+// that straddle a multiple of `tile` are sorted first (tile = 0: none).
 template <int R>
 __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t* loads,
                                             const unsigned long long* boff, void* out_, uint64_t n, uint32_t klev,
-                                            uint32_t lz, uint64_t blk) {
+                                            uint32_t lz, uint64_t blk, uint32_t tile) {
   using T = typename RecOf<R>::T;
   __shared__ uint32_t pre[513];  // NB <= 512: a block has at most 8192 slots, Z >= 16
+  __shared__ uint16_t strad[512];
+  __shared__ uint32_t nstrad;
+  __shared__ __align__(16) unsigned char sbin_raw[2048 * R];  // one bin of at most Z <= 2048 reals
   const T* binned = static_cast<const T*>(binned_);
   T* out = static_cast<T*>(out_);
   const uint32_t tid = threadIdx.x, NB = 1u << klev;
@@ -61,10 +93,39 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
   if (tid == 0) {
     pre[0] = 0;
     for (uint32_t j = 1; j <= NB; ++j) pre[j] += pre[j - 1];
+    nstrad = 0;
   }
   __syncthreads();
   const uint32_t total = pre[NB];
   const uint64_t base = boff[blk];
+  if (tile) {
+    // the straddling bins, in bin order
+    if (tid == 0) {
+      uint32_t c = 0;
+      for (uint32_t j = 0; j < NB; ++j) {
+        const uint64_t b0 = base + pre[j], b1 = base + pre[j + 1];
+        if (b1 - b0 >= 2 && b0 / tile != (b1 - 1) / tile) strad[c++] = uint16_t(j);
+      }
+      nstrad = c;
+    }
+    __syncthreads();
+    T* sb = reinterpret_cast<T*>(sbin_raw);
+    const uint32_t ns = nstrad;
+    for (uint32_t k = 0; k < ns; ++k) {
+      const uint32_t j = strad[k], ld = pre[j + 1] - pre[j];
+      uint32_t P2 = 2;
+      while (P2 < ld) P2 <<= 1;
+      const T* src = binned + ((bin0 + j) << lz);
+      for (uint32_t i = tid; i < P2; i += kStripThreads) sb[i] = i < ld ? src[i] : max_rec<T>();
+      __syncthreads();
+      lds_bitonic(sb, P2);
+      const uint64_t o = base + pre[j];
+      for (uint32_t i = tid; i < ld; i += kStripThreads)
+        if (o + i < n) out[o + i] = sb[i];
+      __syncthreads();
+    }
+  }
+  const uint32_t ns = tile ? nstrad : 0u;
   using V = typename NativeOf<T>::V;  // native vectors stay in registers
   const V* bv = reinterpret_cast<const V*>(binned);
   V* ov = reinterpret_cast<V*>(out);
@@ -85,8 +146,11 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
         else
           hi = mid;
       }
+      // a straddling bin was written sorted above
+      bool done = false;
+      for (uint32_t m = 0; m < ns; ++m) done |= strad[m] == lo;
       v[k] = bv[((bin0 + lo) << lz) + (qq - pre[lo])];
-      dst[k] = q < total ? base + q : ~0ull;
+      dst[k] = q < total && !done ? base + q : ~0ull;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kStripItems; ++k)
@@ -97,8 +161,8 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
 template <int R>
 __global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned, const uint32_t* loads,
                                                               const unsigned long long* boff, void* out, uint64_t n,
-                                                              uint32_t klev, uint32_t lz) {
-  strip_block<R>(binned, loads, boff, out, n, klev, lz, blockIdx.x);
+                                                              uint32_t klev, uint32_t lz, uint32_t tile) {
+  strip_block<R>(binned, loads, boff, out, n, klev, lz, blockIdx.x, tile);
 }
 
 // Batched forms: one scan workgroup per instance; the strip workgroups of
@@ -119,7 +183,7 @@ __global__ __launch_bounds__(kStripThreads) void strip_kernel_b(const StripSeg* 
       hi = mid;
   }
   const StripSeg sg = segs[lo];
-  strip_block<R>(sg.binned, sg.loads, sg.bsum, sg.out, sg.n, sg.klev, sg.lz, blockIdx.x - sg.first);
+  strip_block<R>(sg.binned, sg.loads, sg.bsum, sg.out, sg.n, sg.klev, sg.lz, blockIdx.x - sg.first, sg.tile);
 }
 
 // Batched scan + strip over nsegs instances (device table segs, `blocks` strip
@@ -136,18 +200,20 @@ hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, u
   return hipGetLastError();
 }
 
+// tile: records per tile of the comparison sort's first phase (bins that
+// straddle a tile boundary are sorted); lz <= 11.
 hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
-                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, hipStream_t s) {
-  if (klev > 9 || nblocks == 0) return hipErrorInvalidValue;
+                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, uint32_t tile, hipStream_t s) {
+  if (klev > 9 || lz > 11 || nblocks == 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, bsum, nblocks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (rec == 8)
     hipLaunchKernelGGL(strip_kernel<8>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, out, n, klev,
-                       lz);
+                       lz, tile);
   else
     hipLaunchKernelGGL(strip_kernel<16>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, out, n, klev,
-                       lz);
+                       lz, tile);
   return hipGetLastError();
 }
 
