@@ -107,9 +107,11 @@ size_t bos_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p);
 bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
                    void* ws, size_t ws_bytes, void* stream, bos_report* rep /* host, nullable */);
 
-/* Bucket oblivious sort (Section 3.3): the ORP's bin assignment, a per-bin
- * oblivious sort, then a non-oblivious comparison (merge) sort.  out = in sorted
- * by (key, payload); the output does not depend on seed, Z, k or tile. */
+/* Bucket oblivious sort (Section 3.3): the ORP's bin assignment (each bin
+ * compacted obliviously; a bin that straddles a tile of the first sort phase is
+ * sorted obliviously, every other bin is ordered by the oblivious tile sort),
+ * then a non-oblivious comparison (merge) sort.  out = in sorted by
+ * (key, payload); the output does not depend on seed, Z, k or tile. */
 bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
                     void* ws, size_t ws_bytes, void* stream, bos_report* rep);
 
@@ -151,7 +153,7 @@ size_t bos_step_workspace_bytes(uint32_t count);
 
 /* Continuous batching of bucket oblivious sorts (Section 3.3): run one step
  * of every unfinished job and return.  A job's phases are its routing passes
- * (Algorithm 3.1; the last pass also sorts each bin and strips the dummies),
+ * (Algorithm 3.1; the last pass also compacts each bin and strips the dummies),
  * the tile sort and the merge passes of the comparison sort: phase values
  * 0..P-1, P, P+1.. (P = routing passes of the job's plan).  Array order is
  * priority: a step runs at least one phase of the first unfinished job and

@@ -369,9 +369,10 @@ bool use_route_kernel(const Plan& pl, uint32_t t) {
   return !pl.generic && pl.lz >= 4 && pl.lz <= 11 && pl.klev[t] >= 1;
 }
 
-// The split form of the last pass (a last pass that leaves the sorted bins in
-// slot array (P + 1) & 1, then scan + strip) applies to sorting plans of two
-// or more passes routed by the register-resident kernel.
+// The split form of the last pass (a last pass that leaves the compacted bins
+// in slot array (P + 1) & 1, then scan + strip, which sorts the bins that
+// straddle a tile of the comparison sort) applies to sorting plans of two or
+// more passes routed by the register-resident kernel.
 bool split_last(const Plan& pl) { return pl.P >= 2 && pl.L > 0 && use_route_kernel(pl, pl.P - 1); }
 
 // Where a sort's comparison phase ping-pongs besides `out`: with the split

@@ -104,7 +104,7 @@ struct PassArgs {
   uint32_t levels;            // L
   uint32_t level0, klev;      // first level of this pass, levels in this pass
   uint32_t attempt;
-  uint32_t fin;               // last pass: 0 = random permutation of each bin, 1 = sort each bin
+  uint32_t fin;               // fused last pass: 0 = random permutation of each bin, 1 = sort each bin
   uint32_t pad;
   uint32_t* loads;            // split last pass: real count of every final bin
 };

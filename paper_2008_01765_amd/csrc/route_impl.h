@@ -632,8 +632,8 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
 }
 
 // R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last,
-// bit 2 = split form of the last pass (persistent, bins sorted and written to
-// rec_out; bos_sort only), bit 4 = the launch has exactly Z 2^klev / 16 lanes
+// bit 2 = split form of the last pass (bins compacted and written to rec_out,
+// then scan + strip; the sorts only), bit 4 = the launch has exactly Z 2^klev / 16 lanes
 // (all of them hold slots, so no lane needs a guard).
 // Body of one routing launch.  BATCH = false: a persistent workgroup walks
 // over items blockIdx.x, + gridDim.x, ... (last pass: tickets).  BATCH = true:
