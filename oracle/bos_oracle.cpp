@@ -27,7 +27,7 @@
  *     fresh labels (overflow depends on the labels only, never on the data).
  *   - Labels and per-bin permutation keys come from Philox4x64-10; see
  *     bos_oracle_label and bos_oracle_shuffle_key.
- *   - "Randomly permute each bin": the bin's real elements are put in record
+ *   - The random permutation of each bin: the bin's real elements are put in record
  *     order (key, payload), the p-th of them receives the 64-bit random key
  *     r(b*Z + p), and they are sorted by (r, p).  This is a uniformly random
  *     ordering of the bin (up to 64-bit key ties, broken by p) that does not
