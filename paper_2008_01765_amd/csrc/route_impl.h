@@ -432,14 +432,51 @@ __device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint3
   }
 }
 
+// Value of lane (lane ^ X) within each group of 32 lanes (ds_swizzle in bit
+// mode: and-mask 31, or-mask 0, xor-mask X; no LDS memory is touched).
+template <uint32_t X>
+__device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
+  static_assert(X >= 1 && X < 32, "xor-mask of 5 bits");
+  return uint32_t(__builtin_amdgcn_ds_swizzle(int(v), int((X << 10) | 0x1F)));
+}
+template <uint32_t X>
+__device__ __forceinline__ uint2 swz_xor(uint2 v) {
+  return make_uint2(swz_xor<X>(v.x), swz_xor<X>(v.y));
+}
+template <uint32_t X>
+__device__ __forceinline__ uint4 swz_xor(uint4 v) {
+  return make_uint4(swz_xor<X>(v.x), swz_xor<X>(v.y), swz_xor<X>(v.z), swz_xor<X>(v.w));
+}
+
+// One compaction stage at distance 16 HLX (< 512 slots): the partner slot is
+// held by lane lq ^ HLX, reached by a swizzle; P0 and Ph are the reals'
+// prefix counts at the node's start and middle (the bin's lane prefixes).
+template <uint32_t HLX, typename T>
+__device__ __forceinline__ void compact_xstage(T (&rv)[16], uint32_t (&tv)[16], const uint32_t* bpfx, uint32_t lq,
+                                               bool active) {
+  constexpr uint32_t half = HLX * 16u;
+  const uint32_t node0 = lq & ~(2u * HLX - 1u);
+  const uint32_t P0 = active ? bpfx[node0] : 0u, Ph = active ? bpfx[node0 + HLX] : 0u;
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) {
+    const uint32_t i = 16u * (lq & (HLX - 1u)) + e;  // index in the node's half
+    const bool b = active && swap_bit(P0, Ph, half, i);
+    const T pr = swz_xor<HLX>(rv[e]);
+    const uint32_t pt = swz_xor<HLX>(tv[e]);
+    rv[e] = sel(b, pr, rv[e]);
+    tv[e] = b ? pt : tv[e];
+  }
+}
+
 // Oblivious compaction of every final bin in LDS: the bin's reals move to
 // its first slots.  The last level leaves each bin's reals interleaved with
 // dummies; this is the tight compaction network a MergeSplit level runs
 // (conditional swaps at distances 1, 2, .., Z/2, each decided by swap_bit from
 // the prefix counts of the reals), over one bin of Z slots with the reals as
 // the marks.  Lane lq of the bin's Z/16 lanes holds slots 16 lq + e; stages at
-// distances below 16 pair registers, the others exchange through the bin's own
-// LDS slots.  On return rv holds this lane's 16 slots after the compaction.
+// distances below 16 pair registers, those up to 256 pair lanes by swizzles,
+// and longer ones exchange through the bin's own LDS slots.  On return rv
+// holds this lane's 16 slots after the compaction.
 template <int R, int LZ, bool FULL>
 __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* spfx,
                                             uint32_t* swave, uint32_t klev, typename RecOf<R>::T (&rv)[16]) {
@@ -485,8 +522,16 @@ __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t
       tv[e2] = b ? t1 : t2;
     }
   }
-  // distances 16 .. Z/2: the partner lane is lq ^ (half / 16)
-  for (uint32_t half = 16; half < Z; half <<= 1) {
+  // distances 16 .. 256: the partner lane is lq ^ (half / 16), within 32 lanes
+  lds_group_sync<HL>();  // every lane's prefix is in spfx
+  const uint32_t* bpfx = spfx + S * HL;
+  if constexpr (HL >= 2) compact_xstage<1>(rv, tv, bpfx, lq, active);
+  if constexpr (HL >= 4) compact_xstage<2>(rv, tv, bpfx, lq, active);
+  if constexpr (HL >= 8) compact_xstage<4>(rv, tv, bpfx, lq, active);
+  if constexpr (HL >= 16) compact_xstage<8>(rv, tv, bpfx, lq, active);
+  if constexpr (HL >= 32) compact_xstage<16>(rv, tv, bpfx, lq, active);
+  // distances 512 .. Z/2 (Z >= 1024): through the bin's LDS slots
+  for (uint32_t half = 512; half < Z; half <<= 1) {
     lds_group_sync<HL>();  // spfx written; the previous stage's reads are done
     if (active) {
 #pragma unroll
