@@ -719,7 +719,9 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   const T* X = static_cast<const T*>(a.x_in);
   // first pass: all groups start on a multiple of 8 elements (labels come from
   // whole Philox blocks); otherwise inputs are staged through LDS
-  const bool aligned = (n % (8 * B)) == 0;
+  // (B = 2^L: divisions by B are shifts; a 64-bit division by a run-time
+  // value would be a long software sequence in every lane)
+  const bool aligned = (n & ((8ull << L) - 1ull)) == 0;
 
   // ---- load one block into layout-A registers of level 0 -------------------
   // level 0 pairs LDS buckets 2ms and 2ms+1; lane lt holds slots 16*(lt mod
@@ -742,7 +744,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     } else {
       // group j = h*NB + S_load holds X[floor(jn/B), floor((j+1)n/B))
       const uint64_t j = h * NB + S_load;
-      const uint64_t gs = (j * n) / B, gz = ((j + 1) * n) / B - gs;
+      const uint64_t gs = (j * n) >> L, gz = (((j + 1) * n) >> L) - gs;
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
         const bool real = active && (sb_load + e) < gz;
@@ -756,7 +758,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     if constexpr (FIRST) {
       const uint64_t h = uint64_t(item) >> i0;
       const uint64_t j = h * NB + S_load;
-      const uint64_t gs = (j * n) / B;
+      const uint64_t gs = (j * n) >> L;
       const uint64_t x0 = gs + sb_load;  // multiple of 8
       if (active && dt[0] != kDummyTag) {
         const Philox4 p0 = philox4x64_10(x0 >> 3, a.attempt, a.seed, 0);
@@ -786,7 +788,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     }
     lds_barrier();
     const uint64_t j_lo = h * NB;
-    const uint64_t x_lo = (j_lo * n) / B, x_hi = ((j_lo + NB) * n) / B;
+    const uint64_t x_lo = (j_lo * n) >> L, x_hi = ((j_lo + NB) * n) >> L;
     const uint64_t c_lo = x_lo >> 3, c_hi = (x_hi + 7) >> 3;
     for (uint64_t c = c_lo + tid; c < c_hi; c += nthr) {
       const Philox4 ph = philox4x64_10(c, a.attempt, a.seed, 0);
@@ -796,7 +798,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         if (x < x_lo || x >= x_hi) continue;
         const uint32_t word = uint32_t(ph.v[w >> 1] >> (32u * (w & 1u)));
         const uint64_t j = ((x + 1) * B - 1) / n;
-        const uint64_t gs = (j * n) / B;
+        const uint64_t gs = (j * n) >> L;
         const uint32_t S = uint32_t(j - j_lo), s = uint32_t(x - gs);
         const uint32_t pi = S * ZP + s + (s >> 4);
         srec[pi] = X[x];
