@@ -128,7 +128,7 @@ __device__ __forceinline__ void merge_partition_one(const void* src_, uint64_t n
   using T = typename RecOf<R>::T;
   const T* src = static_cast<const T*>(src_);
   const uint64_t o = b * kMTile<R>;
-  const uint64_t lo = (o / (2 * w)) * (2 * w);
+  const uint64_t lo = o & ~(2 * w - 1);  // run widths are powers of two
   const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
   const uint64_t a = merge_path(src + lo, mid - lo, src + mid, hi - mid, o - lo);
   split[2 * b] = lo + a;
@@ -195,7 +195,7 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
     cnt = uint32_t((o0 + kMTile<R> < n ? o0 + kMTile<R> : n) - o0);
     na = cnt;  // the tile is read as one contiguous range
   } else {
-    const uint64_t lo = (o0 / (2 * w)) * (2 * w);
+    const uint64_t lo = o0 & ~(2 * w - 1);  // run widths are powers of two
     const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
     const uint64_t o1 = o0 + kMTile<R> < hi ? o0 + kMTile<R> : hi;
     a0 = split[2 * b];
@@ -235,7 +235,7 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
     if (whole_pairs) {
       // this thread's outputs lie in one pair (2w is a multiple of kMItems<R>)
       const uint32_t w32 = uint32_t(w);
-      pb = (dd / (2 * w32)) * (2 * w32);
+      pb = dd & ~(2 * w32 - 1);
       pa = cnt - pb < w32 ? cnt - pb : w32;
       pbn = cnt - pb - pa < w32 ? cnt - pb - pa : w32;
     }
