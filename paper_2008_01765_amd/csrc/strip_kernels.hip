@@ -61,7 +61,7 @@ __device__ __forceinline__ void lds_bitonic(T* sb, uint32_t P2) {
   for (uint32_t size = 2; size <= P2; size <<= 1) {
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
       for (uint32_t t = threadIdx.x; t < P2 / 2; t += kStripThreads) {
-        const uint32_t i = (t / stride) * 2 * stride + (t % stride), k = i + stride;
+        const uint32_t i = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u)), k = i + stride;
         const bool asc = (i & size) == 0;
         const T x = sb[i], y = sb[k];
         const bool swap = asc ? rec_less(y, x) : rec_less(x, y);
@@ -99,12 +99,13 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
   const uint32_t total = pre[NB];
   const uint64_t base = boff[blk];
   if (tile) {
-    // the straddling bins, in bin order
+    // the straddling bins, in bin order (tile is a power of two)
     if (tid == 0) {
+      const uint32_t tl = uint32_t(__builtin_ctz(tile));
       uint32_t c = 0;
       for (uint32_t j = 0; j < NB; ++j) {
         const uint64_t b0 = base + pre[j], b1 = base + pre[j + 1];
-        if (b1 - b0 >= 2 && b0 / tile != (b1 - 1) / tile) strad[c++] = uint16_t(j);
+        if (b1 - b0 >= 2 && (b0 >> tl) != ((b1 - 1) >> tl)) strad[c++] = uint16_t(j);
       }
       nstrad = c;
     }
@@ -204,7 +205,7 @@ hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, u
 // straddle a tile boundary are sorted); lz <= 11.
 hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
                         uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, uint32_t tile, hipStream_t s) {
-  if (klev > 9 || lz > 11 || nblocks == 0) return hipErrorInvalidValue;
+  if (klev > 9 || lz > 11 || nblocks == 0 || (tile & (tile - 1u))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, bsum, nblocks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
