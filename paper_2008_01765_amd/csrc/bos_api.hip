@@ -29,8 +29,10 @@ hipError_t launch_labels(uint32_t* out, uint64_t n, uint32_t L, uint64_t seed, u
 hipError_t launch_pass(int rec, const PassArgs& a, bool first, bool last, uint32_t nblocks, hipStream_t s);
 hipError_t launch_route(int rec, const PassArgs& a, bool first, bool last, uint32_t nitems, uint32_t grid,
                         hipStream_t s, bool split);
-hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
-                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, uint32_t tile, hipStream_t s);
+hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum,
+                        unsigned long long* coff, void* out, uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz,
+                        uint32_t tile, hipStream_t s);
+constexpr uint32_t kScanChunk = 1024;  // block counts per workgroup of the strip's first scan
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                   hipStream_t s, void** result);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
@@ -110,7 +112,7 @@ struct Plan {
   int rec = 8;
   uint32_t Z = 512, lz = 9, L = 0, P = 1, k = 0, tile = kDefaultTile;
   uint32_t klev[kMaxPasses] = {0}, lev0[kMaxPasses] = {0};
-  size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_scan = 0, off_split = 0, off_loads = 0;
+  size_t off_rec[2] = {0, 0}, off_tag[2] = {0, 0}, off_status = 0, off_split = 0, off_loads = 0, off_coff = 0;
   size_t total = 0;
   uint32_t nblocks_last = 1;
   bool generic = false;
@@ -292,6 +294,8 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   off = align_up(off + comparison_sort_split_bytes(n));
   pl->off_loads = off;   // split last pass: real count of every final bin
   off = align_up(off + size_t(B) * 4);
+  pl->off_coff = off;    // split last pass: offset of every chunk of kScanChunk block counts
+  off = align_up(off + (size_t(pl->nblocks_last) / kScanChunk + 1) * 8);
   pl->total = off;
   return BOS_OK;
 }
@@ -453,7 +457,8 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
     if (e != hipSuccess) return e;
     if (split_pass) {
       prof_begin(BOS_K_STRIP, 0, 2 * rec_bytes, s);
-      e = launch_strip(pl.rec, a.rec_out, a.loads, a.scan, out, pl.n, nitems, pl.klev[t], pl.lz, pl.tile, s);
+      e = launch_strip(pl.rec, a.rec_out, a.loads, a.scan, reinterpret_cast<unsigned long long*>(ws + pl.off_coff),
+                       out, pl.n, nitems, pl.klev[t], pl.lz, pl.tile, s);
       prof_end(s);
       if (e != hipSuccess) return e;
     }

@@ -54,6 +54,35 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks_kernel(unsigned long
   scan_blocks(v, count);
 }
 
+// First level of the block-count scan: workgroup c turns v[c*1024 ..
+// c*1024 + 1023] into its exclusive scan in place (coalesced, one count per
+// thread) and writes the chunk's total to tot[c]; a second, one-workgroup
+// scan of tot gives every chunk's offset.
+__global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(unsigned long long* v, uint32_t count,
+                                                                   unsigned long long* tot) {
+  __shared__ unsigned long long wsum[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+  const uint64_t idx = uint64_t(blockIdx.x) * kScanThreads + tid;
+  const unsigned long long x = idx < count ? v[idx] : 0ull;
+  unsigned long long incl = x;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  unsigned long long before = 0, total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+    const unsigned long long t = wsum[w];
+    before += w < wv ? t : 0ull;
+    total += t;
+  }
+  if (idx < count) v[idx] = before + incl - x;
+  if (tid == 0) tot[blockIdx.x] = total;
+}
+
 // Bitonic sort of sb[0..P2) by (key, payload) (P2 a power of two), by the
 // whole workgroup.
 template <typename T>
@@ -73,12 +102,14 @@ __device__ __forceinline__ void lds_bitonic(T* sb, uint32_t P2) {
   }
 }
 
-// One routing block's bins (NB = 2^klev of them) to out[boff[blk] ..); bins
-// that straddle a multiple of `tile` are sorted first (tile = 0: none).
+// One routing block's bins (NB = 2^klev of them) to out[boff[blk] + coff[blk /
+// 1024] ..) (coff null: boff alone); bins that straddle a multiple of `tile`
+// are sorted first (tile = 0: none).
 template <int R>
 __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t* loads,
-                                            const unsigned long long* boff, void* out_, uint64_t n, uint32_t klev,
-                                            uint32_t lz, uint64_t blk, uint32_t tile) {
+                                            const unsigned long long* boff, const unsigned long long* coff,
+                                            void* out_, uint64_t n, uint32_t klev, uint32_t lz, uint64_t blk,
+                                            uint32_t tile) {
   using T = typename RecOf<R>::T;
   __shared__ uint32_t pre[513];  // NB <= 512: a block has at most 8192 slots, Z >= 16
   __shared__ uint16_t strad[512];
@@ -97,7 +128,7 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
   }
   __syncthreads();
   const uint32_t total = pre[NB];
-  const uint64_t base = boff[blk];
+  const uint64_t base = boff[blk] + (coff ? coff[blk / kScanThreads] : 0ull);
   if (tile) {
     // the straddling bins, in bin order (tile is a power of two)
     if (tid == 0) {
@@ -161,9 +192,10 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
 
 template <int R>
 __global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned, const uint32_t* loads,
-                                                              const unsigned long long* boff, void* out, uint64_t n,
+                                                              const unsigned long long* boff,
+                                                              const unsigned long long* coff, void* out, uint64_t n,
                                                               uint32_t klev, uint32_t lz, uint32_t tile) {
-  strip_block<R>(binned, loads, boff, out, n, klev, lz, blockIdx.x, tile);
+  strip_block<R>(binned, loads, boff, coff, out, n, klev, lz, blockIdx.x, tile);
 }
 
 // Batched forms: one scan workgroup per instance; the strip workgroups of
@@ -184,7 +216,8 @@ __global__ __launch_bounds__(kStripThreads) void strip_kernel_b(const StripSeg* 
       hi = mid;
   }
   const StripSeg sg = segs[lo];
-  strip_block<R>(sg.binned, sg.loads, sg.bsum, sg.out, sg.n, sg.klev, sg.lz, blockIdx.x - sg.first, sg.tile);
+  strip_block<R>(sg.binned, sg.loads, sg.bsum, nullptr, sg.out, sg.n, sg.klev, sg.lz, blockIdx.x - sg.first,
+                 sg.tile);
 }
 
 // Batched scan + strip over nsegs instances (device table segs, `blocks` strip
@@ -202,19 +235,25 @@ hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, u
 }
 
 // tile: records per tile of the comparison sort's first phase (bins that
-// straddle a tile boundary are sorted); lz <= 11.
-hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum, void* out,
-                        uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz, uint32_t tile, hipStream_t s) {
-  if (klev > 9 || lz > 11 || nblocks == 0 || (tile & (tile - 1u))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, bsum, nblocks);
+// straddle a tile boundary are sorted); lz <= 11.  coff: device,
+// nblocks / 1024 + 1 words (the chunk offsets of the two-level scan).
+hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum,
+                        unsigned long long* coff, void* out, uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz,
+                        uint32_t tile, hipStream_t s) {
+  if (klev > 9 || lz > 11 || nblocks == 0 || (tile & (tile - 1u)) || !coff) return hipErrorInvalidValue;
+  const uint32_t nchunks = (nblocks + kScanThreads - 1) / kScanThreads;
+  hipLaunchKernelGGL(scan_chunks_kernel, dim3(nchunks), dim3(kScanThreads), 0, s, bsum, nblocks, coff);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, coff, nchunks);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (rec == 8)
-    hipLaunchKernelGGL(strip_kernel<8>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, out, n, klev,
-                       lz, tile);
+    hipLaunchKernelGGL(strip_kernel<8>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, coff, out, n,
+                       klev, lz, tile);
   else
-    hipLaunchKernelGGL(strip_kernel<16>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, out, n, klev,
-                       lz, tile);
+    hipLaunchKernelGGL(strip_kernel<16>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, coff, out, n,
+                       klev, lz, tile);
   return hipGetLastError();
 }
 
