@@ -755,7 +755,32 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   };
   // first pass: labels of the loaded reals (word x mod 8 of Philox block x/8)
   auto finish_load = [&](uint32_t item, uint32_t* dt) {
-    if constexpr (FIRST) {
+    constexpr uint32_t QH = HALF_LANES / 2;  // lanes of a bucket that can hold reals
+    if constexpr (FIRST && QH >= 1 && QH < 64) {
+      // A group has at most Z/2 elements, so its reals sit in the first QH
+      // lanes of the bucket (16 slots each, two Philox blocks).  Every lane
+      // computes one block: lane q labels the block (q / QH) of lane q mod QH,
+      // and lane q < QH takes its second block from lane q + QH.
+      const uint64_t h = uint64_t(item) >> i0;
+      const uint64_t j = h * NB + S_load;
+      const uint64_t gs = (j * n) >> L;
+      const uint32_t q = lt % HALF_LANES;
+      const uint64_t xo = gs + 16u * (q % QH);  // first element of the owning lane, a multiple of 8
+      const Philox4 ph = philox4x64_10((xo >> 3) + q / QH, a.attempt, a.seed, 0);
+      uint32_t w[8], wp[8];
+#pragma unroll
+      for (uint32_t e = 0; e < 8; ++e) {
+        w[e] = uint32_t(ph.v[e >> 1] >> (32u * (e & 1u)));
+        wp[e] = uint32_t(__shfl_xor(int(w[e]), int(QH), 64));
+      }
+      if (active) {
+#pragma unroll
+        for (uint32_t e = 0; e < 8; ++e) {
+          if (dt[e] != kDummyTag) dt[e] = L ? (w[e] >> (32u - L)) : 0u;
+          if (dt[8 + e] != kDummyTag) dt[8 + e] = L ? (wp[e] >> (32u - L)) : 0u;
+        }
+      }
+    } else if constexpr (FIRST) {
       const uint64_t h = uint64_t(item) >> i0;
       const uint64_t j = h * NB + S_load;
       const uint64_t gs = (j * n) >> L;
