@@ -62,6 +62,18 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_source_digest():
     h = hashlib.sha256()
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_2008_01765_amd", "csrc"))):
@@ -443,7 +455,7 @@ def main():
                          "call, %.1f s" % (args.cpu_log2n, args.mode, dt),
                "phases_s": {k: round(r["report"][k], 3) for k in ("sec_labels", "sec_route", "sec_finish",
                                                                   "sec_sort")},
-               "host": os.uname().nodename, "nproc": os.cpu_count()}
+               "host": os.uname().nodename, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
     batched = None
     args.tuning_used = None
