@@ -88,3 +88,47 @@ def test_batched_workload_shape():
     outs = bos.sort_batched([bos.from_numpy(h) for h in hosts], [1000 + i for i in range(len(hosts))])
     for h, o in zip(hosts, outs):
         np.testing.assert_array_equal(bos.to_numpy(o), cf.sorted_records(h))
+
+
+def test_batched_workload_full_size():
+    # The batched configuration the benchmark times: 4096 instances of 16-byte
+    # records (uniform u64 key, payload = index), sizes log-uniform in
+    # [2^10, 2^20] rescaled to a total <= 2^28, Z, k and tile from the stored
+    # tuning table.  Every instance comes out sorted by (key, payload) and as a
+    # permutation of its input (an order-independent checksum per instance);
+    # 8 sampled instances are compared whole with numpy's sort.
+    from paper_2008_01765_amd import autotune
+
+    previous = bos.get_tuning()
+    autotune.install()
+    try:
+        sizes = inputs.batched_sizes(4096, 10, 20, 1 << 28, seed=4242)
+        total = int(sizes.sum())
+        host = inputs.records(total, 16, 43)
+        master = bos.from_numpy(host)
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        ins = [master[int(o):int(o) + int(n)] for o, n in zip(offs, sizes)]
+        outm = torch.empty_like(master)
+        outs = [outm[int(o):int(o) + int(n)] for o, n in zip(offs, sizes)]
+        bos.sort_batched(ins, list(range(len(ins))), outs=outs)
+        got = bos.to_numpy(outm)
+        del ins, outs, master, outm
+    finally:
+        bos.set_tuning(previous)
+        bos.release_workspaces()
+    k, p = got[:, 0], got[:, 1]
+    ok = (k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (p[1:] >= p[:-1]))
+    ok[offs[1:] - 1] = True  # instance boundaries
+    assert bool(np.all(ok))
+
+    def mix(a):
+        with np.errstate(over="ignore"):
+            z = a[:, 0] * np.uint64(0x9E3779B97F4A7C15) ^ (a[:, 1] + np.uint64(0x632BE59BD9B4E019))
+            z ^= z >> np.uint64(29)
+            z *= np.uint64(0xBF58476D1CE4E5B9)
+            return z ^ (z >> np.uint64(32))
+
+    np.testing.assert_array_equal(np.add.reduceat(mix(got), offs), np.add.reduceat(mix(host), offs))
+    for i in np.random.default_rng(8).choice(len(sizes), 8, replace=False):
+        o, n = int(offs[i]), int(sizes[i])
+        np.testing.assert_array_equal(got[o:o + n], cf.sorted_records(host[o:o + n]))
