@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import closed_forms as cf
+from gpu_util import record_checksum
 from paper_2008_01765_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -229,3 +230,31 @@ def test_stepper_rejects_null_and_small_workspace():
     assert arr[0].status == bos.OK
     np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(bos.to_numpy(t)))
     st.close()
+
+
+def test_serving_workload_shape():
+    # Requests of the serving workload's shape (16-byte records, sizes
+    # log-uniform in [2^12, 2^24], slices of one device array at pseudo-random
+    # offsets) replayed with Poisson arrivals through the pipelined server:
+    # every output is sorted and a permutation of its request, and 4 sampled
+    # requests are compared whole with numpy's sort.
+    sizes = inputs.request_sizes(64, 12, 24, seed=7)
+    master_n = 1 << 25
+    host = inputs.records(master_n, 16, 44)
+    master = bos.from_numpy(host)
+    starts = (inputs.splitmix64(99, 0, len(sizes)) % np.uint64(master_n - (1 << 24) + 1)).astype(np.int64)
+    reqs = [master[int(s0):int(s0) + int(n)] for s0, n in zip(starts, sizes)]
+    arr = serving.poisson_arrivals(len(reqs), rate_per_s=400.0, seed=11)
+    srv = serving.Server(hbm_budget_bytes=64 << 30)
+    futs = serving.run_trace(srv, reqs, arr)
+    assert srv.idle() and srv.completed == len(reqs)
+    for f in futs:
+        assert f.status == bos.OK
+        o = bos.to_numpy(f.out)
+        k, p = o[:, 0], o[:, 1]
+        assert bool(np.all((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (p[1:] >= p[:-1]))))
+        h = host[int(starts[f.id]):int(starts[f.id]) + f.n]
+        assert record_checksum(o) == record_checksum(h)
+    for i in np.random.default_rng(3).choice(len(reqs), 4, replace=False):
+        h = host[int(starts[i]):int(starts[i]) + int(sizes[i])]
+        np.testing.assert_array_equal(bos.to_numpy(futs[i].out), cf.sorted_records(h))
