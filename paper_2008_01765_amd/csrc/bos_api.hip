@@ -34,9 +34,10 @@ hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsi
                         uint32_t tile, hipStream_t s);
 constexpr uint32_t kScanChunk = 1024;  // block counts per workgroup of the strip's first scan
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
-                                  hipStream_t s, void** result);
+                                  hipStream_t s, void** result, bool multiway);
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
-size_t comparison_sort_split_bytes(uint64_t n);
+uint32_t comparison_sort_hbm_passes(int rec, uint64_t n, uint32_t ts, bool multiway);
+size_t comparison_sort_split_bytes(uint64_t n, int rec);
 hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
                                 const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
                                 uint32_t lds, hipStream_t s, bool split);
@@ -291,7 +292,7 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   pl->off_status = off;  // status word, ticket, then look-back words
   off = align_up(off + 16 + size_t(pl->nblocks_last) * 8);
   pl->off_split = off;   // merge-path splits of the comparison sort
-  off = align_up(off + comparison_sort_split_bytes(n));
+  off = align_up(off + comparison_sort_split_bytes(n, rec));
   pl->off_loads = off;   // split last pass: real count of every final bin
   off = align_up(off + size_t(B) * 4);
   pl->off_coff = off;    // split last pass: offset of every chunk of kScanChunk block counts
@@ -951,7 +952,7 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
   // The comparison sort ping-pongs between `out` and a free region of the
   // workspace (sort_tmp); the routing output goes where the sort must start
   // so that the result lands in `out`.
-  const uint32_t passes = comparison_sort_passes(n, pl.tile);
+  const uint32_t passes = comparison_sort_hbm_passes(pl.rec, n, pl.tile, true);
   const bool split = split_last(pl);
   void* tmp = sort_tmp(pl, w);
   void* start = (passes % 2 == 0) ? out : tmp;
@@ -965,7 +966,7 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
   }
   void* result = nullptr;
   hipError_t e = launch_comparison_sort(pl.rec, start, other, n, pl.tile,
-                                        reinterpret_cast<uint64_t*>(w + pl.off_split), s, &result);
+                                        reinterpret_cast<uint64_t*>(w + pl.off_split), s, &result, true);
   if (e != hipSuccess) return BOS_ERR_HIP;
   if (result != out) {
     e = hipMemcpyAsync(out, result, n * pl.rec, hipMemcpyDeviceToDevice, s);
@@ -1040,7 +1041,7 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
         if (rs == BOS_OK) {
           void* result = nullptr;
           if (launch_comparison_sort(j.pl.rec, j.start, j.other, j.n, j.pl.tile,
-                                     reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), s, &result) != hipSuccess)
+                                     reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), s, &result, false) != hipSuccess)
             return BOS_ERR_HIP;
         }
         hs[i] = rs;

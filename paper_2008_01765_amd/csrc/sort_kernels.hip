@@ -13,6 +13,8 @@
 #include "bos_prof.h"
 #include "route_impl.h"
 
+#include <utility>
+
 namespace bos {
 
 constexpr uint32_t kTileThreads = 512;
@@ -334,6 +336,270 @@ __global__ __launch_bounds__(kMThreads<R>) void merge_tile_kernel_b(const SortSe
   merge_tile_one<R>(sg.src, sg.dst, sg.n, sg.w, sg.split, blockIdx.x - sg.first);
 }
 
+// ---- four-way merge passes --------------------------------------------------
+//
+// A pass merges runs of width w = 2^lw in groups of four, so the comparison
+// sort crosses HBM half as often.  Tiles are cut by value: every G-th record
+// of the input is a sample (G = kMTile/64), and every kSplM-th record of a
+// group's four sample runs merged, in the order (record, run, position), opens
+// a tile.  Between two such splitters each run holds at most its splitter
+// samples' G-blocks plus, for the three runs that do not own the opening
+// splitter, one partial block, so a tile holds at most kSplM*G + 3(G-1)
+// records (4029 of 4096 for 8-byte records, 2013 of 2048 for 16-byte ones).
+
+template <int R>
+constexpr uint32_t kSmpLog = R == 8 ? 6u : 5u;  // log2 G
+// A four-way tile is merged by 512 threads, half a two-way tile's records each.
+template <int R>
+constexpr uint32_t kM4Items = kMItems<R> / 2;
+template <int R>
+constexpr uint32_t kM4Threads = kMTile<R> / kM4Items<R>;
+constexpr uint32_t kSplM = 60;                  // samples per tile
+
+// Does record x of run kx come before record e of run ke (x != e's slot)?
+template <typename T>
+__device__ __forceinline__ bool precedes(T x, uint32_t kx, T e, uint32_t ke) {
+  return kx < ke ? !rec_less(e, x) : rec_less(x, e);
+}
+
+// Sample of the input of the first four-way pass: smp[i] = src[i*G].
+template <int R>
+__global__ void sample_gather_kernel(const void* src_, void* smp_, uint64_t n) {
+  using T = typename RecOf<R>::T;
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < ((n + (1ull << kSmpLog<R>) - 1) >> kSmpLog<R>))
+    static_cast<T*>(smp_)[i] = static_cast<const T*>(src_)[i << kSmpLog<R>];
+}
+
+// One thread per sample: its rank among its group's samples; a sample whose
+// rank is a multiple of kSplM opens tile rank/kSplM of the group and stores
+// the absolute start of the tile in each of the four runs (spl[4*tile + k]).
+template <int R>
+__global__ void merge4_split_kernel(const void* src_, const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf,
+                                    uint64_t* spl) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t LG = kSmpLog<R>;
+  constexpr uint64_t G = 1ull << LG;
+  const T* src = static_cast<const T*>(src_);
+  const T* smp = static_cast<const T*>(smp_);
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ((n + G - 1) >> LG)) return;
+  const uint64_t p = i << LG, w = 1ull << lw, g = p >> (lw + 2), gs = g << (lw + 2);
+  const uint32_t j = uint32_t(p >> lw) & 3u;
+  const T e = smp[i];
+  uint64_t st[4], len[4], c[4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    st[k] = gs + k * w < n ? gs + k * w : n;
+    len[k] = n - st[k] < w ? n - st[k] : w;
+  }
+  // the three sample searches advance together (one round of loads per
+  // halving); c[k] = samples of run k before e, len of the open range in cl[k]
+  uint64_t cl[4], maxl = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    c[k] = 0;
+    cl[k] = k == j ? 0 : (len[k] + G - 1) >> LG;
+    maxl = cl[k] > maxl ? cl[k] : maxl;
+  }
+  while (maxl > 0) {
+    maxl = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      if (cl[k] == 0) continue;
+      const uint64_t half = cl[k] >> 1;
+      if (precedes(smp[(st[k] >> LG) + c[k] + half], k, e, j)) {
+        c[k] += half + 1;
+        cl[k] -= half + 1;
+      } else {
+        cl[k] = half;
+      }
+      maxl = cl[k] > maxl ? cl[k] : maxl;
+    }
+  }
+  const uint64_t r = ((p - st[j]) >> LG) + c[0] + c[1] + c[2] + c[3];
+  if (uint32_t(r) % kSplM != 0) return;
+  uint64_t* out = spl + 4 * (g * ntf + uint32_t(r) / kSplM);
+  // Samples c-1 and c of run k bracket e: search the records between them,
+  // the three searches advancing together.  lb[k] = records of run k before e.
+  uint64_t lb[4];
+  maxl = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    lb[k] = k == j ? p - st[j] : c[k] > 0 ? (c[k] - 1) * G + 1 : 0;
+    const uint64_t hi = c[k] * G < len[k] ? c[k] * G : len[k];
+    cl[k] = k == j || c[k] == 0 ? 0 : hi - lb[k];
+    maxl = cl[k] > maxl ? cl[k] : maxl;
+  }
+  while (maxl > 0) {
+    maxl = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      if (cl[k] == 0) continue;
+      const uint64_t half = cl[k] >> 1;
+      if (precedes(src[st[k] + lb[k] + half], k, e, j)) {
+        lb[k] += half + 1;
+        cl[k] -= half + 1;
+      } else {
+        cl[k] = half;
+      }
+      maxl = cl[k] > maxl ? cl[k] : maxl;
+    }
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) out[k] = st[k] + lb[k];
+}
+
+// ITEMS outputs, from output dd on, of the merge of A (na records at slot
+// xa) and B (nb records at slot xb) in LDS; PAD: slot q lives at q + q/16
+// (the padded staging layout).  The current head of each side stays in
+// registers, so a step reads one record.
+template <bool PAD, typename T, uint32_t ITEMS>
+__device__ __forceinline__ void merge_items_lds(const T* s, uint32_t xa, uint32_t na, uint32_t xb, uint32_t nb,
+                                                uint32_t dd, T (&out)[ITEMS]) {
+  auto at = [&](uint32_t q) { return PAD ? s[q + (q >> 4)] : s[q]; };
+  uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
+  while (l < h) {
+    const uint32_t md = (l + h) >> 1;
+    if (!rec_less(at(xb + dd - md - 1), at(xa + md)))
+      l = md + 1;
+    else
+      h = md;
+  }
+  uint32_t ia = l, ib = dd - l;
+  T va = at(xa + (ia < na ? ia : 0)), vb = at(xb + (ib < nb ? ib : 0));
+#pragma unroll
+  for (uint32_t k = 0; k < ITEMS; ++k) {
+    const bool take_a = ia < na && (ib >= nb || !rec_less(vb, va));
+    out[k] = sel(take_a, va, vb);
+    ia += take_a ? 1u : 0u;
+    ib += take_a ? 0u : 1u;
+    if (k + 1 < ITEMS) {
+      const T nv = at(take_a ? xa + (ia < na ? ia : 0) : xb + (ib < nb ? ib : 0));
+      va = sel(take_a, nv, va);
+      vb = sel(take_a, vb, nv);
+    }
+  }
+}
+
+// One tile of a four-way pass: load the tile's four run segments, merge runs
+// 0+1 and 2+3 (the second result starts at an ITEMS-aligned slot so that no
+// thread's outputs straddle the two), merge the two results, write the tile
+// coalesced and, when smp is set, the next pass's samples.  A tile whose
+// bounds are not what the splitters guarantee is skipped (no access outside
+// its runs or the LDS tile).
+template <int R>
+__device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, uint64_t n, uint32_t lw,
+                                                const uint64_t* spl, uint64_t ntf, uint64_t ng, uint64_t ntl,
+                                                void* smp_, uint64_t tile) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t IT = kM4Items<R>, NT = kM4Threads<R>, TT = kMTile<R>, LG = kSmpLog<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s = reinterpret_cast<T*>(smem);
+  const T* src = static_cast<const T*>(src_);
+  T* dst = static_cast<T*>(dst_);
+  T* smp = static_cast<T*>(smp_);
+  const uint64_t w = 1ull << lw, g = tile / ntf, b = tile - g * ntf, gs = g << (lw + 2);
+  const uint64_t ntg = g + 1 < ng ? ntf : ntl;
+  uint64_t a[4], e[4], o0 = gs;
+  bool ok = b < ntg;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint64_t st = gs + k * w < n ? gs + k * w : n, en = n - st < w ? st + (n - st) : st + w;
+    a[k] = spl[4 * tile + k];
+    e[k] = b + 1 < ntg ? spl[4 * tile + 4 + k] : en;
+    ok = ok && st <= a[k] && a[k] <= e[k] && e[k] <= en;
+    o0 += a[k] - st;
+  }
+  if (!ok) return;
+  const uint32_t n0 = uint32_t(e[0] - a[0]), n1 = uint32_t(e[1] - a[1]), n2 = uint32_t(e[2] - a[2]),
+                 n3 = uint32_t(e[3] - a[3]);
+  const uint32_t nx = n0 + n1, ny = n2 + n3, cnt = nx + ny, nxa = (nx + IT - 1) & ~(IT - 1);
+  if (cnt == 0 || nxa + ny > TT) return;
+  {
+    using V = typename NativeOf<T>::V;
+    const V* srcv = reinterpret_cast<const V*>(src);
+    V* sv = reinterpret_cast<V*>(s);
+    const uint64_t fb = n0 ? a[0] : n1 ? a[1] : n2 ? a[2] : a[3];  // a record of the tile
+    V in[IT];
+#pragma unroll
+    for (uint32_t k = 0; k < IT; ++k) {
+      const uint32_t t = threadIdx.x + k * NT;
+      const uint64_t gi = t < n0 ? a[0] + t : t < nx ? a[1] + (t - n0) : t < nx + n2 ? a[2] + (t - nx)
+                                                                                      : a[3] + (t - nx - n2);
+      in[k] = srcv[t < cnt ? gi : fb];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (uint32_t k = 0; k < IT; ++k) {
+      const uint32_t t = threadIdx.x + k * NT;
+      if (t < cnt) sv[t] = in[k];
+    }
+  }
+  __syncthreads();
+  const uint32_t dd = threadIdx.x * IT;
+  T out[IT];
+  uint32_t lim = 0;
+  if (dd < nx) {
+    merge_items_lds<false>(s, 0u, n0, n0, n1, dd, out);
+    lim = nx;
+  } else if (dd >= nxa && dd - nxa < ny) {
+    merge_items_lds<false>(s, nx, n2, nx + n2, n3, dd - nxa, out);
+    lim = nxa + ny;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < IT; ++k)
+    if (dd + k < lim) s[dd + k + ((dd + k) >> 4)] = out[k];
+  __syncthreads();
+  if (dd < cnt) merge_items_lds<true>(s, 0u, nx, nxa, ny, dd, out);
+  __syncthreads();
+  if (dd < cnt) {
+#pragma unroll
+    for (uint32_t k = 0; k < IT; ++k) s[dd + k + ((dd + k) >> 4)] = out[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < IT; ++k) {
+    const uint32_t t = threadIdx.x + k * NT;
+    if (t < cnt) {
+      const T v = s[t + (t >> 4)];
+      const uint64_t o = o0 + t;
+      dst[o] = v;
+      if (smp && (o & ((1ull << LG) - 1)) == 0) smp[o >> LG] = v;
+    }
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kM4Threads<R>) void merge4_tile_kernel(const void* src, void* dst, uint64_t n, uint32_t lw,
+                                                                const uint64_t* spl, uint64_t ntf, uint64_t ng,
+                                                                uint64_t ntl, void* smp) {
+  merge4_tile_one<R>(src, dst, n, lw, spl, ntf, ng, ntl, smp, blockIdx.x);
+}
+
+// Tiles of a four-way pass over runs of width 2^lw: per full group (ntf), in
+// the last group (ntl), the group count (ng) and the total.
+struct Merge4Tiles {
+  uint64_t ntf, ntl, ng, total;
+};
+static Merge4Tiles merge4_tiles(int rec, uint64_t n, uint32_t lw) {
+  const uint32_t lg = rec == 8 ? kSmpLog<8> : kSmpLog<16>;
+  const uint64_t w = 1ull << lw, gw = w << 2, G = 1ull << lg;
+  Merge4Tiles t;
+  t.ng = (n + gw - 1) / gw;
+  t.ntf = ((gw >> lg) + kSplM - 1) / kSplM;
+  const uint64_t gl = (t.ng - 1) * gw;
+  uint64_t sl = 0;
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint64_t st = gl + k * w < n ? gl + k * w : n, len = n - st < w ? n - st : w;
+    sl += (len + G - 1) >> lg;
+  }
+  t.ntl = (sl + kSplM - 1) / kSplM;
+  t.total = (t.ng - 1) * t.ntf + t.ntl;
+  return t;
+}
+
 // Batched status words: segment s gets p[0] = no overflow, p[1..count) = 0.
 __global__ void fill_status_kernel_b(const FillSeg* segs, uint32_t nsegs) {
   if (blockIdx.x >= nsegs) return;
@@ -480,12 +746,45 @@ static hipError_t launch_tile_sort_t(void* buf, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The split region of the comparison sort: two-way merge-path splits, then
+// the sample of a four-way pass's input, then its tile starts.
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+static size_t split2_bytes(uint64_t n) {
+  constexpr uint64_t t = merge_tile_records(16);  // the smaller merge tile
+  return size_t((n + t - 1) / t + 2) * 16;
+}
+static size_t sample_bytes(int rec, uint64_t n) {
+  const uint32_t lg = rec == 8 ? kSmpLog<8> : kSmpLog<16>;
+  return size_t((n >> lg) + 2) * uint32_t(rec);
+}
+static size_t spl4_bytes(int rec, uint64_t n) {
+  // tiles of any four-way pass: at most (samples / kSplM) + groups + 1, with
+  // groups of at least 4 * kMTile records
+  const uint32_t lg = rec == 8 ? kSmpLog<8> : kSmpLog<16>;
+  const uint64_t tiles = ((n >> lg) + 1) / kSplM + n / (4ull * merge_tile_records(rec)) + 3;
+  return size_t(tiles + 1) * 32;
+}
+
+// Four-way passes take every two remaining merge levels once runs are at
+// least a merge tile long; the two-way pass takes the rest (runs shorter than
+// a tile, and one level when the count left is odd).
+static uint32_t levels_left(uint64_t n, uint64_t w) {
+  uint32_t c = 0;
+  for (; w < n; w <<= 1) ++c;
+  return c;
+}
+static bool four_way_next(int rec, uint64_t n, uint64_t w) {
+  const uint32_t l = levels_left(n, w);
+  return w >= merge_tile_records(rec) && l >= 2 && l % 2 == 0;
+}
+
 template <int R>
 static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
-                                    hipStream_t s, void** result) {
+                                    hipStream_t s, void** result, bool multiway) {
   static bool attr = false;
   if (!attr) {
-    const hipError_t e = allow_lds(merge_tile_kernel<R>);
+    hipError_t e = allow_lds(merge_tile_kernel<R>);
+    if (e == hipSuccess) e = allow_lds(merge4_tile_kernel<R>);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -510,7 +809,33 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   uint32_t pass = 0;
   const uint64_t mtiles = (n + kMTile<R> - 1) / kMTile<R>;
   const uint32_t merge_lds = (kMTile<R> + (kMTile<R> >> 4)) * uint32_t(R);
-  for (uint64_t w = ts; w < n; w *= 2) {
+  char* region = reinterpret_cast<char*>(split);
+  void* smp = region + align256(split2_bytes(n));
+  uint64_t* spl = reinterpret_cast<uint64_t*>(region + align256(split2_bytes(n)) + align256(sample_bytes(R, n)));
+  bool have_sample = false;
+  for (uint64_t w = ts; w < n;) {
+    if (multiway && four_way_next(R, n, w)) {
+      uint32_t lw = 0;
+      while ((1ull << lw) < w) ++lw;
+      const Merge4Tiles t = merge4_tiles(R, n, lw);
+      const uint64_t nsmp = (n + (1ull << kSmpLog<R>) - 1) >> kSmpLog<R>;
+      const bool next4 = four_way_next(R, n, w << 2);
+      prof_begin(BOS_K_SORT_MERGE, pass++, 2 * n * R, s);
+      if (!have_sample)
+        hipLaunchKernelGGL(sample_gather_kernel<R>, dim3(uint32_t((nsmp + 255) / 256)), dim3(256), 0, s, src, smp, n);
+      hipLaunchKernelGGL(merge4_split_kernel<R>, dim3(uint32_t((nsmp + 255) / 256)), dim3(256), 0, s, src, smp, n, lw,
+                         t.ntf, spl);
+      hipLaunchKernelGGL(merge4_tile_kernel<R>, dim3(uint32_t(t.total)), dim3(kM4Threads<R>), merge_lds, s, src, dst, n,
+                         lw, spl, t.ntf, t.ng, t.ntl, next4 ? smp : nullptr);
+      prof_end(s);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      have_sample = next4;
+      std::swap(src, dst);
+      w <<= 2;
+      continue;
+    }
+    have_sample = false;
     prof_begin(BOS_K_SORT_MERGE, pass++, 2 * n * R, s);
     // boundaries 0..mtiles-1 (the end of the last tile is the end of its run pair)
     hipLaunchKernelGGL(merge_partition_kernel<R>, dim3(uint32_t((mtiles + 255) / 256)), dim3(256), 0, s, src, n, w,
@@ -520,9 +845,8 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
     prof_end(s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    void* t = src;
-    src = dst;
-    dst = t;
+    std::swap(src, dst);
+    w <<= 1;
   }
   *result = src;
   return hipSuccess;
@@ -536,16 +860,26 @@ uint32_t comparison_sort_passes(uint64_t n, uint32_t ts) {
   return c;
 }
 
-// Bytes of the split array the merge passes need.
-size_t comparison_sort_split_bytes(uint64_t n) {
-  constexpr uint64_t t = merge_tile_records(16);  // the smaller merge tile
-  return size_t((n + t - 1) / t + 2) * 16;
+// HBM passes of the comparison sort with four-way passes (multiway) or
+// two-way passes only.
+uint32_t comparison_sort_hbm_passes(int rec, uint64_t n, uint32_t ts, bool multiway) {
+  uint32_t c = 0;
+  if (n <= 1) return 0;
+  for (uint64_t w = ts; w < n; ++c) w <<= (multiway && four_way_next(rec, n, w)) ? 2 : 1;
+  return c;
 }
 
+// Bytes of the split region the merge passes need.
+size_t comparison_sort_split_bytes(uint64_t n, int rec) {
+  return align256(split2_bytes(n)) + align256(sample_bytes(rec, n)) + spl4_bytes(rec, n);
+}
+
+// multiway: four-way passes where they apply (split must then hold
+// comparison_sort_split_bytes(n, rec)); else two-way passes only.
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
-                                  hipStream_t s, void** result) {
-  return rec == 8 ? comparison_sort_t<8>(buf0, buf1, n, ts, split, s, result)
-                  : comparison_sort_t<16>(buf0, buf1, n, ts, split, s, result);
+                                  hipStream_t s, void** result, bool multiway) {
+  return rec == 8 ? comparison_sort_t<8>(buf0, buf1, n, ts, split, s, result, multiway)
+                  : comparison_sort_t<16>(buf0, buf1, n, ts, split, s, result, multiway);
 }
 
 template <int R>
