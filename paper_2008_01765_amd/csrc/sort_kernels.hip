@@ -371,64 +371,237 @@ __global__ void sample_gather_kernel(const void* src_, void* smp_, uint64_t n) {
     static_cast<T*>(smp_)[i] = static_cast<const T*>(src_)[i << kSmpLog<R>];
 }
 
-// One thread per sample: its rank among its group's samples; a sample whose
-// rank is a multiple of kSplM opens tile rank/kSplM of the group and stores
-// the absolute start of the tile in each of the four runs (spl[4*tile + k]).
+// Ranks of the samples in their group, kSplS<R> samples per thread with all
+// their searches advancing together (one round of loads per halving).  A
+// sample whose rank is a multiple of kSplM opens tile rank/kSplM of its group;
+// for it, spl[4*tile + k] receives the count of run k's samples before it
+// (k != its run j) and spl[4*tile + j] = kSplOwn | its sample index.
 template <int R>
-__global__ void merge4_split_kernel(const void* src_, const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf,
+constexpr uint32_t kSplS = R == 8 ? 4u : 2u;  // (more would spill registers)
+constexpr uint64_t kSplOwn = 1ull << 63;
+template <int R>
+__global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf, uint64_t* spl) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t LG = kSmpLog<R>;
+  constexpr uint64_t G = 1ull << LG;
+  const T* smp = static_cast<const T*>(smp_);
+  const uint64_t ns = (n + G - 1) >> LG, w = 1ull << lw;
+  const uint64_t i0 = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) * kSplS<R>;
+  if (i0 >= ns) return;
+  T e[kSplS<R>];
+  uint32_t j[kSplS<R>], own[kSplS<R>], c[kSplS<R>][4], cl[kSplS<R>][4], rb[kSplS<R>][4];
+  uint32_t maxl = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kSplS<R>; ++q) {
+    const uint64_t i = i0 + q < ns ? i0 + q : i0;  // past the end: repeat the first (not stored)
+    const uint64_t p = i << LG, gs = (p >> (lw + 2)) << (lw + 2);
+    j[q] = uint32_t(p >> lw) & 3u;
+    e[q] = smp[i];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint64_t st = gs + k * w < n ? gs + k * w : n, len = n - st < w ? n - st : w;
+      rb[q][k] = uint32_t(st >> LG);
+      own[q] = k == j[q] ? rb[q][k] : (k == 0 ? 0u : own[q]);
+      c[q][k] = 0;
+      cl[q][k] = k == j[q] ? 0u : uint32_t((len + G - 1) >> LG);
+      maxl = cl[q][k] > maxl ? cl[q][k] : maxl;
+    }
+  }
+  while (maxl > 0) {
+    maxl = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kSplS<R>; ++q) {
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        if (cl[q][k] == 0) continue;
+        const uint32_t half = cl[q][k] >> 1;
+        if (precedes(smp[uint64_t(rb[q][k]) + c[q][k] + half], k, e[q], j[q])) {
+          c[q][k] += half + 1;
+          cl[q][k] -= half + 1;
+        } else {
+          cl[q][k] = half;
+        }
+        maxl = cl[q][k] > maxl ? cl[q][k] : maxl;
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kSplS<R>; ++q) {
+    const uint64_t i = i0 + q;
+    if (i >= ns) continue;
+    const uint64_t p = i << LG, g = p >> (lw + 2);
+    const uint32_t r = uint32_t(i - own[q]) + c[q][0] + c[q][1] + c[q][2] + c[q][3];
+    if (r % kSplM != 0) continue;
+    uint64_t* out = spl + 4 * (g * ntf + r / kSplM);
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) out[k] = k == j[q] ? (kSplOwn | i) : uint64_t(c[q][k]);
+  }
+}
+
+// The same ranks when a workgroup's kSplW<R> samples lie in one run (the
+// sample runs hold at least kSplW<R> samples).  One wave finds, for each other
+// run k, how many of its samples precede the workgroup's first and last sample
+// (64-ary searches: a round of 64 probes and a ballot narrows the range 64-fold);
+// the samples between those two counts are copied to LDS, where each thread
+// searches for its own samples (in global memory if the window exceeds kSplCap).
+template <int R>
+constexpr uint32_t kSplW = 256u * kSplS<R>;
+template <int R>
+constexpr uint32_t kSplCap = R == 8 ? 2048u : 1024u;
+template <int R>
+__global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_, uint64_t n, uint32_t lw,
+                                                               uint64_t ntf, uint64_t* spl) {
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t LG = kSmpLog<R>, CAP = kSplCap<R>;
+  constexpr uint64_t G = 1ull << LG;
+  __shared__ T win[3 * CAP];
+  __shared__ uint32_t wlo[4], wlen[4];
+  const T* smp = static_cast<const T*>(smp_);
+  const uint64_t ns = (n + G - 1) >> LG, w = 1ull << lw;
+  const uint64_t base = uint64_t(blockIdx.x) * kSplW<R>;
+  const uint64_t last = (base + kSplW<R> < ns ? base + kSplW<R> : ns) - 1;
+  const uint64_t p0 = base << LG, g = p0 >> (lw + 2), gs = g << (lw + 2);
+  const uint32_t j = uint32_t(p0 >> lw) & 3u;
+  uint64_t rb[4];
+  uint32_t sc[4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    const uint64_t st = gs + k * w < n ? gs + k * w : n, len = n - st < w ? n - st : w;
+    rb[k] = st >> LG;
+    sc[k] = uint32_t((len + G - 1) >> LG);
+  }
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    const T ef = smp[base], el = smp[last];
+    uint32_t lo[4][2], hi[4][2];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+      for (uint32_t b = 0; b < 2; ++b) {
+        lo[k][b] = 0;
+        hi[k][b] = k == j ? 0u : sc[k];
+      }
+    bool more = true;
+    while (more) {
+      more = false;
+      // every open search's probe first (one round of loads), then the ballots
+      T x[4][2];
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+        for (uint32_t b = 0; b < 2; ++b) {
+          const uint32_t l = lo[k][b], h = hi[k][b], st = (h - l + 63) / 64, q = l + lane * st;
+          x[k][b] = smp[l < h ? rb[k] + (q < h ? q : l) : base];  // a closed search rereads a valid sample
+        }
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k)
+#pragma unroll
+        for (uint32_t b = 0; b < 2; ++b) {
+          if (lo[k][b] >= hi[k][b]) continue;  // uniform over the wave
+          const uint32_t l = lo[k][b], h = hi[k][b], st = (h - l + 63) / 64, q = l + lane * st;
+          const bool pr = q < h && precedes(x[k][b], k, sel(b != 0, el, ef), j);
+          const uint32_t f = uint32_t(__popcll(__ballot(pr)));
+          if (f == 0) {
+            hi[k][b] = l;
+          } else {
+            lo[k][b] = l + (f - 1) * st + 1;
+            hi[k][b] = l + f * st < h ? l + f * st : h;
+          }
+          more = more || lo[k][b] < hi[k][b];
+        }
+    }
+    if (lane == 0)
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        wlo[k] = lo[k][0];
+        wlen[k] = lo[k][1] - lo[k][0];
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    if (k == j || wlen[k] > CAP) continue;
+    const uint32_t slot = k < j ? k : k - 1;
+    for (uint32_t t = threadIdx.x; t < wlen[k]; t += 256) win[slot * CAP + t] = smp[rb[k] + wlo[k] + t];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t q = 0; q < kSplS<R>; ++q) {
+    const uint64_t i = base + q * 256u + threadIdx.x;
+    if (i > last) continue;
+    const T e = smp[i];
+    uint32_t c[4];
+    uint32_t r = uint32_t(i - rb[j]);
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      c[k] = 0;
+      if (k == j) continue;
+      const uint32_t slot = k < j ? k : k - 1;
+      const bool inl = wlen[k] <= CAP;
+      uint32_t l = 0, len = wlen[k];
+      while (len > 0) {
+        const uint32_t half = len >> 1;
+        const T x = inl ? win[slot * CAP + l + half] : smp[rb[k] + wlo[k] + l + half];
+        if (precedes(x, k, e, j)) {
+          l += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+      c[k] = wlo[k] + l;
+      r += c[k];
+    }
+    if (r % kSplM != 0) continue;
+    uint64_t* out = spl + 4 * (g * ntf + r / kSplM);
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) out[k] = k == j ? (kSplOwn | i) : uint64_t(c[k]);
+  }
+}
+
+// One thread per tile: the tile's exact start in each run.  Samples c-1 and
+// c of run k bracket the opening sample e, so the search covers the records
+// between them; the three searches advance together.
+template <int R>
+__global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t n, uint32_t lw, uint64_t total,
                                     uint64_t* spl) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t LG = kSmpLog<R>;
   constexpr uint64_t G = 1ull << LG;
   const T* src = static_cast<const T*>(src_);
-  const T* smp = static_cast<const T*>(smp_);
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= ((n + G - 1) >> LG)) return;
-  const uint64_t p = i << LG, w = 1ull << lw, g = p >> (lw + 2), gs = g << (lw + 2);
-  const uint32_t j = uint32_t(p >> lw) & 3u;
-  const T e = smp[i];
-  uint64_t st[4], len[4], c[4];
+  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  uint64_t wd[4];
+  uint32_t j = 0, owners = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; ++k) {
+    wd[k] = spl[4 * t + k];
+    j = (wd[k] & kSplOwn) ? k : j;
+    owners += (wd[k] & kSplOwn) ? 1u : 0u;
+  }
+  const uint64_t i = wd[j] & ~kSplOwn, p = i << LG, w = 1ull << lw, gs = (p >> (lw + 2)) << (lw + 2);
+  // entries not of the form the rank kernel writes: mark the tile invalid
+  // (the merge kernel skips it) rather than search out of bounds
+  bool ok = owners == 1 && i < ((n + G - 1) >> LG);
+  uint64_t st[4], lb[4], cl[4], maxl = 0;
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
     st[k] = gs + k * w < n ? gs + k * w : n;
-    len[k] = n - st[k] < w ? n - st[k] : w;
+    const uint64_t len = n - st[k] < w ? n - st[k] : w;
+    ok = ok && (k == j || wd[k] <= (len + G - 1) >> LG);
   }
-  // the three sample searches advance together (one round of loads per
-  // halving); c[k] = samples of run k before e, len of the open range in cl[k]
-  uint64_t cl[4], maxl = 0;
+  if (!ok) {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) spl[4 * t + k] = ~0ull;
+    return;
+  }
+  const T e = static_cast<const T*>(smp_)[i];
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
-    c[k] = 0;
-    cl[k] = k == j ? 0 : (len[k] + G - 1) >> LG;
-    maxl = cl[k] > maxl ? cl[k] : maxl;
-  }
-  while (maxl > 0) {
-    maxl = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-      if (cl[k] == 0) continue;
-      const uint64_t half = cl[k] >> 1;
-      if (precedes(smp[(st[k] >> LG) + c[k] + half], k, e, j)) {
-        c[k] += half + 1;
-        cl[k] -= half + 1;
-      } else {
-        cl[k] = half;
-      }
-      maxl = cl[k] > maxl ? cl[k] : maxl;
-    }
-  }
-  const uint64_t r = ((p - st[j]) >> LG) + c[0] + c[1] + c[2] + c[3];
-  if (uint32_t(r) % kSplM != 0) return;
-  uint64_t* out = spl + 4 * (g * ntf + uint32_t(r) / kSplM);
-  // Samples c-1 and c of run k bracket e: search the records between them,
-  // the three searches advancing together.  lb[k] = records of run k before e.
-  uint64_t lb[4];
-  maxl = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    lb[k] = k == j ? p - st[j] : c[k] > 0 ? (c[k] - 1) * G + 1 : 0;
-    const uint64_t hi = c[k] * G < len[k] ? c[k] * G : len[k];
-    cl[k] = k == j || c[k] == 0 ? 0 : hi - lb[k];
+    const uint64_t len = n - st[k] < w ? n - st[k] : w, ck = wd[k];
+    lb[k] = k == j ? p - st[k] : ck > 0 ? (ck - 1) * G + 1 : 0;
+    const uint64_t hi = ck * G < len ? ck * G : len;
+    cl[k] = k == j || ck == 0 ? 0 : hi - lb[k];
     maxl = cl[k] > maxl ? cl[k] : maxl;
   }
   while (maxl > 0) {
@@ -447,7 +620,7 @@ __global__ void merge4_split_kernel(const void* src_, const void* smp_, uint64_t
     }
   }
 #pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) out[k] = st[k] + lb[k];
+  for (uint32_t k = 0; k < 4; ++k) spl[4 * t + k] = st[k] + lb[k];
 }
 
 // ITEMS outputs, from output dd on, of the merge of A (na records at slot
@@ -823,8 +996,16 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
       prof_begin(BOS_K_SORT_MERGE, pass++, 2 * n * R, s);
       if (!have_sample)
         hipLaunchKernelGGL(sample_gather_kernel<R>, dim3(uint32_t((nsmp + 255) / 256)), dim3(256), 0, s, src, smp, n);
-      hipLaunchKernelGGL(merge4_split_kernel<R>, dim3(uint32_t((nsmp + 255) / 256)), dim3(256), 0, s, src, smp, n, lw,
-                         t.ntf, spl);
+      if ((w >> kSmpLog<R>) >= kSplW<R>) {
+        hipLaunchKernelGGL(merge4_rank_wide_kernel<R>, dim3(uint32_t((nsmp + kSplW<R> - 1) / kSplW<R>)), dim3(256), 0,
+                           s, smp, n, lw, t.ntf, spl);
+      } else {
+        const uint64_t rthreads = (nsmp + kSplS<R> - 1) / kSplS<R>;
+        hipLaunchKernelGGL(merge4_rank_kernel<R>, dim3(uint32_t((rthreads + 255) / 256)), dim3(256), 0, s, smp, n, lw,
+                           t.ntf, spl);
+      }
+      hipLaunchKernelGGL(merge4_bound_kernel<R>, dim3(uint32_t((t.total + 255) / 256)), dim3(256), 0, s, src, smp, n,
+                         lw, t.total, spl);
       hipLaunchKernelGGL(merge4_tile_kernel<R>, dim3(uint32_t(t.total)), dim3(kM4Threads<R>), merge_lds, s, src, dst, n,
                          lw, spl, t.ntf, t.ng, t.ntl, next4 ? smp : nullptr);
       prof_end(s);

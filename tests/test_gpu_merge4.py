@@ -42,11 +42,13 @@ def test_sort_four_way_passes(n, rec, tile):
     np.testing.assert_array_equal(out, cf.sorted_records(a))
 
 
+@pytest.mark.parametrize("n", [4096 * 24 + 513, (1 << 21) + 3])
 @pytest.mark.parametrize("rec", [8, 16])
 @pytest.mark.parametrize("distinct", [1, 3, 1000])
-def test_sort_four_way_repeated_records(rec, distinct):
-    # whole records repeated (key and payload), so ties cross every run
-    n = 4096 * 24 + 513
+def test_sort_four_way_repeated_records(n, rec, distinct):
+    # whole records repeated (key and payload), so ties cross every run; the
+    # larger n reaches runs wide enough for the workgroup-wide sample ranks,
+    # with windows of repeated samples larger than the LDS holds
     g = np.random.default_rng(distinct)
     dt = np.uint32 if rec == 8 else np.uint64
     v = g.integers(0, distinct, n)
