@@ -19,6 +19,18 @@ namespace bos {
 
 constexpr uint32_t kTileThreads = 512;
 
+// Every G-th record of a four-way merge pass's input is a sample (G = 2^kSmpLog).
+template <int R>
+constexpr uint32_t kSmpLog = R == 8 ? 6u : 5u;
+
+// A sorted tile's share of the samples: the records at multiples of G.  A
+// lane holds 16 consecutive records from a multiple of 16 (G >= 16), so only
+// its first record can be one.
+template <int R, typename T>
+__device__ __forceinline__ void write_sample(void* smp, uint64_t base, uint64_t n, T first) {
+  if (smp && (base & ((1ull << kSmpLog<R>) - 1)) == 0 && base < n) static_cast<T*>(smp)[base >> kSmpLog<R>] = first;
+}
+
 __device__ __forceinline__ uint32_t lpad(uint32_t s) { return s + (s >> 5); }
 
 // In-LDS bitonic network over `cnt` (power of two) records.  Ascending when
@@ -69,7 +81,7 @@ constexpr uint32_t tile_threads() { return (1u << TLOG) / 16u; }
 // network of the per-bin finish (record order; slots past n sort last as the
 // maximal record).
 template <int R, uint32_t TLOG>
-__device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t tile) {
+__device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t tile, void* smp) {
   using T = typename RecOf<R>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   T* srec = reinterpret_cast<T*>(smem);
@@ -84,11 +96,12 @@ __device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t ti
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e)
     if (base + e < n) B[base + e] = v[e].r;
+  write_sample<R>(smp, base, n, v[0].r);
 }
 
 template <int R, uint32_t TLOG>
-__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel(void* buf, uint64_t n) {
-  tile_sort_one<R, TLOG>(buf, n, blockIdx.x);
+__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel(void* buf, uint64_t n, void* smp) {
+  tile_sort_one<R, TLOG>(buf, n, blockIdx.x, smp);
 }
 
 // Segment holding launch index x (largest s with segs[s].first <= x).
@@ -108,7 +121,7 @@ template <int R, uint32_t TLOG>
 __global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel_b(const SortSeg* segs,
                                                                               uint32_t nsegs) {
   const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
-  tile_sort_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first);
+  tile_sort_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first, nullptr);
 }
 
 // Merge tiles: kMTile outputs per workgroup of 256 threads, kMItems per thread
@@ -264,7 +277,7 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
 // ascending half-cleaner stages inside each half.  It saves TLOG - 12 merge
 // passes over HBM.
 template <int R, uint32_t TLOG>
-__device__ __forceinline__ void tile_sort_big_one(void* buf, uint64_t n, uint64_t tile) {
+__device__ __forceinline__ void tile_sort_big_one(void* buf, uint64_t n, uint64_t tile, void* smp) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t kSub = 4096, kSubPad = kSub + kSub / 16;
   static_assert(TLOG == 13 || TLOG == 14, "two or four register tiles");
@@ -310,18 +323,19 @@ __device__ __forceinline__ void tile_sort_big_one(void* buf, uint64_t n, uint64_
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e)
     if (base + e < n) B[base + e] = v[e].r;
+  write_sample<R>(smp, base, n, v[0].r);
 }
 
 template <int R, uint32_t TLOG>
-__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel(void* buf, uint64_t n) {
-  tile_sort_big_one<R, TLOG>(buf, n, blockIdx.x);
+__global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel(void* buf, uint64_t n, void* smp) {
+  tile_sort_big_one<R, TLOG>(buf, n, blockIdx.x, smp);
 }
 
 template <int R, uint32_t TLOG>
 __global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel_b(const SortSeg* segs,
                                                                               uint32_t nsegs) {
   const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
-  tile_sort_big_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first);
+  tile_sort_big_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first, nullptr);
 }
 
 template <int R>
@@ -347,8 +361,6 @@ __global__ __launch_bounds__(kMThreads<R>) void merge_tile_kernel_b(const SortSe
 // splitter, one partial block, so a tile holds at most kSplM*G + 3(G-1)
 // records (4029 of 4096 for 8-byte records, 2013 of 2048 for 16-byte ones).
 
-template <int R>
-constexpr uint32_t kSmpLog = R == 8 ? 6u : 5u;  // log2 G
 // A four-way tile is merged by 512 threads, half a two-way tile's records each.
 template <int R>
 constexpr uint32_t kM4Items = kMItems<R> / 2;
@@ -901,7 +913,7 @@ bool sort_tile_ok(int rec, uint32_t t) {
 }
 
 template <int R, uint32_t TLOG>
-static hipError_t launch_tile_sort_t(void* buf, uint64_t n, hipStream_t s) {
+static hipError_t launch_tile_sort_t(void* buf, uint64_t n, hipStream_t s, void* smp) {
   constexpr bool BIG = TLOG > 12;
   static bool attr = false;
   if (!attr) {
@@ -913,9 +925,9 @@ static hipError_t launch_tile_sort_t(void* buf, uint64_t n, hipStream_t s) {
   const uint64_t tiles = (n + (1ull << TLOG) - 1) >> TLOG;
   const uint32_t threads = tile_threads<TLOG>(), lds = tile_sort_lds<R, TLOG>();
   if constexpr (BIG)
-    hipLaunchKernelGGL((tile_sort_big_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n);
+    hipLaunchKernelGGL((tile_sort_big_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n, smp);
   else
-    hipLaunchKernelGGL((tile_sort_reg_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n);
+    hipLaunchKernelGGL((tile_sort_reg_kernel<R, TLOG>), dim3(uint32_t(tiles)), dim3(threads), lds, s, buf, n, smp);
   return hipGetLastError();
 }
 
@@ -964,15 +976,21 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   if (!sort_tile_ok(R, ts)) return hipErrorInvalidValue;
   *result = buf0;
   if (n <= 1) return hipSuccess;
+  char* region = reinterpret_cast<char*>(split);
+  void* smp = region + align256(split2_bytes(n));
+  uint64_t* spl = reinterpret_cast<uint64_t*>(region + align256(split2_bytes(n)) + align256(sample_bytes(R, n)));
+  // the tile sort writes the first merge pass's samples when that pass is four-way
+  bool have_sample = multiway && ts < n && four_way_next(R, n, ts);
+  void* tsmp = have_sample ? smp : nullptr;
   prof_begin(BOS_K_SORT_TILE, 0, 2 * n * R, s);
   hipError_t e = hipErrorInvalidValue;
   switch (ts) {
-    case 1024: e = launch_tile_sort_t<R, 10>(buf0, n, s); break;
-    case 2048: e = launch_tile_sort_t<R, 11>(buf0, n, s); break;
-    case 4096: e = launch_tile_sort_t<R, 12>(buf0, n, s); break;
-    case 8192: e = launch_tile_sort_t<R, 13>(buf0, n, s); break;
+    case 1024: e = launch_tile_sort_t<R, 10>(buf0, n, s, tsmp); break;
+    case 2048: e = launch_tile_sort_t<R, 11>(buf0, n, s, tsmp); break;
+    case 4096: e = launch_tile_sort_t<R, 12>(buf0, n, s, tsmp); break;
+    case 8192: e = launch_tile_sort_t<R, 13>(buf0, n, s, tsmp); break;
     default:
-      if constexpr (R == 8) e = launch_tile_sort_t<R, 14>(buf0, n, s);
+      if constexpr (R == 8) e = launch_tile_sort_t<R, 14>(buf0, n, s, tsmp);
       break;
   }
   prof_end(s);
@@ -982,10 +1000,6 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   uint32_t pass = 0;
   const uint64_t mtiles = (n + kMTile<R> - 1) / kMTile<R>;
   const uint32_t merge_lds = (kMTile<R> + (kMTile<R> >> 4)) * uint32_t(R);
-  char* region = reinterpret_cast<char*>(split);
-  void* smp = region + align256(split2_bytes(n));
-  uint64_t* spl = reinterpret_cast<uint64_t*>(region + align256(split2_bytes(n)) + align256(sample_bytes(R, n)));
-  bool have_sample = false;
   for (uint64_t w = ts; w < n;) {
     if (multiway && four_way_next(R, n, w)) {
       uint32_t lw = 0;
