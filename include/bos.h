@@ -110,8 +110,9 @@ bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos
 /* Bucket oblivious sort (Section 3.3): the ORP's bin assignment (each bin
  * compacted obliviously; a bin that straddles a tile of the first sort phase is
  * sorted obliviously, every other bin is ordered by the oblivious tile sort),
- * then a non-oblivious comparison (merge) sort.  out = in sorted by
- * (key, payload); the output does not depend on seed, Z, k or tile. */
+ * then a non-oblivious comparison (merge) sort whose passes merge four runs
+ * at a time once runs span a merge tile.  out = in sorted by (key, payload);
+ * the output does not depend on seed, Z, k or tile. */
 bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
                     void* ws, size_t ws_bytes, void* stream, bos_report* rep);
 
@@ -273,7 +274,7 @@ typedef enum {
   BOS_K_ROUTE_LAST = 3,   /* last routing pass: levels, per-bin finish, strip */
   BOS_K_ROUTE_SINGLE = 4, /* first and last pass at once (L <= k) */
   BOS_K_SORT_TILE = 5,    /* comparison sort: tile sort */
-  BOS_K_SORT_MERGE = 6,   /* comparison sort: one merge pass */
+  BOS_K_SORT_MERGE = 6,   /* comparison sort: one merge pass (two-way, or four-way with its splitters) */
   BOS_K_BITONIC_TILE = 7, /* bitonic baseline: local phases */
   BOS_K_BITONIC_GLOBAL = 8,
   BOS_K_BITONIC_TAIL = 9,
