@@ -359,9 +359,11 @@ __global__ __launch_bounds__(kMThreads<R>) void merge_tile_kernel_b(const SortSe
 // a tile.  Between two such splitters each run holds at most its splitter
 // samples' G-blocks plus, for the three runs that do not own the opening
 // splitter, one partial block, so a tile holds at most kSplM*G + 3(G-1)
-// records (4029 of 4096 for 8-byte records, 2013 of 2048 for 16-byte ones).
+// records (4029 of 4096 for 8-byte records, 2013 of 2048 for 16-byte ones;
+// aligning the second merge result adds at most ITEMS-1 slots).
 
-// A four-way tile is merged by 512 threads, half a two-way tile's records each.
+// A four-way tile is merged by 512 threads, each with half the records of a
+// two-way pass's thread.
 template <int R>
 constexpr uint32_t kM4Items = kMItems<R> / 2;
 template <int R>
@@ -374,7 +376,8 @@ __device__ __forceinline__ bool precedes(T x, uint32_t kx, T e, uint32_t ke) {
   return kx < ke ? !rec_less(e, x) : rec_less(x, e);
 }
 
-// Sample of the input of the first four-way pass: smp[i] = src[i*G].
+// Samples of a four-way pass's input, smp[i] = src[i*G], when a two-way pass
+// produced it (the tile sort and the four-way tile kernel write their own).
 template <int R>
 __global__ void sample_gather_kernel(const void* src_, void* smp_, uint64_t n) {
   using T = typename RecOf<R>::T;
