@@ -48,7 +48,10 @@ typedef enum {
   BOS_ERR_WORKSPACE = 3,   /* ws NULL or smaller than bos_workspace_bytes() */
   BOS_ERR_HIP = 4,         /* a HIP runtime call failed */
   BOS_ERR_INSECURE_Z = 5,  /* log2 of the Lemma 3.2 failure bound exceeds -min_security_bits */
-  BOS_ERR_UNSUPPORTED = 6  /* no GPU, or a parameter combination the kernels do not cover */
+  BOS_ERR_UNSUPPORTED = 6, /* no GPU, or a parameter combination the kernels do not cover */
+  BOS_ERR_INTERNAL = 7     /* a consistency check of the comparison sort failed (a merge
+                              tile whose bounds break the splitters' guarantee was
+                              skipped); reported by bos_sort under BOS_SYNC */
 } bos_status;
 
 typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
@@ -64,7 +67,12 @@ typedef struct {
                                  [8, 2048]; 0 = the tuning table's, else 512 (the
                                  paper's choice) */
   uint32_t k;                 /* butterfly levels fused per pass; 0 = the tuning
-                                 table's, else the planner's choice (3) */
+                                 table's, else the planner's choice (3), either
+                                 capped at what fits.  An explicit k whose block
+                                 of 2^k buckets does not fit in LDS (64 KiB..160
+                                 KiB by Z and record size) or in one workgroup
+                                 is rejected with BOS_ERR_UNSUPPORTED; k > 12
+                                 with BOS_ERR_INVALID_ARG */
   uint32_t tile;              /* records per tile of the final sort: 1024, 2048,
                                  4096, 8192 or (8-byte records) 16384; 0 = the
                                  tuning table's, else 4096 */

@@ -8,7 +8,7 @@
  *
  * The code follows the paper in its own order:
  *   plan            Algorithm 3.1 (choice of Z and B), Section 3.1
- *   labels          Algorithm 3.1 (a uniformly random key in [0, B-1] per element)
+ *   labels          Algorithm 3.1 (every element draws its destination bin uniformly)
  *   placement       Algorithm 3.1 (B even groups, padded with dummies to Z)
  *   butterfly       Algorithm 3.1 (levels i, pairs j, MergeSplit, overflow abort)
  *   ORP finish      Section 3.2 (delete dummies, permute each bin, concatenate)

@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbos.so")
 
-OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED = range(7)
+OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED, INTERNAL = range(8)
 SYNC = 1
 GENERIC_ROUTING = 2
 

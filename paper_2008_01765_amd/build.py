@@ -24,20 +24,34 @@ def flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose=False, jobs=None):
-    """Compile every HIP source and link libbos.so.  Always recompiles."""
+def _headers_mtime():
+    t = 0.0
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in os.listdir(d):
+            if f.endswith(".h"):
+                t = max(t, os.path.getmtime(os.path.join(d, f)))
+    return t
+
+
+def build(verbose=False, jobs=None, force=True):
+    """Compile every HIP source and link libbos.so.  force=False recompiles
+    only objects older than their source or any header."""
     if jobs is None:
         jobs = max(1, min(16, os.cpu_count() or 4))
     objs = []
     procs = []
+    hdr = _headers_mtime()
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
         os.makedirs(os.path.dirname(obj), exist_ok=True)
+        objs.append(obj)
+        if not force and os.path.exists(obj) and \
+                os.path.getmtime(obj) >= max(hdr, os.path.getmtime(os.path.join(CSRC, src))):
+            continue
         cmd = [HIPCC] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        objs.append(obj)
         if len(procs) >= jobs:
             _wait(procs.pop(0))
     while procs:
@@ -61,4 +75,4 @@ def _wait(item):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--changed" not in sys.argv))

@@ -38,6 +38,7 @@ hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, u
 uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
 uint32_t comparison_sort_hbm_passes(int rec, uint64_t n, uint32_t ts, bool multiway);
 size_t comparison_sort_split_bytes(uint64_t n, int rec);
+unsigned long long* comparison_sort_err_word(uint64_t* split, uint64_t n, int rec);
 hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, const PassArgs* segs,
                                 const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
                                 uint32_t lds, hipStream_t s, bool split);
@@ -246,6 +247,10 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   if (kmid == 0 || klast == 0) return BOS_ERR_UNSUPPORTED;
   // default: 3 levels per pass (a block of 2^3 Z slots leaves LDS for three
   // workgroups per CU at Z = 512, which outruns fewer, larger passes)
+  // An explicit k must fit a block of 2^k buckets in LDS and in one
+  // workgroup; the tuned or default k is capped at what fits.
+  if (q.k > 12) return BOS_ERR_INVALID_ARG;
+  if (q.k > kmid) return BOS_ERR_UNSUPPORTED;
   const uint32_t kreq = q.k ? q.k : (tuned && te.k && te.z == Z ? te.k : 3u);
   const uint32_t k = std::min(kreq, kmid);
   pl->k = k;
@@ -973,7 +978,12 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
     if (e != hipSuccess) return BOS_ERR_HIP;
   }
   if (q.flags & BOS_SYNC) {
-    if (hipStreamSynchronize(s) != hipSuccess) return BOS_ERR_HIP;
+    unsigned long long err = 0;
+    if (hipMemcpyAsync(&err, comparison_sort_err_word(reinterpret_cast<uint64_t*>(w + pl.off_split), n, pl.rec), 8,
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return BOS_ERR_HIP;
+    if (err) return BOS_ERR_INTERNAL;
   }
   fill_report(rep, pl, attempts, ovf, uint64_t(2 + 2 * passes) * n * pl.rec);
   return BOS_OK;
@@ -1598,6 +1608,7 @@ const char* bos_status_string(bos_status s) {
     case BOS_ERR_HIP: return "HIP runtime error";
     case BOS_ERR_INSECURE_Z: return "Z below the security floor";
     case BOS_ERR_UNSUPPORTED: return "unsupported (no GPU or parameters)";
+    case BOS_ERR_INTERNAL: return "internal consistency check failed (merge tile bounds)";
   }
   return "unknown status";
 }

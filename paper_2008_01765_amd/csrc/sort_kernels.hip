@@ -369,6 +369,11 @@ constexpr uint32_t kM4Items = kMItems<R> / 2;
 template <int R>
 constexpr uint32_t kM4Threads = kMTile<R> / kM4Items<R>;
 constexpr uint32_t kSplM = 60;                  // samples per tile
+// the tile bound above, with the alignment slots, fits a merge tile
+static_assert(kSplM * (1u << kSmpLog<8>) + 3u * ((1u << kSmpLog<8>) - 1u) + kM4Items<8> - 1u <= kMTile<8>,
+              "four-way tile bound, 8-byte records");
+static_assert(kSplM * (1u << kSmpLog<16>) + 3u * ((1u << kSmpLog<16>) - 1u) + kM4Items<16> - 1u <= kMTile<16>,
+              "four-way tile bound, 16-byte records");
 
 // Does record x of run kx come before record e of run ke (x != e's slot)?
 template <typename T>
@@ -679,7 +684,7 @@ __device__ __forceinline__ void merge_items_lds(const T* s, uint32_t xa, uint32_
 template <int R>
 __device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, uint64_t n, uint32_t lw,
                                                 const uint64_t* spl, uint64_t ntf, uint64_t ng, uint64_t ntl,
-                                                void* smp_, uint64_t tile) {
+                                                void* smp_, uint64_t tile, unsigned long long* err) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t IT = kM4Items<R>, NT = kM4Threads<R>, TT = kMTile<R>, LG = kSmpLog<R>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -699,11 +704,21 @@ __device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, ui
     ok = ok && st <= a[k] && a[k] <= e[k] && e[k] <= en;
     o0 += a[k] - st;
   }
-  if (!ok) return;
+  // A tile whose bounds break what the splitters guarantee is skipped (no
+  // access out of bounds) and reported in the error word, which the host
+  // turns into a non-OK status.
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(err, 1ull);
+    return;
+  }
   const uint32_t n0 = uint32_t(e[0] - a[0]), n1 = uint32_t(e[1] - a[1]), n2 = uint32_t(e[2] - a[2]),
                  n3 = uint32_t(e[3] - a[3]);
   const uint32_t nx = n0 + n1, ny = n2 + n3, cnt = nx + ny, nxa = (nx + IT - 1) & ~(IT - 1);
-  if (cnt == 0 || nxa + ny > TT) return;
+  if (nxa + ny > TT) {
+    if (threadIdx.x == 0) atomicOr(err, 1ull);
+    return;
+  }
+  if (cnt == 0) return;
   {
     using V = typename NativeOf<T>::V;
     const V* srcv = reinterpret_cast<const V*>(src);
@@ -762,8 +777,8 @@ __device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, ui
 template <int R>
 __global__ __launch_bounds__(kM4Threads<R>) void merge4_tile_kernel(const void* src, void* dst, uint64_t n, uint32_t lw,
                                                                 const uint64_t* spl, uint64_t ntf, uint64_t ng,
-                                                                uint64_t ntl, void* smp) {
-  merge4_tile_one<R>(src, dst, n, lw, spl, ntf, ng, ntl, smp, blockIdx.x);
+                                                                uint64_t ntl, void* smp, unsigned long long* err) {
+  merge4_tile_one<R>(src, dst, n, lw, spl, ntf, ng, ntl, smp, blockIdx.x, err);
 }
 
 // Tiles of a four-way pass over runs of width 2^lw: per full group (ntf), in
@@ -966,6 +981,9 @@ static bool four_way_next(int rec, uint64_t n, uint64_t w) {
   return w >= merge_tile_records(rec) && l >= 2 && l % 2 == 0;
 }
 
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
+unsigned long long* comparison_sort_err_word(uint64_t* split, uint64_t n, int rec);
+
 template <int R>
 static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                     hipStream_t s, void** result, bool multiway) {
@@ -982,6 +1000,11 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   char* region = reinterpret_cast<char*>(split);
   void* smp = region + align256(split2_bytes(n));
   uint64_t* spl = reinterpret_cast<uint64_t*>(region + align256(split2_bytes(n)) + align256(sample_bytes(R, n)));
+  unsigned long long* err = comparison_sort_err_word(split, n, R);
+  if (multiway) {
+    hipError_t e0 = launch_fill_u64(err, 1, 0ull, s);
+    if (e0 != hipSuccess) return e0;
+  }
   // the tile sort writes the first merge pass's samples when that pass is four-way
   bool have_sample = multiway && ts < n && four_way_next(R, n, ts);
   void* tsmp = have_sample ? smp : nullptr;
@@ -1024,7 +1047,7 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
       hipLaunchKernelGGL(merge4_bound_kernel<R>, dim3(uint32_t((t.total + 255) / 256)), dim3(256), 0, s, src, smp, n,
                          lw, t.total, spl);
       hipLaunchKernelGGL(merge4_tile_kernel<R>, dim3(uint32_t(t.total)), dim3(kM4Threads<R>), merge_lds, s, src, dst, n,
-                         lw, spl, t.ntf, t.ng, t.ntl, next4 ? smp : nullptr);
+                         lw, spl, t.ntf, t.ng, t.ntl, next4 ? smp : nullptr, err);
       prof_end(s);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -1069,7 +1092,15 @@ uint32_t comparison_sort_hbm_passes(int rec, uint64_t n, uint32_t ts, bool multi
 
 // Bytes of the split region the merge passes need.
 size_t comparison_sort_split_bytes(uint64_t n, int rec) {
-  return align256(split2_bytes(n)) + align256(sample_bytes(rec, n)) + spl4_bytes(rec, n);
+  return align256(split2_bytes(n)) + align256(sample_bytes(rec, n)) + align256(spl4_bytes(rec, n)) + 256;
+}
+
+// The four-way passes' error word: nonzero once a tile failed its bound
+// checks (cleared at the start of every comparison sort with four-way passes).
+unsigned long long* comparison_sort_err_word(uint64_t* split, uint64_t n, int rec) {
+  char* region = reinterpret_cast<char*>(split);
+  return reinterpret_cast<unsigned long long*>(region + align256(split2_bytes(n)) + align256(sample_bytes(rec, n)) +
+                                               align256(spl4_bytes(rec, n)));
 }
 
 // multiway: four-way passes where they apply (split must then hold

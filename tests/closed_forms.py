@@ -5,10 +5,10 @@ Everything here is derived from the paper's statements, not from the oracle's
 code:
   * random numbers come from numpy.random.Philox (an independent Philox4x64-10),
   * bucket membership at every level comes from the closed form implied by the
-    index formula of Algorithm 3.1 and the caption of Figure 1 ("at level i
-    every 2^i consecutive buckets are semi-sorted by the i most significant
-    bits"): element x with initial group s and label l sits, at level i, in
-    bucket 2^i * floor(s / 2^i) + floor(l / 2^(L-i)),
+    index formula of Algorithm 3.1 and the invariant stated under Figure 1
+    (after i levels, each aligned run of 2^i buckets is partitioned by the top
+    i label bits): element x with initial group s and label l sits, at level
+    i, in bucket 2^i * floor(s / 2^i) + floor(l / 2^(L-i)),
   * the access sequence comes from the simulator of Lemma 3.3 (a fixed routing
     pattern plus the loads of the final bins).
 """
@@ -125,6 +125,49 @@ def expected_orp(recs, seed, attempt, lab, B, Z):
     if not out:
         return np.zeros((0, 2), dtype=recs.dtype)
     return np.concatenate(out)
+
+
+def _ordered_i64(col):
+    """A uint32 or uint64 numpy column as int64 values with the same order."""
+    if col.dtype == np.uint32:
+        return col.astype(np.int64)
+    return (col.view(np.int64) ^ np.int64(-(1 << 63)))
+
+
+def expected_orp_vec(recs, seed, attempt, lab, B, Z, device="cpu"):
+    """expected_orp by whole-array library sorts (torch's stable sort), for
+    sizes where the per-bin loop is too slow: group the elements by bin (=
+    label) in record order, give the p-th element of bin b the key
+    r(b*Z + p), and order each bin by (r, p).  Returns a numpy array."""
+    import torch
+
+    n = recs.shape[0]
+    if n == 0:
+        return np.zeros((0, 2), dtype=recs.dtype)
+    dev = torch.device(device)
+    key = torch.from_numpy(_ordered_i64(recs[:, 0])).to(dev)
+    pay = torch.from_numpy(_ordered_i64(recs[:, 1])).to(dev)
+    lb = torch.from_numpy(lab.astype(np.int64)).to(dev)
+    idx = torch.argsort(pay, stable=True)
+    idx = idx[torch.argsort(key[idx], stable=True)]
+    idx = idx[torch.argsort(lb[idx], stable=True)]
+    del key, pay
+    lab_s = lb[idx]
+    del lb
+    counts = torch.bincount(lab_s, minlength=B)
+    off = torch.cumsum(counts, 0) - counts
+    p = torch.arange(n, device=dev) - off[lab_s]
+    g = lab_s * Z + p
+    nblk = (int(B) * int(Z) + 3) // 4
+    rk = philox_blocks(seed, 1, attempt, 0, nblk).reshape(-1)
+    r_all = torch.from_numpy(_ordered_i64(rk)).to(dev)
+    del rk
+    r = r_all[g]
+    del r_all, g, p
+    idx2 = torch.argsort(r, stable=True)
+    idx2 = idx2[torch.argsort(lab_s[idx2], stable=True)]
+    order = idx[idx2].cpu().numpy()
+    return recs[order]
 
 
 def sorted_records(recs):

@@ -30,3 +30,33 @@ def record_checksum(a):
         z *= np.uint64(0xBF58476D1CE4E5B9)
         z ^= z >> np.uint64(32)
         return int(z.sum(dtype=np.uint64)), int(np.bitwise_xor.reduce(z)) if z.size else 0
+
+
+def _unsigned_order_i64(col):
+    """int32 / int64 record column (bits taken as unsigned) as int64 values
+    with the unsigned order (torch has no 64-bit unsigned sort)."""
+    import torch
+    if col.dtype == torch.int32:
+        return col.to(torch.int64) & 0xFFFFFFFF
+    return col ^ torch.iinfo(torch.int64).min
+
+
+def torch_sorted_records(t):
+    """Records of a CUDA tensor sorted by (key, payload), unsigned, with torch's
+    library sort."""
+    import torch
+    k = _unsigned_order_i64(t[:, 0])
+    p = _unsigned_order_i64(t[:, 1])
+    idx = torch.argsort(p, stable=True)
+    idx = idx[torch.argsort(k[idx], stable=True)]
+    return t[idx]
+
+
+def torch_is_sorted(t):
+    """True when the records of a CUDA tensor are in (key, payload) order."""
+    k = _unsigned_order_i64(t[:, 0])
+    p = _unsigned_order_i64(t[:, 1])
+    if t.shape[0] < 2:
+        return True
+    ok = (k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (p[1:] >= p[:-1]))
+    return bool(ok.all())

@@ -205,30 +205,6 @@ def test_duplicate_keys_workload_sort():
     np.testing.assert_array_equal(out2, out)
 
 
-def test_duplicate_keys_workload_orp_sampled_bins():
-    # Full size ORP: permutation property and the content of sampled bins by
-    # the closed form (bin = label; record order, then the per-bin keys).
-    a = inputs.workload_dup(43)
-    n = a.shape[0]
-    out, rep = bos.orp(_gpu(a), seed=1, report=True)
-    o = bos.to_numpy(out)
-    assert record_checksum(o) == record_checksum(a)
-    B, L, Z = rep["buckets"], rep["levels"], rep["z"]
-    att = rep["attempts"] - 1
-    lab = cf.labels(1, att, n, L)
-    loads = np.bincount(lab, minlength=B)
-    off = np.concatenate([[0], np.cumsum(loads)])
-    rng = np.random.default_rng(0)
-    for b in rng.choice(B, 24, replace=False):
-        idx = np.nonzero(lab == b)[0]
-        kk = a[idx, 0]
-        pp = a[idx, 1]
-        ordered = idx[np.lexsort((pp, kk))]
-        r = cf.shuffle_keys(1, att, int(b) * Z, idx.size)
-        want = a[ordered[np.lexsort((np.arange(idx.size), r))]]
-        np.testing.assert_array_equal(o[off[b]:off[b + 1]], want)
-
-
 def test_sort_uses_split_last_pass_orp_fused():
     # bos_sort of a multi-pass plan runs the split last pass (persistent last
     # pass, then scan + strip); bos_orp keeps the fused last pass.  Both stay
@@ -272,40 +248,3 @@ def test_routing_pattern_independent_of_data():
         launches.append([(l["kind"], l["index"], l["bytes"]) for l in bos.profile_read()])
         bos.profile_enable(False)
     assert launches[0] == launches[1]
-
-
-def test_headline_workload_full_size():
-    # n = 2^28 records of 8 bytes (uniform u32 key, payload = index), Z = 512
-    # and the planner's k: the configuration the benchmark times.  Sort: the
-    # output is sorted by (key, payload), is a permutation of the input, and
-    # holds the exact record at sampled ranks.  ORP: a permutation of the
-    # input whose sampled bins equal the closed form (bin = label; the bin's
-    # records in record order, then ordered by the per-bin keys).
-    n = 1 << 28
-    a = inputs.records(n, 8, 42)
-    x = _gpu(a)
-    out, rep = bos.sort(x, seed=1, z=512, report=True)
-    assert rep["z"] == 512 and rep["k"] == 3
-    o = bos.to_numpy(out)
-    del out
-    key = (a[:, 0].astype(np.uint64) << np.uint64(32)) | a[:, 1].astype(np.uint64)
-    okey = (o[:, 0].astype(np.uint64) << np.uint64(32)) | o[:, 1].astype(np.uint64)
-    assert np.all(okey[1:] >= okey[:-1])
-    assert record_checksum(o) == record_checksum(a)
-    ranks = np.sort(np.random.default_rng(5).choice(n, 64, replace=False))
-    np.testing.assert_array_equal(okey[ranks], np.partition(key, ranks)[ranks])
-    del o, okey, key
-    out, rep = bos.orp(x, seed=1, z=512, report=True)
-    o = bos.to_numpy(out)
-    del out, x
-    assert record_checksum(o) == record_checksum(a)
-    B, L, Z = rep["buckets"], rep["levels"], rep["z"]
-    att = rep["attempts"] - 1
-    lab = cf.labels(1, att, n, L)
-    off = np.concatenate([[0], np.cumsum(np.bincount(lab, minlength=B))])
-    for b in np.random.default_rng(6).choice(B, 16, replace=False):
-        idx = np.nonzero(lab == b)[0]
-        ordered = idx[np.lexsort((a[idx, 1], a[idx, 0]))]
-        r = cf.shuffle_keys(1, att, int(b) * Z, idx.size)
-        want = a[ordered[np.lexsort((np.arange(idx.size), r))]]
-        np.testing.assert_array_equal(o[off[b]:off[b + 1]], want)

@@ -281,6 +281,51 @@ def test_orp_uniform_permutation(oracle_lib):
     assert p > 1e-4
 
 
+def test_orp_single_bin_shuffle_uniform(oracle_lib):
+    # Section 3.2 with no butterfly level (B = 1, L = 0, as 2n <= Z): the
+    # output is the per-bin random permutation alone, so this pins the per-bin
+    # shuffle apart from the routing.  Over seeds, every one of the 5! orders
+    # of five distinct records must be equally likely.  The records enter out
+    # of record order so that a shuffle that kept (or sorted) the input order
+    # fails.
+    n = 5
+    recs = np.array([[30, 0], [10, 1], [40, 2], [0, 3], [20, 4]], dtype=np.uint32)
+    assert oracle_lib.plan(n, 16) == (1, 0)
+    perms = {}
+    trials = 30000
+    for seed in range(trials):
+        out = oracle_lib.orp(recs, seed, z=16, max_retries=0)["out"]
+        key = tuple(int(v) for v in out[:, 1])
+        perms[key] = perms.get(key, 0) + 1
+    assert len(perms) == math.factorial(n)
+    assert all(sorted(p) == list(range(n)) for p in perms)
+    p = stats.chisquare(np.array(list(perms.values()))).pvalue
+    assert p > 1e-4
+    # each record lands in each position with probability 1/n
+    pos = np.zeros((n, n))
+    for k, c in perms.items():
+        for t, rid in enumerate(k):
+            pos[rid, t] += c
+    assert stats.chisquare(pos.reshape(-1)).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("n,rec,z,kb", [(1 << 12, 8, 64, None), (5000, 16, 32, 4), (3001, 8, 16, 6),
+                                        (1, 8, 512, None), (300, 16, 512, None)])
+def test_vectorised_orp_closed_form(oracle_lib, n, rec, z, kb):
+    # The library-sort form of the ORP closed form (used at sizes where the
+    # per-bin loop is too slow) equals the per-bin loop and the oracle.
+    recs = _recs(n, rec, key_bits=kb)
+    if kb is not None:
+        recs[:, 1] = recs[:, 1] % 5  # byte-identical records too
+    B, L = oracle_lib.plan(n, z)
+    r = oracle_lib.orp(recs, 11, z=z, max_retries=40)
+    a = r["report"]["attempts"] - 1
+    lab = cf.labels(11, a, n, L)
+    want = cf.expected_orp(recs, 11, a, lab, B, z)
+    np.testing.assert_array_equal(cf.expected_orp_vec(recs, 11, a, lab, B, z), want)
+    np.testing.assert_array_equal(r["out"], want)
+
+
 def test_loads_multinomial(oracle_lib):
     # Lemma 3.3's simulator draws the loads by throwing n balls into B bins.
     n, z = 1 << 12, 64
