@@ -189,6 +189,10 @@ def release_workspaces():
 def workspace_bytes(n, rec, p):
     nb = lib().bos_workspace_bytes(n, rec, C.byref(p))
     if nb == 0:
+        # the planner's own status says why (bos_plan runs the same planner)
+        b, l = C.c_uint64(), C.c_uint32()
+        passes = (C.c_uint32 * 33)()
+        _check(lib().bos_plan(n, rec, C.byref(p), C.byref(b), C.byref(l), passes))
         raise BosError(INVALID_ARG, "libbos: no workspace size for these arguments")
     return nb
 

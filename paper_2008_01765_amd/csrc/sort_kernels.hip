@@ -996,15 +996,16 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   }
   if (!sort_tile_ok(R, ts)) return hipErrorInvalidValue;
   *result = buf0;
+  // the error word is cleared on every call, before anything can return
+  unsigned long long* err = comparison_sort_err_word(split, n, R);
+  {
+    const hipError_t e0 = launch_fill_u64(err, 1, 0ull, s);
+    if (e0 != hipSuccess) return e0;
+  }
   if (n <= 1) return hipSuccess;
   char* region = reinterpret_cast<char*>(split);
   void* smp = region + align256(split2_bytes(n));
   uint64_t* spl = reinterpret_cast<uint64_t*>(region + align256(split2_bytes(n)) + align256(sample_bytes(R, n)));
-  unsigned long long* err = comparison_sort_err_word(split, n, R);
-  if (multiway) {
-    hipError_t e0 = launch_fill_u64(err, 1, 0ull, s);
-    if (e0 != hipSuccess) return e0;
-  }
   // the tile sort writes the first merge pass's samples when that pass is four-way
   bool have_sample = multiway && ts < n && four_way_next(R, n, ts);
   void* tsmp = have_sample ? smp : nullptr;

@@ -53,7 +53,7 @@ def test_labels_match(L):
 ORP_CASES = [  # n, rec, Z, k
     (1 << 16, 8, 512, 4),     # the small workload
     (1 << 17, 8, 256, 4),
-    (1 << 17, 16, 2048, 2),
+    (1 << 17, 16, 2048, 1),   # one level per pass: a block of 4 such buckets exceeds LDS
     (100000, 8, 1024, 3),     # ragged: first pass staged through LDS
     (1024, 8, 16, 4),         # tiny Z: several attempts overflow first
     (5000, 16, 128, 1),       # last pass with 16 of 64 lanes holding bins
@@ -172,6 +172,19 @@ def test_invalid_arguments():
     for z in (0 + 3, 4, 4096, 96):
         with pytest.raises(bos.BosError):
             bos.orp(a, seed=1, z=z, min_security_bits=0)
+
+
+@pytest.mark.parametrize("rec,z,k", [(16, 2048, 2), (8, 1024, 4), (16, 1024, 4), (8, 2048, 3)])
+def test_explicit_k_that_does_not_fit_is_rejected(rec, z, k):
+    # a block of 2^k buckets of Z slots beyond LDS: rejected, never clamped
+    a = _gpu(_recs(1 << 16, rec))
+    for fn in (bos.orp, bos.sort):
+        with pytest.raises(bos.BosError) as ei:
+            fn(a, seed=1, z=z, k=k, min_security_bits=0)
+        assert ei.value.status == bos.UNSUPPORTED
+    with pytest.raises(bos.BosError) as ei:
+        bos.orp(a, seed=1, z=512, k=13, min_security_bits=0)
+    assert ei.value.status == bos.INVALID_ARG
 
 
 def test_orp_independent_of_k(ora):
