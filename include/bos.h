@@ -124,6 +124,20 @@ bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos
 bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
                     void* ws, size_t ws_bytes, void* stream, bos_report* rep);
 
+/* bos_sort without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a 64 MiB array inside the library,
+ * one per GPU, held until the process ends; the call allocates nothing.
+ * Limit: the plan's workspace (bos_workspace_bytes) must fit in 64 MiB, which
+ * holds n <= 2^20 records of 8 bytes or n <= 2^19 of 16 bytes at Z = 512;
+ * larger n returns BOS_ERR_WORKSPACE before anything is launched.  Every call
+ * on one GPU uses that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.  The
+ * array keeps the last call's contents; the call clears what it needs.
+ * Arguments, output and errors otherwise as bos_sort. */
+bos_status bos_sort_noalloc(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p,
+                            void* stream, bos_report* rep);
+
 /* Workspace for bos_sort_batched over `count` instances of the given sizes. */
 size_t bos_batched_workspace_bytes(const uint64_t* n, uint32_t count, bos_rec rec,
                                    const bos_params* p);

@@ -74,7 +74,7 @@ EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
            "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning",
-           "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async"]
+           "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async", "bos_sort_noalloc"]
 
 _lib = None
 
@@ -95,6 +95,8 @@ def lib():
         for fn in (L.bos_orp, L.bos_sort):
             fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, R]
             fn.restype = C.c_int
+        L.bos_sort_noalloc.argtypes = [vp, vp, u64, C.c_int, P, vp, R]
+        L.bos_sort_noalloc.restype = C.c_int
         L.bos_batched_workspace_bytes.argtypes = [C.POINTER(u64), u32, C.c_int, P]
         L.bos_batched_workspace_bytes.restype = C.c_size_t
         L.bos_sort_batched.argtypes = [C.POINTER(Instance), u32, C.c_int, P, vp, C.c_size_t, vp, vp, R]
@@ -226,6 +228,21 @@ def sort(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=N
     p = params(seed, z, k, tile, max_retries, min_security_bits, sync=sync, generic=generic)
     o, rep = _run(lib().bos_sort, t, p, out, stream)
     return (o, rep) if report else o
+
+
+def sort_noalloc(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
+                 report=False):
+    """bos_sort with the library's own workspace (bos_sort_noalloc): no
+    workspace is allocated; n is limited by that workspace's 64 MiB."""
+    rec = rec_bytes(t)
+    n = t.shape[0]
+    if out is None:
+        out = torch.empty_like(t)
+    p = params(seed, z, k, tile, max_retries, min_security_bits)
+    rep = Report()
+    _check(lib().bos_sort_noalloc(C.c_void_p(t.data_ptr()), C.c_void_p(out.data_ptr()), n, rec, C.byref(p),
+                                  _stream(stream), C.byref(rep)))
+    return (out, rep.as_dict()) if report else out
 
 
 def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, outs=None,

@@ -939,8 +939,16 @@ bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos
   return st;
 }
 
-bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* ws,
-                    size_t ws_bytes, void* stream, bos_report* rep) {
+}  // extern "C"
+
+// Workspace of bos_sort_noalloc (see below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+bos_status sort_impl(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* ws,
+                     size_t ws_bytes, void* stream, bos_report* rep) {
   if (!has_gpu()) return BOS_ERR_UNSUPPORTED;
   const bos_params q = resolve(p);
   Plan pl;
@@ -987,6 +995,51 @@ bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bo
   }
   fill_report(rep, pl, attempts, ovf, uint64_t(2 + 2 * passes) * n * pl.rec);
   return BOS_OK;
+}
+
+// ---- workspace held by the library, for callers that cannot allocate ------
+//
+// bos_sort_noalloc runs bos_sort with its workspace in this array.  Each GPU
+// the library runs on holds its own copy for the life of the process.  In
+// host code the array's name is only a host-side stand-in: its device address
+// is looked up once per device (with that device current) and only that
+// address is handed to kernels and copies.
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {nullptr};
+
+bos_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BOS_ERR_HIP;
+  if (dev < 0 || dev >= kScratchDevices) return BOS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BOS_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bos_status bos_sort(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* ws,
+                    size_t ws_bytes, void* stream, bos_report* rep) {
+  return sort_impl(in, out, n, rec, p, ws, ws_bytes, stream, rep);
+}
+
+bos_status bos_sort_noalloc(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* stream,
+                            bos_report* rep) {
+  if (!has_gpu()) return BOS_ERR_UNSUPPORTED;
+  void* ws = nullptr;
+  const bos_status st = scratch_of_current_device(&ws);
+  if (st != BOS_OK) return st;
+  // sort_impl rejects a plan whose workspace exceeds the array with
+  // BOS_ERR_WORKSPACE before it launches anything
+  return sort_impl(in, out, n, rec, p, ws, kScratchBytes, stream, rep);
 }
 
 size_t bos_batched_workspace_bytes(const uint64_t* n, uint32_t count, bos_rec rec, const bos_params* p) {
