@@ -60,6 +60,9 @@ typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
 #define BOS_SYNC 1u        /* synchronize and retry on overflow inside the call */
 #define BOS_GENERIC_ROUTING 2u /* test hook: route with the generic (non-specialised)
                                   kernel; same results, slower */
+#define BOS_EXACT_FINISH 4u    /* test hook: run bos_orp's per-bin finish through its
+                                  exact-comparator launch (otherwise taken only when two
+                                  random keys of a bin tie); same results, slower */
 
 typedef struct {
   uint64_t seed;              /* Philox key: labels and per-bin permutation keys */
@@ -301,7 +304,9 @@ typedef enum {
   BOS_K_BITONIC_GLOBAL = 8,
   BOS_K_BITONIC_TAIL = 9,
   BOS_K_OTHER = 10,
-  BOS_K_STRIP = 11        /* scan of the bin loads and strip after a split last pass */
+  BOS_K_STRIP = 11,       /* scan of the bin loads and strip after a split last pass */
+  BOS_K_ORP_FINISH = 12   /* bos_orp after a split last pass: scan of the bin loads, then
+                             each bin sorted, permuted by its random keys and stripped */
 } bos_kernel_kind;
 typedef struct {
   uint32_t kind;     /* bos_kernel_kind */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libbos.so")
 OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED, INTERNAL = range(8)
 SYNC = 1
 GENERIC_ROUTING = 2
+EXACT_FINISH = 4
 
 
 class BosError(RuntimeError):
@@ -68,7 +69,7 @@ class LaunchTime(C.Structure):
 
 KERNEL_KINDS = {1: "route_first", 2: "route_mid", 3: "route_last", 4: "route_single", 5: "sort_tile",
                 6: "sort_merge", 7: "bitonic_tile", 8: "bitonic_global", 9: "bitonic_tail", 10: "other",
-                11: "strip"}
+                11: "strip", 12: "orp_finish"}
 
 EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "bos_batched_workspace_bytes",
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
@@ -143,14 +144,15 @@ def _check(st):
         raise BosError(st, "libbos: " + lib().bos_status_string(st).decode())
 
 
-def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True, generic=False):
+def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True, generic=False,
+           exact_finish=False):
     p = Params()
     lib().bos_default_params(C.byref(p))
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.z, p.k, p.tile = z, k, tile
     p.max_retries = max_retries
     p.min_security_bits = min_security_bits
-    p.flags = (SYNC if sync else 0) | (GENERIC_ROUTING if generic else 0)
+    p.flags = (SYNC if sync else 0) | (GENERIC_ROUTING if generic else 0) | (EXACT_FINISH if exact_finish else 0)
     return p
 
 
@@ -213,9 +215,9 @@ def _run(fn, t, p, out, stream):
 
 
 def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stream=None, report=False,
-        generic=False):
+        generic=False, exact_finish=False):
     """Bucket ORP of the records in t (Section 3.2)."""
-    p = params(seed, z, k, 0, max_retries, min_security_bits, generic=generic)
+    p = params(seed, z, k, 0, max_retries, min_security_bits, generic=generic, exact_finish=exact_finish)
     o, rep = _run(lib().bos_orp, t, p, out, stream)
     return (o, rep) if report else o
 

@@ -43,6 +43,8 @@ hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, con
                                 const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks, uint32_t threads,
                                 uint32_t lds, hipStream_t s, bool split);
 hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, uint32_t blocks, hipStream_t s);
+hipError_t launch_block_scan(unsigned long long* bsum, unsigned long long* coff, uint32_t nblocks, hipStream_t s);
+hipError_t launch_orp_finish(int rec, uint32_t lz, const FinishArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs, uint32_t total,
                                hipStream_t s);
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
@@ -300,8 +302,9 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   off = align_up(off + comparison_sort_split_bytes(n, rec));
   pl->off_loads = off;   // split last pass: real count of every final bin
   off = align_up(off + size_t(B) * 4);
-  pl->off_coff = off;    // split last pass: offset of every chunk of kScanChunk block counts
-  off = align_up(off + (size_t(pl->nblocks_last) / kScanChunk + 1) * 8);
+  pl->off_coff = off;    // split last pass: offset of every chunk of kScanChunk block counts,
+                         // then bos_orp's key-tie flag
+  off = align_up(off + (size_t(pl->nblocks_last) / kScanChunk + 2) * 8);
   pl->total = off;
   return BOS_OK;
 }
@@ -415,7 +418,8 @@ StripSeg strip_seg(const Plan& pl, char* ws, void* out, uint32_t first) {
 // split: last pass in split form (requires split_last(pl); `out` must not be
 // slot array (P + 1) & 1, which holds the bins until the strip).
 hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t seed, uint32_t attempt,
-                           uint32_t fin, char* ws, hipStream_t s, int stop_after = -1, bool split = false) {
+                           uint32_t fin, char* ws, hipStream_t s, int stop_after = -1, bool split = false,
+                           uint32_t flags = 0) {
   unsigned long long* status = reinterpret_cast<unsigned long long*>(ws + pl.off_status);
   hipError_t e = launch_fill_u64(status, 2 + pl.nblocks_last, 0, s);
   if (e != hipSuccess) return e;
@@ -444,8 +448,10 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
     a.level0 = pl.lev0[t];
     a.klev = pl.klev[t];
     a.attempt = attempt;
-    a.fin = fin;
     const bool split_pass = split && last;
+    // the split last pass compacts every bin whatever the finish; the fused
+    // one permutes (fin 0) or sorts (fin 1) its bins itself
+    a.fin = split_pass ? 1u : fin;
     if (split_pass) a.loads = reinterpret_cast<uint32_t*>(ws + pl.off_loads);
     const uint64_t slot_bytes = pl.B * pl.Z * (uint64_t(pl.rec) + 4), rec_bytes = pl.n * pl.rec;
     const uint32_t kind = first && last ? BOS_K_ROUTE_SINGLE
@@ -461,10 +467,36 @@ hipError_t enqueue_routing(const Plan& pl, const void* in, void* out, uint64_t s
       e = launch_pass(pl.rec, a, first, last, nitems, s);
     prof_end(s);
     if (e != hipSuccess) return e;
-    if (split_pass) {
+    if (split_pass && fin != 0) {
       prof_begin(BOS_K_STRIP, 0, 2 * rec_bytes, s);
       e = launch_strip(pl.rec, a.rec_out, a.loads, a.scan, reinterpret_cast<unsigned long long*>(ws + pl.off_coff),
                        out, pl.n, nitems, pl.klev[t], pl.lz, pl.tile, s);
+      prof_end(s);
+      if (e != hipSuccess) return e;
+    } else if (split_pass) {
+      // bos_orp: scan of the block counts, then the per-bin permutation and
+      // strip (Section 3.2)
+      unsigned long long* coff = reinterpret_cast<unsigned long long*>(ws + pl.off_coff);
+      unsigned long long* tie = coff + nitems / kScanChunk + 1;
+      prof_begin(BOS_K_ORP_FINISH, 0, 2 * rec_bytes, s);
+      e = launch_fill_u64(tie, 1, (flags & BOS_EXACT_FINISH) ? 1ull : 0ull, s);
+      if (e == hipSuccess) e = launch_block_scan(a.scan, coff, nitems, s);
+      if (e == hipSuccess) {
+        FinishArgs f;
+        std::memset(&f, 0, sizeof(f));
+        f.binned = a.rec_out;
+        f.loads = a.loads;
+        f.boff = a.scan;
+        f.coff = coff;
+        f.out = out;
+        f.n = pl.n;
+        f.nbins = pl.B;
+        f.seed = seed;
+        f.klev = pl.klev[t];
+        f.attempt = attempt;
+        f.tie = tie;
+        e = launch_orp_finish(pl.rec, pl.lz, f, num_cus(), s);
+      }
       prof_end(s);
       if (e != hipSuccess) return e;
     }
@@ -494,7 +526,7 @@ bos_status run_routing(const Plan& pl, const bos_params& q, const void* in, void
   uint64_t last_ovf = prev_ovf;
   const uint32_t tries = (q.flags & BOS_SYNC) ? q.max_retries + 1 : 1;
   for (uint32_t att = first_attempt; att < tries; ++att) {
-    hipError_t e = enqueue_routing(pl, in, out, q.seed, att, fin, ws, s, -1, split);
+    hipError_t e = enqueue_routing(pl, in, out, q.seed, att, fin, ws, s, -1, split, q.flags);
     if (e != hipSuccess) return BOS_ERR_HIP;
     *attempts_out = att + 1;
     if (!(q.flags & BOS_SYNC)) {
@@ -934,7 +966,10 @@ bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos
   if (!ws || ws_bytes < pl.total) return BOS_ERR_WORKSPACE;
   uint32_t attempts = 0;
   uint64_t ovf = kNoOverflow;
-  st = run_routing(pl, q, in, out, 0, static_cast<char*>(ws), static_cast<hipStream_t>(stream), &attempts, &ovf);
+  // plans of two or more passes: split last pass, scan, then the per-bin
+  // finish kernel; single-pass plans keep the fused last pass
+  st = run_routing(pl, q, in, out, 0, static_cast<char*>(ws), static_cast<hipStream_t>(stream), &attempts, &ovf, 0,
+                   kNoOverflow, split_last(pl));
   fill_report(rep, pl, attempts, ovf, 0);
   return st;
 }

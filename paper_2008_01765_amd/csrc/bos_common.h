@@ -133,6 +133,21 @@ struct StripSeg {
   uint32_t pad;
 };
 
+// Per-bin finish of bos_orp after a split last pass.
+struct FinishArgs {
+  const void* binned;               // bin gb's reals in slots gb*Z .. gb*Z + loads[gb] - 1
+  const uint32_t* loads;            // real count per bin
+  const unsigned long long* boff;   // exclusive scan of the block counts within 1024-block chunks
+  const unsigned long long* coff;   // offset of every chunk of 1024 blocks
+  void* out;                        // n output records
+  uint64_t n;
+  uint64_t nbins;                   // B
+  uint64_t seed;
+  uint32_t klev;                    // levels of the last pass: a block holds 2^klev bins
+  uint32_t attempt;
+  unsigned long long* tie;          // raised when a bin's random keys tie (cleared before the finish)
+};
+
 // One instance's status words to initialise before its first routing pass.
 struct FillSeg {
   unsigned long long* p;  // status word, ticket, look-back words

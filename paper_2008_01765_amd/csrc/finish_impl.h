@@ -1,0 +1,340 @@
+// finish_impl.h — per-bin finish of the bucket ORP (Section 3.2) after the
+// split form of the last routing pass: each final bin's reals are put in a
+// uniformly random order and written, dummies stripped, to the bin's place in
+// the output.
+//
+// The split last pass leaves bin gb's reals compacted in slots gb*Z ..
+// gb*Z + loads[gb] - 1 of the binned array (in the order the network left
+// them) and every routing block's real count, which a two-level scan turns
+// into block offsets.  This kernel then, per bin:
+//   1. sorts the bin's Z slots in record order (key, payload), dummies last,
+//      so that the permutation below does not depend on the order in which
+//      the butterfly delivered the reals;
+//   2. gives the p-th real the 64-bit key r(gb*Z + p): word (g mod 4) of the
+//      Philox4x64-10 block g/4 under key (seed, 1) and counter (g/4, attempt);
+//   3. sorts the bin by (r, p), dummies last (a uniformly random order of
+//      the reals: random labels followed by a sort, the construction of
+//      Section 4.1).  The reals are in record order, so p increases with the
+//      record and (r, record) is the same order.  The network compares r
+//      alone; the keys depend on (seed, bin, p) only, and when two of a bin's
+//      reals (or its last real and first dummy) end up with equal keys, a
+//      flag that depends on no data sends the whole finish through a second
+//      launch with the (r, record) comparator;
+//   4. writes the reals to out[offset of the bin ..].
+// Both sorts are bitonic networks over all Z slots, so every address but the
+// final writes (which depend on the loads, revealed by the method) is a
+// function of (Z, bin) only.
+//
+// Layout: lane lq of the bin's Z/16 lanes holds slots 16 lq + e (e = 0..15) in
+// registers, each record as the 64-bit word(s) that order it (key in the high
+// half for 8-byte records).  Stages on slot bits 0..3 pair registers; stages on higher bits
+// pair lanes lq ^ X through DPP (X = 1, 2), ds_swizzle (X = 4, 8, 16) or a
+// lane permute (X = 32).  No LDS memory is used for Z <= 1024; Z = 2048
+// (two waves per bin) sorts through LDS with the routing kernel's padded bin
+// layout.
+#pragma once
+#include "route_impl.h"
+
+namespace bos {
+
+constexpr uint32_t kFinishThreads = 256;
+
+namespace finish_detail {
+
+template <uint32_t X>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (X == 1) return dpp<kDppXor1>(v);
+  else if constexpr (X == 2) return dpp<kDppXor2>(v);
+  else if constexpr (X < 32) return swz_xor<X>(v);
+  else return uint32_t(__shfl_xor(int(v), int(X), 64));
+}
+template <uint32_t X>
+__device__ __forceinline__ uint2 lane_xor(uint2 v) {
+  return make_uint2(lane_xor<X>(v.x), lane_xor<X>(v.y));
+}
+template <uint32_t X>
+__device__ __forceinline__ uint4 lane_xor(uint4 v) {
+  return make_uint4(lane_xor<X>(v.x), lane_xor<X>(v.y), lane_xor<X>(v.z), lane_xor<X>(v.w));
+}
+template <uint32_t X, typename T>
+__device__ __forceinline__ ElemR<T> e_xor(const ElemR<T>& a) {
+  return ElemR<T>{lane_xor<X>(a.r)};
+}
+template <uint32_t X, typename T>
+__device__ __forceinline__ ElemRK<T> e_xor(const ElemRK<T>& a) {
+  return ElemRK<T>{lane_xor<X>(a.r), lane_xor<X>(a.klo), lane_xor<X>(a.khi), lane_xor<X>(a.aux)};
+}
+
+// Comparators of the networks below: CMP 0 = e_less of the element type
+// (record order), 1 = the random key alone, 2 = (random key, record).
+template <int CMP, typename E>
+__device__ __forceinline__ bool lt(const E& a, const E& b) {
+  if constexpr (CMP == 0) return e_less(a, b);
+  else if constexpr (CMP == 1) return a.key < b.key;
+  else return (a.key < b.key) | ((a.key == b.key) & f_less(a.r, b.r));
+}
+
+// Compare-exchange of two registers (x gets the smaller when ascending) and
+// with the element of lane lq ^ X (the lower lane keeps the smaller when
+// ascending).  Elements equal under the comparator are byte-identical, or
+// (CMP 1) have equal keys, which the caller detects and re-sorts.
+template <int CMP, typename E>
+__device__ __forceinline__ void cx_r(E& x, E& y, bool asc) {
+  const bool sw = lt<CMP>(y, x) == asc;
+  const E nx = e_sel(sw, y, x), ny = e_sel(sw, x, y);
+  x = nx;
+  y = ny;
+}
+template <int CMP, uint32_t X, typename E>
+__device__ __forceinline__ void cx_xor(E& x, bool is_lo, bool asc) {
+  const E p = e_xor<X>(x);
+  const bool take = lt<CMP>(p, x) == (is_lo == asc);
+  x = e_sel(take, p, x);
+}
+
+// Phase KK (merges of 2^KK slots), stages JJ = KK-1 .. 0, on layout P held
+// entirely in registers and lane exchanges (LZ <= 10).
+template <int LZ, int KK, int JJ, int CMP, typename E>
+__device__ __forceinline__ void reg_stages(E (&v)[16], uint32_t lq) {
+  if constexpr (JJ >= 0) {
+    if constexpr (JJ < 4) {
+      constexpr uint32_t hb = 1u << JJ;
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        if (e & hb) continue;
+        bool asc;
+        if constexpr (KK == LZ) asc = true;
+        else if constexpr (KK < 4) asc = ((e >> KK) & 1u) == 0u;
+        else asc = ((lq >> (KK - 4)) & 1u) == 0u;
+        cx_r<CMP>(v[e], v[e | hb], asc);
+      }
+    } else {
+      constexpr uint32_t X = 1u << (JJ - 4);
+      const bool is_lo = (lq & X) == 0u;
+      bool asc;
+      if constexpr (KK == LZ) asc = true;
+      else asc = ((lq >> (KK - 4)) & 1u) == 0u;
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) cx_xor<CMP, X>(v[e], is_lo, asc);
+    }
+    reg_stages<LZ, KK, JJ - 1, CMP>(v, lq);
+  }
+}
+template <int LZ, int KK, int CMP, typename E>
+__device__ __forceinline__ void reg_phases(E (&v)[16], uint32_t lq) {
+  if constexpr (KK <= LZ) {
+    reg_stages<LZ, KK, KK - 1, CMP>(v, lq);
+    reg_phases<LZ, KK + 1, CMP>(v, lq);
+  }
+}
+
+}  // namespace finish_detail
+
+// Dynamic LDS bytes of the finish kernel (only Z = 2048 sorts through LDS).
+__host__ __device__ inline uint32_t finish_lds_bytes(int rec, uint32_t lz) {
+  if (lz < 11) return 0;
+  const uint32_t z = 1u << lz, zp = z + (z >> 4), bpw = kFinishThreads / (z >> 4);
+  return (bpw * zp * (uint32_t(rec) + 10u) + 15u) & ~15u;
+}
+
+namespace finish_detail {
+
+// A record as the words that order it: one 64-bit word (key << 32 | payload)
+// for 8-byte records, (key, payload) for 16-byte ones.
+template <int R> struct FRec;
+template <> struct FRec<8> {
+  uint64_t k;
+};
+template <> struct FRec<16> {
+  uint64_t k, p;
+};
+__device__ __forceinline__ bool f_less(const FRec<8>& a, const FRec<8>& b) { return a.k < b.k; }
+__device__ __forceinline__ bool f_less(const FRec<16>& a, const FRec<16>& b) {
+  return (a.k < b.k) | ((a.k == b.k) & (a.p < b.p));
+}
+__device__ __forceinline__ bool f_eq(const FRec<8>& a, const FRec<8>& b) { return a.k == b.k; }
+__device__ __forceinline__ bool f_eq(const FRec<16>& a, const FRec<16>& b) { return (a.k == b.k) & (a.p == b.p); }
+__device__ __forceinline__ FRec<8> f_sel(bool c, const FRec<8>& a, const FRec<8>& b) { return {c ? a.k : b.k}; }
+__device__ __forceinline__ FRec<16> f_sel(bool c, const FRec<16>& a, const FRec<16>& b) {
+  return {c ? a.k : b.k, c ? a.p : b.p};
+}
+template <uint32_t X>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v) {
+  return uint64_t(lane_xor<X>(uint32_t(v))) | (uint64_t(lane_xor<X>(uint32_t(v >> 32))) << 32);
+}
+template <uint32_t X>
+__device__ __forceinline__ FRec<8> f_xor(const FRec<8>& a) { return {lane_xor64<X>(a.k)}; }
+template <uint32_t X>
+__device__ __forceinline__ FRec<16> f_xor(const FRec<16>& a) { return {lane_xor64<X>(a.k), lane_xor64<X>(a.p)}; }
+__device__ __forceinline__ FRec<8> f_load(const uint2& r) { return {(uint64_t(r.x) << 32) | r.y}; }
+__device__ __forceinline__ FRec<16> f_load(const uint4& r) {
+  return {uint64_t(r.x) | (uint64_t(r.y) << 32), uint64_t(r.z) | (uint64_t(r.w) << 32)};
+}
+__device__ __forceinline__ uint2 f_store(const FRec<8>& f) { return make_uint2(uint32_t(f.k >> 32), uint32_t(f.k)); }
+__device__ __forceinline__ uint4 f_store(const FRec<16>& f) {
+  return make_uint4(uint32_t(f.k), uint32_t(f.k >> 32), uint32_t(f.p), uint32_t(f.p >> 32));
+}
+template <int R> __device__ __forceinline__ FRec<R> f_max();
+template <> __device__ __forceinline__ FRec<8> f_max<8>() { return {~0ull}; }
+template <> __device__ __forceinline__ FRec<16> f_max<16>() { return {~0ull, ~0ull}; }
+
+// Sort elements of the two per-bin sorts.
+template <int R>
+struct FE1 {  // record order
+  FRec<R> r;
+};
+template <int R>
+struct FE2 {  // random-key order: key r (then the record, for ties)
+  uint64_t key;
+  FRec<R> r;
+};
+template <int R>
+__device__ __forceinline__ bool e_less(const FE1<R>& a, const FE1<R>& b) { return f_less(a.r, b.r); }
+template <int R>
+__device__ __forceinline__ FE1<R> e_sel(bool c, const FE1<R>& a, const FE1<R>& b) { return {f_sel(c, a.r, b.r)}; }
+template <int R>
+__device__ __forceinline__ FE2<R> e_sel(bool c, const FE2<R>& a, const FE2<R>& b) {
+  return {c ? a.key : b.key, f_sel(c, a.r, b.r)};
+}
+template <uint32_t X, int R>
+__device__ __forceinline__ FE1<R> e_xor(const FE1<R>& a) { return {f_xor<X>(a.r)}; }
+template <uint32_t X, int R>
+__device__ __forceinline__ FE2<R> e_xor(const FE2<R>& a) { return {lane_xor64<X>(a.key), f_xor<X>(a.r)}; }
+
+// True when this lane holds two adjacent slots p, p+1 <= load (reals and the
+// first dummy) with equal keys; the pair across the lane boundary is checked
+// by the lower lane.
+template <int R, uint32_t HL>
+__device__ __forceinline__ bool key_tie(const FE2<R> (&w)[16], uint32_t lq, uint32_t load) {
+  bool tie = false;
+#pragma unroll
+  for (uint32_t e = 0; e + 1 < 16; ++e) {
+    const uint32_t p = 16u * lq + e;
+    tie |= (p < load) & (w[e].key == w[e + 1].key);
+  }
+  if constexpr (HL > 1) {
+    // first key of lane lq + 1 (within the bin)
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t src = (lane + 1u) & 63u;
+    const uint32_t lo = uint32_t(__shfl(int(uint32_t(w[0].key)), int(src), 64));
+    const uint32_t hi = uint32_t(__shfl(int(uint32_t(w[0].key >> 32)), int(src), 64));
+    const uint64_t nk = (uint64_t(hi) << 32) | lo;
+    const uint32_t p = 16u * lq + 15u;
+    tie |= (lq + 1u < HL) & (p < load) & (w[15].key == nk);
+  }
+  return tie;
+}
+
+}  // namespace finish_detail
+
+// EXACT = false: the key sort compares the random keys alone and raises
+// *a.tie when a bin holds two equal keys among its reals (and its first
+// dummy).  EXACT = true runs after it: it returns at once unless *a.tie is
+// set, and then redoes every bin with the (key, record) comparator.  The
+// flag depends on the keys only, never on the data.
+template <int R, int LZ, bool EXACT>
+__global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(R == 8 ? 3 : 2))) void orp_finish_kernel(FinishArgs a) {
+  using namespace finish_detail;
+  using T = typename RecOf<R>::T;
+  constexpr uint32_t Z = 1u << LZ, HL = Z >> 4, BPW = kFinishThreads / HL, ZP = Z + (Z >> 4);
+  static_assert(LZ >= 4 && LZ <= 11, "Z in [16, 2048]");
+  const uint32_t tid = threadIdx.x, S = tid / HL, lq = tid % HL;
+  const T* binned = static_cast<const T*>(a.binned);
+  T* out = static_cast<T*>(a.out);
+  extern __shared__ __align__(16) unsigned char smem[];
+  if constexpr (EXACT) {
+    if (__hip_atomic_load(a.tie, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0ull) return;
+  }
+  for (uint64_t g0 = uint64_t(blockIdx.x) * BPW; g0 < a.nbins; g0 += uint64_t(gridDim.x) * BPW) {
+    const uint64_t gb = g0 + S;
+    const bool act = gb < a.nbins;
+    uint32_t load = 0;
+    uint64_t off = 0;
+    if (act) {
+      // output offset: the routing block's offset plus the loads of the
+      // block's earlier bins
+      load = a.loads[gb];
+      const uint64_t blk = gb >> a.klev;
+      off = a.boff[blk] + a.coff[blk >> 10];
+      for (uint64_t j = blk << a.klev; j < gb; ++j) off += a.loads[j];
+    }
+    const uint64_t src = (gb << LZ) + 16u * lq;
+    if constexpr (LZ <= 10) {
+      // 1. record order, dummies (maximal record) last
+      FE1<R> v[16];
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        const uint32_t p = 16u * lq + e;
+        v[e] = FE1<R>{(act && p < load) ? f_load(binned[src + e]) : f_max<R>()};
+      }
+      reg_phases<LZ, 1, 0>(v, lq);
+      // 2. the per-bin keys of the reals (reals hold slots 0 .. load-1)
+      FE2<R> w[16];
+#pragma unroll
+      for (uint32_t e4 = 0; e4 < 4; ++e4) {
+        const uint32_t p0 = 16u * lq + 4u * e4;
+        const Philox4 ph = philox4x64_10(((gb << LZ) + p0) >> 2, a.attempt, a.seed, 1);
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          const uint32_t e = 4u * e4 + q;
+          w[e] = FE2<R>{p0 + q < load ? ph.v[q] : ~0ull, v[e].r};
+        }
+      }
+      // 3. order by the keys; ties (a wave-wide, data-independent branch)
+      //    are sorted again by (key, record)
+      if constexpr (EXACT) reg_phases<LZ, 1, 2>(w, lq);
+      else reg_phases<LZ, 1, 1>(w, lq);
+      // 4. the reals to their place in the output
+      if (act) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t p = 16u * lq + e;
+          if (p < load && off + p < a.n) out[off + p] = f_store(w[e].r);
+        }
+      }
+      if constexpr (!EXACT) {
+        if (act && key_tie<R, HL>(w, lq, load)) atomicOr(a.tie, 1ull);
+      }
+    } else if constexpr (!EXACT) {
+      // Z = 2048: two waves per bin, networks through LDS (padded bins), with
+      // the (key, rank) comparator
+      ElemR<T> v[16];
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        const uint32_t p = 16u * lq + e;
+        v[e] = ElemR<T>{(act && p < load) ? binned[src + e] : max_rec<T>()};
+      }
+      T* srec = reinterpret_cast<T*>(smem);
+      bin_bitonic<LZ>(v, LdsR<T>{srec}, S * ZP, lq, act);
+      ElemRK<T> w[16];
+#pragma unroll
+      for (uint32_t e4 = 0; e4 < 4; ++e4) {
+        const uint32_t p0 = 16u * lq + 4u * e4;
+        const Philox4 ph = philox4x64_10(((gb << LZ) + p0) >> 2, a.attempt, a.seed, 1);
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          const uint32_t e = 4u * e4 + q;
+          const bool real = p0 + q < load;
+          w[e] = ElemRK<T>{v[e].r, real ? uint32_t(ph.v[q]) : ~0u, real ? uint32_t(ph.v[q] >> 32) : ~0u,
+                           real ? p0 + q : 0xFFFFu};
+        }
+      }
+      lds_barrier();  // the record sort's last LDS reads are done
+      const uint32_t mp = BPW * ZP;
+      uint32_t* sklo = reinterpret_cast<uint32_t*>(smem + size_t(mp) * R);
+      uint32_t* skhi = sklo + mp;
+      uint16_t* saux = reinterpret_cast<uint16_t*>(skhi + mp);
+      bin_bitonic<LZ>(w, LdsRK<T>{srec, sklo, skhi, saux}, S * ZP, lq, act);
+      if (act) {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t p = 16u * lq + e;
+          if (p < load && off + p < a.n) out[off + p] = w[e].r;
+        }
+      }
+      lds_barrier();  // LDS of this group is no longer read
+    }
+  }
+}
+
+}  // namespace bos

@@ -1,6 +1,7 @@
 // route_launch.h — launch helpers of the register-resident routing kernel.
 #pragma once
 #include "route_impl.h"
+#include "finish_impl.h"
 
 namespace bos {
 
@@ -80,6 +81,41 @@ hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t
     case 22: return launch_route_t<R, LZ, 22>(a, nitems, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Per-bin finish of bos_orp (finish_impl.h): a persistent walk over groups of
+// bins, as many workgroups as fit on `grid` compute units at once; the fast
+// kernel, then the exact one (which returns at once unless a key tie was
+// flagged).  *a.tie must be zero on entry.
+template <int R, int LZ, bool EXACT>
+hipError_t launch_orp_finish_e(const FinishArgs& a, uint32_t grid, hipStream_t s) {
+  constexpr uint32_t HL = (1u << LZ) >> 4, BPW = kFinishThreads / HL;
+  const uint32_t lds = finish_lds_bytes(R, LZ);
+  static bool attr_set = false;
+  static uint32_t occ = 0;
+  const void* fn = reinterpret_cast<const void*>(&orp_finish_kernel<R, LZ, EXACT>);
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, int(kFinishThreads), lds) != hipSuccess || nb < 1)
+      nb = 1;
+    occ = uint32_t(nb);
+    attr_set = true;
+  }
+  const uint64_t groups = (a.nbins + BPW - 1) / BPW;
+  const uint64_t cap = uint64_t(grid) * occ;
+  const uint32_t g = uint32_t(groups < cap ? groups : cap);
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL((orp_finish_kernel<R, LZ, EXACT>), dim3(g), dim3(kFinishThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int R, int LZ>
+hipError_t launch_orp_finish_t(const FinishArgs& a, uint32_t grid, hipStream_t s) {
+  hipError_t e = launch_orp_finish_e<R, LZ, false>(a, grid, s);
+  if (e == hipSuccess && LZ <= 10) e = launch_orp_finish_e<R, LZ, true>(a, grid, s);
+  return e;
 }
 
 }  // namespace bos

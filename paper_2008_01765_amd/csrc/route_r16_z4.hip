@@ -5,4 +5,7 @@ namespace bos {
 hipError_t launch_route_r16_z4(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
   return launch_route_m<16, 4>(a, mode, nitems, grid, s);
 }
+hipError_t launch_orp_finish_r16_z4(const FinishArgs& a, uint32_t grid, hipStream_t s) {
+  return launch_orp_finish_t<16, 4>(a, grid, s);
+}
 }  // namespace bos

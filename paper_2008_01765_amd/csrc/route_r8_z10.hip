@@ -9,4 +9,7 @@ hipError_t launch_route_b_r8_z10(const PassArgs* segs, const uint32_t* blk_start
                                uint32_t threads, uint32_t lds, int mode, hipStream_t s) {
   return launch_route_bm<8, 10>(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
 }
+hipError_t launch_orp_finish_r8_z10(const FinishArgs& a, uint32_t grid, hipStream_t s) {
+  return launch_orp_finish_t<8, 10>(a, grid, s);
+}
 }  // namespace bos

@@ -9,4 +9,7 @@ hipError_t launch_route_b_r8_z8(const PassArgs* segs, const uint32_t* blk_start,
                                uint32_t threads, uint32_t lds, int mode, hipStream_t s) {
   return launch_route_bm<8, 8>(segs, blk_start, nsegs, blocks, threads, lds, mode, s);
 }
+hipError_t launch_orp_finish_r8_z8(const FinishArgs& a, uint32_t grid, hipStream_t s) {
+  return launch_orp_finish_t<8, 8>(a, grid, s);
+}
 }  // namespace bos

@@ -234,6 +234,18 @@ hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, u
   return hipGetLastError();
 }
 
+// The two-level scan of the block counts alone (bos_orp's finish reads the
+// offsets): bsum scanned in place within chunks of 1024, coff the chunk offsets.
+hipError_t launch_block_scan(unsigned long long* bsum, unsigned long long* coff, uint32_t nblocks, hipStream_t s) {
+  if (nblocks == 0 || !coff) return hipErrorInvalidValue;
+  const uint32_t nchunks = (nblocks + kScanThreads - 1) / kScanThreads;
+  hipLaunchKernelGGL(scan_chunks_kernel, dim3(nchunks), dim3(kScanThreads), 0, s, bsum, nblocks, coff);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanThreads), 0, s, coff, nchunks);
+  return hipGetLastError();
+}
+
 // tile: records per tile of the comparison sort's first phase (bins that
 // straddle a tile boundary are sorted); lz <= 11.  coff: device,
 // nblocks / 1024 + 1 words (the chunk offsets of the two-level scan).

@@ -90,6 +90,20 @@ def test_orp_bit_exact(ora, n, rec, z, k, generic):
         np.testing.assert_array_equal(bos.to_numpy(out), want["out"])
 
 
+@pytest.mark.parametrize("n,rec,z,k", [(1 << 16, 8, 512, 3), (1 << 17, 16, 256, 2), (100000, 8, 1024, 3),
+                                       (12345, 8, 64, 3), (1 << 14, 16, 32, 3), (1024, 8, 16, 4),
+                                       (1 << 16, 8, 128, 4)])
+def test_orp_exact_finish_launch(ora, n, rec, z, k):
+    # The per-bin finish's second launch (the (key, record) comparator, taken
+    # when two random keys of a bin tie) forced on: the same output.
+    a = _recs(n, rec)
+    want = ora.orp(a, 21, z=z, max_retries=40)
+    out, rep = bos.orp(_gpu(a), seed=21, z=z, k=k, max_retries=40, min_security_bits=0, report=True,
+                       exact_finish=True)
+    assert rep["attempts"] == want["report"]["attempts"]
+    np.testing.assert_array_equal(bos.to_numpy(out), want["out"])
+
+
 @pytest.mark.parametrize("n,rec,z,k", ORP_CASES)
 def test_sort_bit_exact(ora, n, rec, z, k):
     a = _recs(n, rec, key_bits=(12 if rec == 16 else None))
@@ -218,10 +232,10 @@ def test_duplicate_keys_workload_sort():
     np.testing.assert_array_equal(out2, out)
 
 
-def test_sort_uses_split_last_pass_orp_fused():
+def test_split_last_pass_then_strip_or_finish():
     # bos_sort of a multi-pass plan runs the split last pass (persistent last
-    # pass, then scan + strip); bos_orp keeps the fused last pass.  Both stay
-    # bit-exact against the oracle.
+    # pass, then scan + strip); bos_orp runs the same split last pass, then
+    # its per-bin finish.  Both stay bit-exact against the oracle.
     import oracle
     oracle.build(force=False)
     h = inputs.records(1 << 17, 8, 77)
@@ -234,7 +248,7 @@ def test_sort_uses_split_last_pass_orp_fused():
     kinds_orp = [l["kind"] for l in bos.profile_read()]
     bos.profile_enable(False)
     assert "strip" in kinds_sort and "route_last" in kinds_sort
-    assert "strip" not in kinds_orp and "route_last" in kinds_orp
+    assert "strip" not in kinds_orp and "route_last" in kinds_orp and "orp_finish" in kinds_orp
     np.testing.assert_array_equal(bos.to_numpy(out), cf.sorted_records(h))
     np.testing.assert_array_equal(bos.to_numpy(orp), oracle.orp(h, 5)["out"])
 
