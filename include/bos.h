@@ -66,9 +66,12 @@ typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
 
 typedef struct {
   uint64_t seed;              /* Philox key: labels and per-bin permutation keys */
-  uint32_t z;                 /* bucket capacity Z (Algorithm 3.1); power of two in
-                                 [8, 2048]; 0 = the tuning table's, else 512 (the
-                                 paper's choice) */
+  uint32_t z;                 /* bucket capacity Z (Algorithm 3.1): a power of two;
+                                 the kernels take Z in [8, 2048] (2, 4 and larger
+                                 powers: BOS_ERR_UNSUPPORTED; Z = 2 or 4 fails
+                                 Lemma 3.2's bound at every n > 1 anyway); 0 =
+                                 the tuning table's, else 512 (the paper's
+                                 choice) */
   uint32_t k;                 /* butterfly levels fused per pass; 0 = the tuning
                                  table's, else the planner's choice (3), either
                                  capped at what fits.  An explicit k whose block
@@ -83,10 +86,21 @@ typedef struct {
   uint32_t min_security_bits; /* reject Z when log2(B log2 B e^(-Z/6)) > -bits;
                                  0 disables the check (default 80) */
   uint32_t flags;             /* BOS_SYNC */
+  uint32_t attempt;           /* bos_orp / bos_sort: index of the first attempt
+                                 (Philox counter word of the labels, Algorithm
+                                 3.1's retry).  With BOS_SYNC the call runs
+                                 attempts attempt .. max(attempt, max_retries);
+                                 without, attempt alone.  Default 0.  An
+                                 asynchronous caller that finds the status word
+                                 (bos_status_offset) set re-issues the call with
+                                 attempt + 1 and gets what a BOS_SYNC call would
+                                 have produced.  Ignored by the batched and step
+                                 entry points (their jobs carry their own). */
 } bos_params;
 
 typedef struct {
-  uint32_t attempts;              /* attempts run (1 = no overflow) */
+  uint32_t attempts;              /* index of the last attempt run, plus one
+                                     (1 = the first attempt did not overflow) */
   uint32_t z, k, tile;            /* parameters used */
   uint32_t levels;                /* L = log2 B */
   uint32_t passes;                /* HBM passes of the routing phase */
@@ -111,6 +125,17 @@ void bos_default_params(bos_params* p);
 /* Device workspace (bytes) that bos_orp / bos_sort need for n records.
  * Returns 0 when the arguments are invalid. */
 size_t bos_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p);
+
+/* Byte offset, within the workspace of a bos_orp or bos_sort call with these
+ * arguments (n, rec, z, k and tile as resolved by the planner), of the call's
+ * overflow status word: 8 bytes, device memory, written in stream order by the
+ * attempt's routing passes.  Once the stream has passed an asynchronous call
+ * (no BOS_SYNC) it holds 0xFFFFFFFFFFFFFFFF if the attempt did not overflow,
+ * else (level << 32) | pair of the first overflowing MergeSplit (Algorithm
+ * 3.1's abort); the output is then unspecified and the caller re-issues the
+ * call with bos_params.attempt + 1.  Returns SIZE_MAX for invalid arguments or
+ * without a GPU. */
+size_t bos_status_offset(uint64_t n, bos_rec rec, const bos_params* p);
 
 /* Bucket ORP (Algorithm 3.1 followed by Section 3.2): out = in permuted by a
  * uniformly random permutation drawn from `seed`.  The output is a deterministic
@@ -151,7 +176,12 @@ size_t bos_batched_workspace_bytes(const uint64_t* n, uint32_t count, bos_rec re
  * pointers, n, seed).  d_status: device array of `count` uint32 receiving
  * BOS_OK or BOS_ERR_OVERFLOW per instance of the last attempt.  With BOS_SYNC
  * the call retries overflowing instances (one at a time) and returns the worst
- * status; rep (nullable) receives totals. */
+ * status; rep (nullable) receives totals.  Without BOS_SYNC the call enqueues
+ * the first attempt of every instance and returns without waiting for the
+ * device (the per-instance tables are uploaded from pinned host memory that
+ * the library keeps per batch shape); d_status then holds each instance's
+ * outcome once `stream` has passed the call, and an instance that overflowed
+ * is redone by a BOS_SYNC call (or bos_sort with attempt 1) on it alone. */
 bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec rec,
                             const bos_params* p, void* ws, size_t ws_bytes, void* stream,
                             uint32_t* d_status, bos_report* rep);

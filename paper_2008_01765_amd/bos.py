@@ -31,7 +31,8 @@ class BosError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("z", C.c_uint32), ("k", C.c_uint32), ("tile", C.c_uint32),
-                ("max_retries", C.c_uint32), ("min_security_bits", C.c_uint32), ("flags", C.c_uint32)]
+                ("max_retries", C.c_uint32), ("min_security_bits", C.c_uint32), ("flags", C.c_uint32),
+                ("attempt", C.c_uint32)]
 
 
 class Report(C.Structure):
@@ -75,7 +76,8 @@ EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "
            "bos_sort_batched", "bos_bitonic_workspace_bytes", "bos_bitonic_sort", "bos_release_cache",
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
            "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning",
-           "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async", "bos_sort_noalloc"]
+           "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async", "bos_sort_noalloc",
+           "bos_status_offset"]
 
 _lib = None
 
@@ -93,6 +95,8 @@ def lib():
         L.bos_default_params.restype = None
         L.bos_workspace_bytes.argtypes = [u64, C.c_int, P]
         L.bos_workspace_bytes.restype = C.c_size_t
+        L.bos_status_offset.argtypes = [u64, C.c_int, P]
+        L.bos_status_offset.restype = C.c_size_t
         for fn in (L.bos_orp, L.bos_sort):
             fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, R]
             fn.restype = C.c_int
@@ -145,9 +149,10 @@ def _check(st):
 
 
 def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True, generic=False,
-           exact_finish=False):
+           exact_finish=False, attempt=0):
     p = Params()
     lib().bos_default_params(C.byref(p))
+    p.attempt = attempt
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.z, p.k, p.tile = z, k, tile
     p.max_retries = max_retries
@@ -215,21 +220,41 @@ def _run(fn, t, p, out, stream):
 
 
 def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stream=None, report=False,
-        generic=False, exact_finish=False):
-    """Bucket ORP of the records in t (Section 3.2)."""
-    p = params(seed, z, k, 0, max_retries, min_security_bits, generic=generic, exact_finish=exact_finish)
+        generic=False, exact_finish=False, sync=True, attempt=0):
+    """Bucket ORP of the records in t (Section 3.2).  With sync=False the call
+    enqueues attempt `attempt` alone and leaves its overflow status on the
+    device (status_word)."""
+    p = params(seed, z, k, 0, max_retries, min_security_bits, sync=sync, generic=generic,
+               exact_finish=exact_finish, attempt=attempt)
     o, rep = _run(lib().bos_orp, t, p, out, stream)
     return (o, rep) if report else o
 
 
 def sort(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
-         report=False, generic=False, sync=True):
+         report=False, generic=False, sync=True, attempt=0):
     """Bucket oblivious sort of the records in t (Section 3.3).  With
-    sync=False the call does not wait for the overflow check (one attempt,
-    stream-ordered); the report then cannot tell an overflow."""
-    p = params(seed, z, k, tile, max_retries, min_security_bits, sync=sync, generic=generic)
+    sync=False the call does not wait for the overflow check (attempt
+    `attempt` alone, stream-ordered); status_word reads its outcome."""
+    p = params(seed, z, k, tile, max_retries, min_security_bits, sync=sync, generic=generic, attempt=attempt)
     o, rep = _run(lib().bos_sort, t, p, out, stream)
     return (o, rep) if report else o
+
+
+def status_word(t, z=0, k=0, tile=0, min_security_bits=80):
+    """The overflow status word (Algorithm 3.1's abort) that the last
+    bos_orp / bos_sort call on t's shape left in the cached workspace: None if
+    the attempt did not overflow, else (level, pair).  Synchronizes."""
+    rec = rec_bytes(t)
+    n = t.shape[0]
+    p = params(0, z, k, tile, 3, min_security_bits)
+    off = lib().bos_status_offset(n, rec, C.byref(p))
+    if off == 2 ** 64 - 1 or off == C.c_size_t(-1).value:
+        raise BosError(INVALID_ARG, "libbos: no status word for these arguments")
+    ws = workspace(workspace_bytes(n, rec, p), t.device)
+    w = int(ws[off:off + 8].cpu().view(torch.int64).item()) & 0xFFFFFFFFFFFFFFFF
+    if w == 0xFFFFFFFFFFFFFFFF:
+        return None
+    return (w >> 32, w & 0xFFFFFFFF)
 
 
 def sort_noalloc(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
@@ -248,8 +273,10 @@ def sort_noalloc(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=8
 
 
 def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, outs=None,
-                 stream=None, report=False):
-    """Bucket oblivious sort of every tensor in `tensors` (same record type)."""
+                 stream=None, report=False, sync=True, status=False):
+    """Bucket oblivious sort of every tensor in `tensors` (same record type).
+    With sync=False the call enqueues the first attempts and returns at once;
+    status=True also returns the per-instance device status array."""
     if not tensors:
         return []
     rec = rec_bytes(tensors[0])
@@ -258,7 +285,7 @@ def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_b
             raise ValueError("all instances must use the same record type")
     if outs is None:
         outs = [torch.empty_like(t) for t in tensors]
-    p = params(0, z, k, tile, max_retries, min_security_bits)
+    p = params(0, z, k, tile, max_retries, min_security_bits, sync=sync)
     cnt = len(tensors)
     arr = (Instance * cnt)()
     ns = (C.c_uint64 * cnt)()
@@ -275,7 +302,8 @@ def sort_batched(tensors, seeds, z=0, k=0, tile=0, max_retries=3, min_security_b
     st = lib().bos_sort_batched(arr, cnt, rec, C.byref(p), C.c_void_p(ws.data_ptr()), ws.numel(),
                                 _stream(stream), C.c_void_p(dstat.data_ptr()), C.byref(rep))
     _check(st)
-    return (outs, rep.as_dict()) if report else outs
+    res = (outs, rep.as_dict()) if report else outs
+    return (res, dstat) if status else res
 
 
 def sort_step(jobs, rec, p, step_ws, stream=None, count_left=True):

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -225,7 +226,10 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   std::memset(&te, 0, sizeof(te));
   const bool tuned = (q.z == 0 || q.k == 0 || q.tile == 0) && tuned_for(n, rec, &te);
   uint32_t Z = q.z ? q.z : (tuned && te.z ? te.z : 512u);
-  if (Z < 8 || Z > 2048 || (Z & (Z - 1))) return BOS_ERR_INVALID_ARG;
+  if (Z < 2 || (Z & (Z - 1))) return BOS_ERR_INVALID_ARG;
+  // the kernels hold 16 slots per lane and draw per-bin keys four at a
+  // time: Z in [8, 2048] (Z = 2 or 4 fails Lemma 3.2's bound at any n > 1)
+  if (Z < 8 || Z > 2048) return BOS_ERR_UNSUPPORTED;
   uint64_t B = 1;
   uint32_t L = levels_for(n, Z, &B);
   if (q.z == 0) {
@@ -524,8 +528,10 @@ bos_status run_routing(const Plan& pl, const bos_params& q, const void* in, void
                        hipStream_t s, uint32_t* attempts_out, uint64_t* ovf_out, uint32_t first_attempt = 0,
                        uint64_t prev_ovf = kNoOverflow, bool split = false) {
   uint64_t last_ovf = prev_ovf;
-  const uint32_t tries = (q.flags & BOS_SYNC) ? q.max_retries + 1 : 1;
-  for (uint32_t att = first_attempt; att < tries; ++att) {
+  // with BOS_SYNC: attempts first_attempt .. max_retries (at least one);
+  // without: first_attempt alone, its status left on the device
+  const uint32_t last = (q.flags & BOS_SYNC) ? std::max(q.max_retries, first_attempt) : first_attempt;
+  for (uint32_t att = first_attempt; att <= last; ++att) {
     hipError_t e = enqueue_routing(pl, in, out, q.seed, att, fin, ws, s, -1, split, q.flags);
     if (e != hipSuccess) return BOS_ERR_HIP;
     *attempts_out = att + 1;
@@ -833,10 +839,23 @@ hipError_t enqueue_batch(const Batch& b, char* tables, hipStream_t s, uint32_t* 
 
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
-  std::vector<char> host_tables;  // kept alive while the upload is in flight
+  char* pinned = nullptr;          // pinned host copy of the tables, uploaded before each replay
+  size_t pinned_cap = 0;
+  hipEvent_t uploaded = nullptr;   // recorded after the upload: the copy may be rewritten once it completes
+  bool upload_pending = false;
 };
 std::mutex g_graph_mu;
 std::map<std::string, GraphEntry> g_graphs;
+
+// Frees a cache entry once its last upload has completed.
+void release_entry(GraphEntry& ge) {
+  if (ge.upload_pending && ge.uploaded) (void)hipEventSynchronize(ge.uploaded);
+  ge.upload_pending = false;
+  if (ge.uploaded) (void)hipEventDestroy(ge.uploaded);
+  if (ge.pinned) (void)hipHostFree(ge.pinned);
+  if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+  ge = GraphEntry();
+}
 hipStream_t g_cap_stream = nullptr;
 hipEvent_t g_ev_in = nullptr, g_ev_out = nullptr;
 
@@ -880,12 +899,33 @@ bos_status run_batch(Batch& b, const bos_params& q, hipStream_t s, uint32_t* d_s
   }
   const std::string key = batch_key(b, q, tables, d_status);
   GraphEntry& ge = g_graphs[key];
-  ge.host_tables = b.tables;
   hipStream_t cs = g_cap_stream;
+  // The tables go to the device from a pinned host copy, so the call returns
+  // without waiting for the upload; the copy is rewritten only once the
+  // previous upload from it has completed.
+  if (!b.tables.empty()) {
+    if (ge.upload_pending && hipEventSynchronize(ge.uploaded) != hipSuccess) return BOS_ERR_HIP;
+    ge.upload_pending = false;
+    if (ge.pinned_cap < b.tables.size()) {
+      if (ge.pinned) (void)hipHostFree(ge.pinned);
+      ge.pinned = nullptr;
+      ge.pinned_cap = 0;
+      void* ph = nullptr;
+      if (hipHostMalloc(&ph, b.tables.size(), hipHostMallocDefault) != hipSuccess) return BOS_ERR_HIP;
+      ge.pinned = static_cast<char*>(ph);
+      ge.pinned_cap = b.tables.size();
+    }
+    if (!ge.uploaded && hipEventCreateWithFlags(&ge.uploaded, hipEventDisableTiming) != hipSuccess)
+      return BOS_ERR_HIP;
+    std::memcpy(ge.pinned, b.tables.data(), b.tables.size());
+  }
   if (hipEventRecord(g_ev_in, s) != hipSuccess || hipStreamWaitEvent(cs, g_ev_in, 0) != hipSuccess) return BOS_ERR_HIP;
-  if (!ge.host_tables.empty() &&
-      hipMemcpyAsync(tables, ge.host_tables.data(), ge.host_tables.size(), hipMemcpyHostToDevice, cs) != hipSuccess)
-    return BOS_ERR_HIP;
+  if (!b.tables.empty()) {
+    if (hipMemcpyAsync(tables, ge.pinned, b.tables.size(), hipMemcpyHostToDevice, cs) != hipSuccess ||
+        hipEventRecord(ge.uploaded, cs) != hipSuccess)
+      return BOS_ERR_HIP;
+    ge.upload_pending = true;
+  }
   if (!ge.exec) {
     const bool prof = g_prof_on;
     g_prof_on = false;  // no event records inside the captured graph
@@ -900,6 +940,7 @@ bos_status run_batch(Batch& b, const bos_params& q, hipStream_t s, uint32_t* d_s
     if (e == hipSuccess) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
+      release_entry(ge);
       g_graphs.erase(key);
       return BOS_ERR_HIP;
     }
@@ -910,8 +951,6 @@ bos_status run_batch(Batch& b, const bos_params& q, hipStream_t s, uint32_t* d_s
   if (e != hipSuccess) return BOS_ERR_HIP;
   if (hipEventRecord(g_ev_out, cs) != hipSuccess || hipStreamWaitEvent(s, g_ev_out, 0) != hipSuccess)
     return BOS_ERR_HIP;
-  // the host copy of the tables must outlive the upload
-  if (hipStreamSynchronize(cs) != hipSuccess) return BOS_ERR_HIP;
   return BOS_OK;
 }
 
@@ -933,6 +972,15 @@ size_t bos_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p) {
   q.min_security_bits = 0;  // the size does not depend on the security floor
   if (make_plan(n, int(rec), q, true, &pl) != BOS_OK) return 0;
   return pl.total;
+}
+
+size_t bos_status_offset(uint64_t n, bos_rec rec, const bos_params* p) {
+  if (!has_gpu()) return SIZE_MAX;
+  Plan pl;
+  bos_params q = resolve(p);
+  q.min_security_bits = 0;  // the layout does not depend on the security floor
+  if (make_plan(n, int(rec), q, true, &pl) != BOS_OK) return SIZE_MAX;
+  return pl.off_status;
 }
 
 bos_status bos_plan(uint64_t n, bos_rec rec, const bos_params* p, uint64_t* buckets, uint32_t* levels,
@@ -968,8 +1016,8 @@ bos_status bos_orp(const void* in, void* out, uint64_t n, bos_rec rec, const bos
   uint64_t ovf = kNoOverflow;
   // plans of two or more passes: split last pass, scan, then the per-bin
   // finish kernel; single-pass plans keep the fused last pass
-  st = run_routing(pl, q, in, out, 0, static_cast<char*>(ws), static_cast<hipStream_t>(stream), &attempts, &ovf, 0,
-                   kNoOverflow, split_last(pl));
+  st = run_routing(pl, q, in, out, 0, static_cast<char*>(ws), static_cast<hipStream_t>(stream), &attempts, &ovf,
+                   q.attempt, kNoOverflow, split_last(pl));
   fill_report(rep, pl, attempts, ovf, 0);
   return st;
 }
@@ -1007,7 +1055,7 @@ bos_status sort_impl(const void* in, void* out, uint64_t n, bos_rec rec, const b
   void* other = (passes % 2 == 0) ? tmp : out;
   uint32_t attempts = 0;
   uint64_t ovf = kNoOverflow;
-  st = run_routing(pl, q, in, start, 1, w, s, &attempts, &ovf, 0, kNoOverflow, split);
+  st = run_routing(pl, q, in, start, 1, w, s, &attempts, &ovf, q.attempt, kNoOverflow, split);
   if (st != BOS_OK) {
     fill_report(rep, pl, attempts, ovf, 0);
     return st;
@@ -1656,8 +1704,7 @@ uint32_t bos_get_tuning(bos_tune_entry* out, uint32_t cap) {
 
 void bos_release_cache(void) {
   std::lock_guard<std::mutex> lock(g_graph_mu);
-  for (auto& kv : g_graphs)
-    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  for (auto& kv : g_graphs) release_entry(kv.second);
   g_graphs.clear();
 }
 
