@@ -78,6 +78,8 @@ class Future:
         self.phase = 0
         self._ws = None
         self._step0 = 0
+        self._ready = None   # event on the submitter's stream after which the input is valid
+        self._done = None    # event on the server's stream after the request's last step
 
     def done(self):
         return self.finished is not None
@@ -92,6 +94,13 @@ class Future:
             server.step()
         if self.status != bos.OK:
             raise bos.BosError(self.status, "libbos: " + bos.lib().bos_status_string(self.status).decode())
+        if self._done is not None:
+            # the caller's stream reads the output after the server's stream
+            # has written it; the output's memory is then released in the
+            # caller's stream order as well
+            cur = torch.cuda.current_stream(self.out.device)
+            cur.wait_event(self._done)
+            self.out.record_stream(cur)
         return self.out
 
     @property
@@ -109,6 +118,12 @@ class Server:
     (bos_sort_step_async): the device runs one step while the host plans the
     next, and a request is reported finished one call after its last step
     was enqueued, as soon as that step has completed.
+
+    stream: the stream the steps run on (None: the current stream at each
+    call).  With a stream of its own the server allocates outputs and
+    workspaces on that stream (so freed blocks are reused in its order), has
+    it wait for the submitter's stream before a request's first step, and
+    makes the caller's stream wait for the request's last step in result().
     """
 
     def __init__(self, hbm_budget_bytes=64 << 30, z=0, k=0, max_retries=3, min_security_bits=80,
@@ -146,6 +161,12 @@ class Server:
         rid = self._next_id
         self._next_id += 1
         f = Future(self, rid, tensor, rid if seed is None else seed, self.clock() if arrival is None else arrival)
+        if self.stream is not None:
+            cur = torch.cuda.current_stream(self.device)
+            if cur != self.stream:
+                f._ready = torch.cuda.Event()
+                f._ready.record(cur)
+                tensor.record_stream(self.stream)  # not reused before the server's stream is done with it
         if f.n:
             bos.plan(f.n, rec, self.params.z, self.params.k, 0, self.params.min_security_bits)  # raises if Z is rejected
         f.footprint = self.footprint(f.n, rec)
@@ -155,6 +176,13 @@ class Server:
         self.queue.append(f)
         return f
 
+    def _on_stream(self):
+        """Context that makes the server's stream current (allocations then
+        belong to it)."""
+        if self.stream is None:
+            return _NoStream()
+        return torch.cuda.stream(self.stream)
+
     def _admit(self):
         # lazily: admission stops at the first request that does not fit
         k = admit_prefix((f.footprint for f in self.queue), self.budget - self.used)
@@ -162,16 +190,19 @@ class Server:
             return 0
         now = self.clock()
         new = []
-        for _ in range(k):
-            f = self.queue.popleft()
-            f.admitted = now
-            f._step0 = self.steps
-            f.out = torch.empty_like(f.input)
-            if f.n:
-                f._ws = torch.empty(max(bos.workspace_bytes(f.n, self.rec, self.params), 256), dtype=torch.uint8,
-                                    device=self.device)
-            self.used += f.footprint
-            new.append(f)
+        with self._on_stream():
+            for _ in range(k):
+                f = self.queue.popleft()
+                f.admitted = now
+                f._step0 = self.steps
+                if f._ready is not None:
+                    self.stream.wait_event(f._ready)
+                f.out = torch.empty_like(f.input)
+                if f.n:
+                    f._ws = torch.empty(max(bos.workspace_bytes(f.n, self.rec, self.params), 256),
+                                        dtype=torch.uint8, device=self.device)
+                self.used += f.footprint
+                new.append(f)
         # job array: the resident jobs' entries (phase and attempt as the
         # last step left them) followed by the new ones
         old = len(self.active)
@@ -208,9 +239,11 @@ class Server:
         jobs = self._jobs  # the step updates phase, attempt and status in place
         need = bos.step_workspace_bytes(cnt) * (2 if self._stepper else 1)
         if self._step_ws is None or self._step_ws.numel() < need:
-            # a replaced buffer is released in stream order, after the step
-            # in flight that may still read it
-            self._step_ws = torch.empty(2 * need, dtype=torch.uint8, device=self.device)
+            # a replaced buffer is released in the order of the stream it was
+            # allocated on (the server's), after the step in flight that may
+            # still read it
+            with self._on_stream():
+                self._step_ws = torch.empty(2 * need, dtype=torch.uint8, device=self.device)
         if self._stepper:
             self._stepper.step(jobs, self.rec, self.params, self._step_ws, self.stream)
         else:
@@ -222,8 +255,13 @@ class Server:
         if not fin.any():
             return []
         done = []
+        ev = None
+        if self.stream is not None:
+            ev = torch.cuda.Event()
+            ev.record(self.stream)  # after every step enqueued so far
         for i in np.flatnonzero(fin).tolist():
             f = self.active[i]
+            f._done = ev
             f.phase = bos.PHASE_DONE
             f.attempts = int(view["attempt"][i])
             f.status = int(view["status"][i])
@@ -244,6 +282,14 @@ class Server:
     def run_until_idle(self):
         while not self.idle():
             self.step()
+
+
+class _NoStream:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *exc):
+        return False
 
 
 def run_trace(server, tensors, arrivals, seeds=None, spin=True):

@@ -48,6 +48,32 @@ def test_mix_equals_alone(rec, z, pipeline):
     assert srv.used == 0
 
 
+@pytest.mark.parametrize("pipeline", [True, False])
+def test_side_stream_server(pipeline):
+    # The server runs on a stream of its own: inputs produced on the caller's
+    # stream just before submission, outputs read on the caller's stream
+    # right after result(), buffers of finished requests released while
+    # later ones still run.  Every result equals the sort alone.
+    side = torch.cuda.Stream()
+    sizes = [1 << 16, 4096, 70000, 1 << 18, 333, 9999, 1 << 12, 5000] * 2
+    hosts = _hosts(sizes, 16, 1300)
+    srv = serving.Server(hbm_budget_bytes=1 << 34, z=512, min_security_bits=0, pipeline=pipeline, stream=side)
+    futs, srcs = [], []
+    for i, h in enumerate(hosts):
+        staged = bos.from_numpy(h)
+        t = staged.clone()  # written on the caller's stream, read on the server's
+        srcs.append(t)
+        futs.append(srv.submit(t, seed=70 + i))
+        if i % 4 == 3:
+            srv.step()
+    outs = [f.result() for f in futs]
+    srv.run_until_idle()
+    for h, o in zip(hosts, outs):
+        chk = o.clone()  # read on the caller's stream after result()
+        np.testing.assert_array_equal(bos.to_numpy(chk), cf.sorted_records(h))
+    assert srv.used == 0
+
+
 def test_budget_bounds_resident_footprint():
     sizes = [1 << 16] * 6 + [1 << 14] * 4
     hosts = _hosts(sizes, 16, 900)
