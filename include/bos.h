@@ -348,6 +348,17 @@ typedef struct {
 void bos_profile_enable(int on);
 uint32_t bos_profile_read(bos_launch_time* out, uint32_t cap);
 
+/* Address digests (the test build libbos_trace.so, compiled with
+ * BOS_TRACE_DIGEST): bind two device buffers of `slots` uint64 words (a power
+ * of two; the caller zeroes them).  From then on every HBM and LDS access of
+ * the routing passes, the per-bin finish and the strip folds (array, index)
+ * into route_buf[g], and every access of the comparison sort into
+ * sort_buf[g], g = the accessing thread's global index in its launch modulo
+ * `slots`, in program order; equal buffers after two runs mean equal access
+ * sequences (Definition 2.1).  The plain library returns BOS_ERR_UNSUPPORTED.
+ * Null buffers switch the folding off. */
+bos_status bos_trace_bind(void* route_buf, void* sort_buf, uint64_t slots);
+
 /* Number of passes and levels per pass the planner picks (passes_out[0] =
  * P, passes_out[1 + t] = levels of pass t, up to 32 passes). */
 bos_status bos_plan(uint64_t n, bos_rec rec, const bos_params* p, uint64_t* buckets,

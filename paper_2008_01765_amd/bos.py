@@ -9,6 +9,7 @@ Record tensors have shape (n, 2) on a CUDA device: int32 columns for 8-byte
 records {u32 key, u32 payload}, int64 columns for 16-byte records
 {u64 key, u64 payload}; the bits are taken as unsigned.
 """
+import contextlib
 import ctypes as C
 import os
 
@@ -16,6 +17,8 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbos.so")
+# the same library built with BOS_TRACE_DIGEST (address digests; tests only)
+TRACE_LIB_PATH = os.path.join(HERE, "libbos_trace.so")
 
 OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED, INTERNAL = range(8)
 SYNC = 1
@@ -77,70 +80,93 @@ EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
            "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning",
            "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async", "bos_sort_noalloc",
-           "bos_status_offset"]
+           "bos_status_offset", "bos_trace_bind"]
 
 _lib = None
+_loaded = {}
 
 
 def lib():
     """Load libbos.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libbos.so is not built; run python -m paper_2008_01765_amd.build")
-        L = C.CDLL(LIB_PATH)
-        P, R = C.POINTER(Params), C.POINTER(Report)
-        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
-        L.bos_default_params.argtypes = [P]
-        L.bos_default_params.restype = None
-        L.bos_workspace_bytes.argtypes = [u64, C.c_int, P]
-        L.bos_workspace_bytes.restype = C.c_size_t
-        L.bos_status_offset.argtypes = [u64, C.c_int, P]
-        L.bos_status_offset.restype = C.c_size_t
-        for fn in (L.bos_orp, L.bos_sort):
-            fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, R]
-            fn.restype = C.c_int
-        L.bos_sort_noalloc.argtypes = [vp, vp, u64, C.c_int, P, vp, R]
-        L.bos_sort_noalloc.restype = C.c_int
-        L.bos_batched_workspace_bytes.argtypes = [C.POINTER(u64), u32, C.c_int, P]
-        L.bos_batched_workspace_bytes.restype = C.c_size_t
-        L.bos_sort_batched.argtypes = [C.POINTER(Instance), u32, C.c_int, P, vp, C.c_size_t, vp, vp, R]
-        L.bos_sort_batched.restype = C.c_int
-        L.bos_step_workspace_bytes.argtypes = [u32]
-        L.bos_step_workspace_bytes.restype = C.c_size_t
-        L.bos_sort_step.argtypes = [C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
-        L.bos_sort_step.restype = C.c_int
-        L.bos_stepper_create.argtypes = []
-        L.bos_stepper_create.restype = vp
-        L.bos_stepper_destroy.argtypes = [vp]
-        L.bos_stepper_destroy.restype = None
-        L.bos_sort_step_async.argtypes = [vp, C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
-        L.bos_sort_step_async.restype = C.c_int
-        L.bos_set_tuning.argtypes = [C.POINTER(TuneEntry), u32]
-        L.bos_set_tuning.restype = C.c_int
-        L.bos_get_tuning.argtypes = [C.POINTER(TuneEntry), u32]
-        L.bos_get_tuning.restype = u32
-        L.bos_bitonic_workspace_bytes.argtypes = [u64, C.c_int]
-        L.bos_bitonic_workspace_bytes.restype = C.c_size_t
-        L.bos_bitonic_sort.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
-        L.bos_bitonic_sort.restype = C.c_int
-        L.bos_release_cache.argtypes = []
-        L.bos_release_cache.restype = None
-        L.bos_status_string.argtypes = [C.c_int]
-        L.bos_status_string.restype = C.c_char_p
-        L.bos_debug_levels.argtypes = [vp, u64, C.c_int, P, u32, vp, C.c_size_t, vp, vp, vp, vp,
-                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
-        L.bos_debug_levels.restype = C.c_int
-        L.bos_debug_labels.argtypes = [u64, u32, u64, u32, vp, vp]
-        L.bos_debug_labels.restype = C.c_int
-        L.bos_plan.argtypes = [u64, C.c_int, P, C.POINTER(u64), C.POINTER(u32), C.POINTER(u32)]
-        L.bos_plan.restype = C.c_int
-        L.bos_profile_enable.argtypes = [C.c_int]
-        L.bos_profile_enable.restype = None
-        L.bos_profile_read.argtypes = [C.POINTER(LaunchTime), u32]
-        L.bos_profile_read.restype = u32
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path):
+    """Run the calls of this module through another build of the library
+    (e.g. TRACE_LIB_PATH) inside the block."""
+    global _lib
+    prev = _lib
+    _lib = _load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = prev
+
+
+def _load(path):
+    if path in _loaded:
+        return _loaded[path]
+    if not os.path.exists(path):
+        raise RuntimeError("%s is not built; run python -m paper_2008_01765_amd.build" % os.path.basename(path))
+    L = C.CDLL(path)
+    P, R = C.POINTER(Params), C.POINTER(Report)
+    vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+    L.bos_default_params.argtypes = [P]
+    L.bos_default_params.restype = None
+    L.bos_workspace_bytes.argtypes = [u64, C.c_int, P]
+    L.bos_workspace_bytes.restype = C.c_size_t
+    L.bos_status_offset.argtypes = [u64, C.c_int, P]
+    L.bos_status_offset.restype = C.c_size_t
+    L.bos_trace_bind.argtypes = [vp, vp, u64]
+    L.bos_trace_bind.restype = C.c_int
+    for fn in (L.bos_orp, L.bos_sort):
+        fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, R]
+        fn.restype = C.c_int
+    L.bos_sort_noalloc.argtypes = [vp, vp, u64, C.c_int, P, vp, R]
+    L.bos_sort_noalloc.restype = C.c_int
+    L.bos_batched_workspace_bytes.argtypes = [C.POINTER(u64), u32, C.c_int, P]
+    L.bos_batched_workspace_bytes.restype = C.c_size_t
+    L.bos_sort_batched.argtypes = [C.POINTER(Instance), u32, C.c_int, P, vp, C.c_size_t, vp, vp, R]
+    L.bos_sort_batched.restype = C.c_int
+    L.bos_step_workspace_bytes.argtypes = [u32]
+    L.bos_step_workspace_bytes.restype = C.c_size_t
+    L.bos_sort_step.argtypes = [C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
+    L.bos_sort_step.restype = C.c_int
+    L.bos_stepper_create.argtypes = []
+    L.bos_stepper_create.restype = vp
+    L.bos_stepper_destroy.argtypes = [vp]
+    L.bos_stepper_destroy.restype = None
+    L.bos_sort_step_async.argtypes = [vp, C.POINTER(Job), u32, C.c_int, P, vp, C.c_size_t, vp]
+    L.bos_sort_step_async.restype = C.c_int
+    L.bos_set_tuning.argtypes = [C.POINTER(TuneEntry), u32]
+    L.bos_set_tuning.restype = C.c_int
+    L.bos_get_tuning.argtypes = [C.POINTER(TuneEntry), u32]
+    L.bos_get_tuning.restype = u32
+    L.bos_bitonic_workspace_bytes.argtypes = [u64, C.c_int]
+    L.bos_bitonic_workspace_bytes.restype = C.c_size_t
+    L.bos_bitonic_sort.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
+    L.bos_bitonic_sort.restype = C.c_int
+    L.bos_release_cache.argtypes = []
+    L.bos_release_cache.restype = None
+    L.bos_status_string.argtypes = [C.c_int]
+    L.bos_status_string.restype = C.c_char_p
+    L.bos_debug_levels.argtypes = [vp, u64, C.c_int, P, u32, vp, C.c_size_t, vp, vp, vp, vp,
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+    L.bos_debug_levels.restype = C.c_int
+    L.bos_debug_labels.argtypes = [u64, u32, u64, u32, vp, vp]
+    L.bos_debug_labels.restype = C.c_int
+    L.bos_plan.argtypes = [u64, C.c_int, P, C.POINTER(u64), C.POINTER(u32), C.POINTER(u32)]
+    L.bos_plan.restype = C.c_int
+    L.bos_profile_enable.argtypes = [C.c_int]
+    L.bos_profile_enable.restype = None
+    L.bos_profile_read.argtypes = [C.POINTER(LaunchTime), u32]
+    L.bos_profile_read.restype = u32
+    _loaded[path] = L
+    return L
 
 
 def _check(st):

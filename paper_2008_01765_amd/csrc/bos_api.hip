@@ -82,6 +82,8 @@ hipEvent_t prof_event() {
 }  // namespace
 
 namespace bos {
+TraceHost g_trace = {{nullptr, nullptr}, 0, 0};
+
 void prof_begin(uint32_t kind, uint32_t index, uint64_t bytes, hipStream_t s) {
   if (!g_prof_on) return;
   g_prof_open.kind = kind;
@@ -972,6 +974,22 @@ size_t bos_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p) {
   q.min_security_bits = 0;  // the size does not depend on the security floor
   if (make_plan(n, int(rec), q, true, &pl) != BOS_OK) return 0;
   return pl.total;
+}
+
+bos_status bos_trace_bind(void* route_buf, void* sort_buf, uint64_t slots) {
+#ifdef BOS_TRACE_DIGEST
+  if (slots && (slots & (slots - 1))) return BOS_ERR_INVALID_ARG;
+  g_trace.buf[0] = route_buf;
+  g_trace.buf[1] = sort_buf;
+  g_trace.slots = slots;
+  ++g_trace.gen;
+  return BOS_OK;
+#else
+  (void)route_buf;
+  (void)sort_buf;
+  (void)slots;
+  return BOS_ERR_UNSUPPORTED;
+#endif
 }
 
 size_t bos_status_offset(uint64_t n, bos_rec rec, const bos_params* p) {

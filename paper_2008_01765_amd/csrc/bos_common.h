@@ -155,6 +155,65 @@ struct FillSeg {
   uint32_t pad;
 };
 
+// ---- address digests (test build) ------------------------------------------
+//
+// Built with BOS_TRACE_DIGEST, every HBM and LDS access of the routing, the
+// per-bin finish, the strip (trace buffer 0) and the comparison sort (trace
+// buffer 1) folds (array class, index) into a 64-bit slot of its thread, in
+// program order: slot[g] = mix(slot[g], class, index), g = the thread's
+// global index in its launch (modulo the buffer's slot count).  Two runs
+// leave equal buffers when every thread of every launch touched the same
+// arrays at the same indices in the same order, which is what a data-
+// independent access pattern means (Definition 2.1) at the granularity of
+// array elements.  The normal build compiles every hook to nothing.
+//
+// Device code reads the buffers through a file-scope pointer pair of its own
+// translation unit, which the host sets (trace_bind) before each launch when
+// bos_trace_bind has changed them.
+struct TraceHost {
+  void* buf[2];
+  uint64_t slots;
+  uint64_t gen;
+};
+extern TraceHost g_trace;  // host side, defined in bos_api.hip
+
+#ifdef BOS_TRACE_DIGEST
+static __device__ unsigned long long* bos_trace_buf[2];
+static __device__ uint64_t bos_trace_mask;
+[[maybe_unused]] static uint64_t g_trace_bound = 0;  // host: the generation this translation unit was bound to
+
+__device__ __forceinline__ void trace_idx(uint32_t which, uint32_t cls, uint64_t idx) {
+  unsigned long long* b = bos_trace_buf[which];
+  if (!b) return;
+  const uint64_t g = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) & bos_trace_mask;
+  uint64_t h = b[g];
+  h ^= idx + (uint64_t(cls) << 56) + 0x9E3779B97F4A7C15ull;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 31;
+  h *= 0x94D049BB133111EBull;
+  h ^= h >> 29;
+  b[g] = h;
+}
+
+[[maybe_unused]] static inline hipError_t trace_bind() {
+  if (g_trace_bound == g_trace.gen) return hipSuccess;
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(bos_trace_buf), g_trace.buf, sizeof(g_trace.buf));
+  const uint64_t mask = g_trace.slots ? g_trace.slots - 1 : 0;
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(bos_trace_mask), &mask, sizeof(mask));
+  if (e == hipSuccess) g_trace_bound = g_trace.gen;
+  return e;
+}
+#define BOS_TR(which, cls, idx) ::bos::trace_idx((which), (cls), uint64_t(idx))
+#define BOS_TRACE_BIND()                             \
+  do {                                               \
+    const hipError_t te_ = ::bos::trace_bind();      \
+    if (te_ != hipSuccess) return te_;               \
+  } while (0)
+#else
+#define BOS_TR(which, cls, idx) ((void)0)
+#define BOS_TRACE_BIND() ((void)0)
+#endif
+
 // Dynamic LDS bytes of a routing block (must match the carve in the kernel).
 __host__ __device__ inline uint32_t pass_lds_bytes(int rec, uint32_t z, uint32_t klev, bool last_shuffle) {
   const uint32_t m = z << klev;

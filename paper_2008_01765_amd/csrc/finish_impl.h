@@ -253,10 +253,16 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
     if (act) {
       // output offset: the routing block's offset plus the loads of the
       // block's earlier bins
+      BOS_TR(0, 22, gb);
       load = a.loads[gb];
       const uint64_t blk = gb >> a.klev;
+      BOS_TR(0, 23, blk);
+      BOS_TR(0, 23, blk >> 10);
       off = a.boff[blk] + a.coff[blk >> 10];
-      for (uint64_t j = blk << a.klev; j < gb; ++j) off += a.loads[j];
+      for (uint64_t j = blk << a.klev; j < gb; ++j) {
+        BOS_TR(0, 22, j);
+        off += a.loads[j];
+      }
     }
     const uint64_t src = (gb << LZ) + 16u * lq;
     if constexpr (LZ <= 10) {
@@ -265,6 +271,7 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
         const uint32_t p = 16u * lq + e;
+        if (act && p < load) BOS_TR(0, 20, src + e);
         v[e] = FE1<R>{(act && p < load) ? f_load(binned[src + e]) : f_max<R>()};
       }
       reg_phases<LZ, 1, 0>(v, lq);
@@ -289,11 +296,17 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (uint32_t e = 0; e < 16; ++e) {
           const uint32_t p = 16u * lq + e;
-          if (p < load && off + p < a.n) out[off + p] = f_store(w[e].r);
+          if (p < load && off + p < a.n) {
+            BOS_TR(0, 21, off + p);
+            out[off + p] = f_store(w[e].r);
+          }
         }
       }
       if constexpr (!EXACT) {
-        if (act && key_tie<R, HL>(w, lq, load)) atomicOr(a.tie, 1ull);
+        if (act && key_tie<R, HL>(w, lq, load)) {
+          BOS_TR(0, 24, 0);
+          atomicOr(a.tie, 1ull);
+        }
       }
     } else if constexpr (!EXACT) {
       // Z = 2048: two waves per bin, networks through LDS (padded bins), with
@@ -302,6 +315,7 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
         const uint32_t p = 16u * lq + e;
+        if (act && p < load) BOS_TR(0, 20, src + e);
         v[e] = ElemR<T>{(act && p < load) ? binned[src + e] : max_rec<T>()};
       }
       T* srec = reinterpret_cast<T*>(smem);
@@ -329,7 +343,10 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (uint32_t e = 0; e < 16; ++e) {
           const uint32_t p = 16u * lq + e;
-          if (p < load && off + p < a.n) out[off + p] = w[e].r;
+          if (p < load && off + p < a.n) {
+            BOS_TR(0, 21, off + p);
+            out[off + p] = w[e].r;
+          }
         }
       }
       lds_barrier();  // LDS of this group is no longer read

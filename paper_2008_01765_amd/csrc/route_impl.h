@@ -130,13 +130,17 @@ __device__ __forceinline__ uint32_t seg_scan(uint32_t v, uint32_t* swave, uint32
       *total = __shfl(x, int(lane | (W - 1u)), 64);
     return x - v;
   } else {
-    if (lane == 63u) swave[wave] = x;
+    if (lane == 63u) {
+      BOS_TR(0, 9, wave);
+      swave[wave] = x;
+    }
     lds_barrier();
     constexpr uint32_t WPS = SEG / 64u;
     const uint32_t w0 = wave & ~(WPS - 1u);
     uint32_t pre = 0, tot = 0;
 #pragma unroll
     for (uint32_t q = 0; q < WPS; ++q) {
+      BOS_TR(0, 9, w0 + q);
       const uint32_t t = swave[w0 + q];
       if (w0 + q < wave) pre += t;
       tot += t;
@@ -201,11 +205,20 @@ __device__ __forceinline__ ElemRK<T> e_dpp(const ElemRK<T>& a) {
 }
 
 // LDS views of the bins (padded slot index)
+// (tw: the trace buffer its accesses fold into in the digest build: 0 for
+// the routing and the per-bin finish, 1 for the comparison sort)
 template <typename T>
 struct LdsR {
   T* rec;
-  __device__ ElemR<T> ld(uint32_t i) const { return ElemR<T>{rec[i]}; }
-  __device__ void st(uint32_t i, const ElemR<T>& v) const { rec[i] = v.r; }
+  uint32_t tw = 0;
+  __device__ ElemR<T> ld(uint32_t i) const {
+    BOS_TR(tw, 4, i);
+    return ElemR<T>{rec[i]};
+  }
+  __device__ void st(uint32_t i, const ElemR<T>& v) const {
+    BOS_TR(tw, 4, i);
+    rec[i] = v.r;
+  }
 };
 template <typename T>
 struct LdsRK {
@@ -213,8 +226,13 @@ struct LdsRK {
   uint32_t* klo;
   uint32_t* khi;
   uint16_t* aux;
-  __device__ ElemRK<T> ld(uint32_t i) const { return ElemRK<T>{rec[i], klo[i], khi[i], aux[i]}; }
+  uint32_t tw = 0;
+  __device__ ElemRK<T> ld(uint32_t i) const {
+    BOS_TR(tw, 17, i);
+    return ElemRK<T>{rec[i], klo[i], khi[i], aux[i]};
+  }
   __device__ void st(uint32_t i, const ElemRK<T>& v) const {
+    BOS_TR(tw, 17, i);
     rec[i] = v.r;
     klo[i] = v.klo;
     khi[i] = v.khi;
@@ -400,9 +418,14 @@ __device__ __forceinline__ void sort_bins(const PassArgs& a, uint64_t blk, uint3
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) {
     const uint32_t i = bbase + 17u * lq + e;
+    if (active) {
+      BOS_TR(0, 5, i);
+      BOS_TR(0, 4, i);
+    }
     v[e] = ElemR<T>{(active && stag[i] != kDummyTag) ? srec[i] : max_rec<T>()};
   }
   bin_bitonic<LZ>(v, lr, bbase, lq, active);
+  if (active) BOS_TR(0, 7, S);
   const uint32_t load = active ? sload[S] : 0u;
   *load_out = load;
   const bool permute = FIN == 2 || (FIN == 0 && a.fin == 0);
@@ -456,6 +479,10 @@ __device__ __forceinline__ void compact_xstage(T (&rv)[16], uint32_t (&tv)[16], 
                                                bool active) {
   constexpr uint32_t half = HLX * 16u;
   const uint32_t node0 = lq & ~(2u * HLX - 1u);
+  if (active) {
+    BOS_TR(0, 6, node0);
+    BOS_TR(0, 6, node0 + HLX);
+  }
   const uint32_t P0 = active ? bpfx[node0] : 0u, Ph = active ? bpfx[node0 + HLX] : 0u;
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) {
@@ -489,6 +516,10 @@ __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t
   uint32_t tv[16];
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) {
+    if (active) {
+      BOS_TR(0, 4, bbase + 17u * lq + e);
+      BOS_TR(0, 5, bbase + 17u * lq + e);
+    }
     rv[e] = active ? srec[bbase + 17u * lq + e] : zero_rec<T>();
     tv[e] = active ? stag[bbase + 17u * lq + e] : kDummyTag;
   }
@@ -504,7 +535,10 @@ __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t
   const uint32_t excl = seg_scan<HL>(active ? run : 0u, swave, &tot);
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) pm[e] += excl;
-  if (active) spfx[S * HL + lq] = pm[0];
+  if (active) {
+    BOS_TR(0, 6, S * HL + lq);
+    spfx[S * HL + lq] = pm[0];
+  }
   // distances 1, 2, 4, 8: register pairs
 #pragma unroll
   for (uint32_t eb = 0; eb < 4; ++eb) {
@@ -536,6 +570,8 @@ __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t
     if (active) {
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
+        BOS_TR(0, 4, bbase + 17u * lq + e);
+        BOS_TR(0, 5, bbase + 17u * lq + e);
         srec[bbase + 17u * lq + e] = rv[e];
         stag[bbase + 17u * lq + e] = tv[e];
       }
@@ -544,12 +580,20 @@ __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t
     const uint32_t hl = half >> 4;                   // lanes per half node
     const uint32_t node0 = lq & ~(2u * hl - 1u);     // first lane of this lane's node
     const uint32_t plq = lq ^ hl;
+    if (active) {
+      BOS_TR(0, 6, S * HL + node0);
+      BOS_TR(0, 6, S * HL + node0 + hl);
+    }
     const uint32_t P0 = active ? spfx[S * HL + node0] : 0u, Ph = active ? spfx[S * HL + node0 + hl] : 0u;
 #pragma unroll
     for (uint32_t e = 0; e < 16; ++e) {
       const uint32_t i = 16u * (lq & (hl - 1u)) + e;  // index in the node's half
       const bool b = active && swap_bit(P0, Ph, half, i);
       const uint32_t pi = bbase + 17u * plq + e;
+      if (active) {
+        BOS_TR(0, 4, pi);
+        BOS_TR(0, 5, pi);
+      }
       const T pr = active ? srec[pi] : zero_rec<T>();
       const uint32_t pt = active ? stag[pi] : kDummyTag;
       rv[e] = sel(b, pr, rv[e]);
@@ -576,13 +620,18 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   if (tid == 0) {
     uint64_t agg = 0;
-    for (uint32_t b = 0; b < NB; ++b) agg += sload[b] < Z ? sload[b] : Z;
+    for (uint32_t b = 0; b < NB; ++b) {
+      BOS_TR(0, 7, b);
+      agg += sload[b] < Z ? sload[b] : Z;
+    }
+    BOS_TR(0, 14, blk);
     a.scan[blk] = agg;
   }
   T outr[16];
   uint32_t load = 0;
   if constexpr (FIN == 3) {
     compact_bin<R, LZ, FULL>(srec, stag, spfx, swave, klev, outr);
+    if (active) BOS_TR(0, 7, S);
     load = active ? sload[S] : 0u;
   } else {
     sort_bins<R, LZ, FIN, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
@@ -592,11 +641,17 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
     const uint32_t kept = load < Z ? load : Z;
     const uint64_t gb = uint64_t(blk) * NB + brev_k(S, klev);
     T* BO = static_cast<T*>(a.rec_out);
-    if (lq == 0) a.loads[gb] = kept;
+    if (lq == 0) {
+      BOS_TR(0, 13, gb);
+      a.loads[gb] = kept;
+    }
 #pragma unroll
     for (uint32_t e = 0; e < 16; ++e) {
       const uint32_t p = 16u * lq + e;
-      if (p < kept) BO[(gb << LZ) + p] = outr[e];
+      if (p < kept) {
+        BOS_TR(0, 12, (gb << LZ) + p);
+        BO[(gb << LZ) + p] = outr[e];
+      }
     }
   }
 }
@@ -618,7 +673,11 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
   // look-back does not wait for this block's sort.
   uint64_t agg = 0;
   if (tid == 0) {
-    for (uint32_t b = 0; b < NB; ++b) agg += sload[b];
+    for (uint32_t b = 0; b < NB; ++b) {
+      BOS_TR(0, 7, b);
+      agg += sload[b];
+    }
+    BOS_TR(0, 14, blk);
     __hip_atomic_store(&a.scan[blk], ((blk == 0 ? 2ull : 1ull) << 62) | agg, __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -658,6 +717,8 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
       uint64_t off = excl;
       for (uint32_t u = 0; u < NB; ++u) {
         const uint32_t b = brev_k(u, klev);
+        BOS_TR(0, 8, b);
+        BOS_TR(0, 7, b);
         soff[2 * b] = uint32_t(off);
         soff[2 * b + 1] = uint32_t(off >> 32);
         off += sload[b];
@@ -667,11 +728,15 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
   lds_barrier();
   if (active) {
     T* OUT = static_cast<T*>(a.out);
+    BOS_TR(0, 8, S);
     const uint64_t off = (uint64_t(soff[2 * S + 1]) << 32) | soff[2 * S];
 #pragma unroll
     for (uint32_t e = 0; e < 16; ++e) {
       const uint32_t p = 16u * lq + e;
-      if (p < load && off + p < a.n) OUT[off + p] = outr[e];
+      if (p < load && off + p < a.n) {
+        BOS_TR(0, 16, off + p);
+        OUT[off + p] = outr[e];
+      }
     }
   }
 }
@@ -738,6 +803,10 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       const uint64_t gi = (bucket << LZ) + sb_load;
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
+        if (active) {
+          BOS_TR(0, 1, gi + e);
+          BOS_TR(0, 2, gi + e);
+        }
         dr[e] = active ? RI[gi + e] : zero_rec<T>();
         dt[e] = active ? a.tag_in[gi + e] : kDummyTag;
       }
@@ -748,6 +817,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
         const bool real = active && (sb_load + e) < gz;
+        if (real) BOS_TR(0, 3, gs + sb_load + e);
         dr[e] = real ? X[gs + sb_load + e] : zero_rec<T>();
         dt[e] = real ? 0u : kDummyTag;  // label filled in by finish_load
       }
@@ -808,6 +878,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   auto staged_first_load = [&](uint32_t item) {
     const uint64_t h = uint64_t(item) >> i0;
     for (uint32_t t = tid; t < mp; t += nthr) {
+      BOS_TR(0, 4, t);
+      BOS_TR(0, 5, t);
       srec[t] = zero_rec<T>();
       stag[t] = kDummyTag;
     }
@@ -826,6 +898,9 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         const uint64_t gs = (j * n) >> L;
         const uint32_t S = uint32_t(j - j_lo), s = uint32_t(x - gs);
         const uint32_t pi = S * ZP + s + (s >> 4);
+        BOS_TR(0, 3, x);
+        BOS_TR(0, 4, pi);
+        BOS_TR(0, 5, pi);
         srec[pi] = X[x];
         stag[pi] = L ? (word >> (32u - L)) : 0u;
       }
@@ -835,6 +910,10 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     for (uint32_t e = 0; e < 16; ++e) {
       const uint32_t s = sb_load + e;
       const uint32_t pi = S_load * ZP + s + (s >> 4);
+      if (active) {
+        BOS_TR(0, 4, pi);
+        BOS_TR(0, 5, pi);
+      }
       rv[e] = active ? srec[pi] : zero_rec<T>();
       tv[e] = active ? stag[pi] : kDummyTag;
     }
@@ -854,6 +933,10 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       if (d > 0) {
 #pragma unroll
         for (uint32_t e = 0; e < 16; ++e) {
+          if (active) {
+            BOS_TR(0, 4, baseA + e);
+            BOS_TR(0, 5, baseA + e);
+          }
           rv[e] = active ? srec[baseA + e] : zero_rec<T>();
           tv[e] = active ? stag[baseA + e] : kDummyTag;
         }
@@ -880,11 +963,14 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         pm[e] = (pe & 0xFFFFu) + min(pe >> 16, need);
       }
       if (active) {
+        BOS_TR(0, 6, ms * TPM + lt);
         spfx[ms * TPM + lt] = pm[0];
         if (LAST && lt == 0 && d + 1 == klev) {
           // bin loads of this block: S0 keeps min(x, Z) reals, S1 the rest of
           // the pair's reals (exact even when the MergeSplit overflowed)
           const uint32_t k0 = x < Z ? x : Z;
+          BOS_TR(0, 7, S0);
+          BOS_TR(0, 7, S1);
           sload[S0] = k0;
           sload[S1] = x + y - k0;
         }
@@ -892,6 +978,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
           const uint64_t G = S0 >> (d + 1);
           const uint64_t v = brev_k(S0 & ((1u << d) - 1u), d);
           const uint64_t j = (((h << (klev - d - 1)) + G) << lev) + (r << d) + v;
+          BOS_TR(0, 15, 0);
           atomicMin(a.status, (unsigned long long)((uint64_t(lev) << 32) | j));
         }
       }
@@ -944,6 +1031,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         if (active) {
 #pragma unroll
           for (uint32_t e = 0; e < 16; ++e) {
+            BOS_TR(0, 4, baseA + e);
+            BOS_TR(0, 5, baseA + e);
             srec[baseA + e] = rv[e];
             stag[baseA + e] = tv[e];
           }
@@ -961,9 +1050,11 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         for (uint32_t e = 0; e < 16; ++e) {
           const uint32_t q = e << (LQ - 4);
           const uint32_t i1 = (q & 15u) == 0u ? (q >> 4) : 0u;
+          if (active) BOS_TR(0, 6, ms * TPM + i1);
           pv[e] = active ? spfx[ms * TPM + i1] : 0u;
           if constexpr (LQ >= 11) {
             const uint32_t qh = q | (1u << (LQ - 5));
+            if (active) BOS_TR(0, 6, ms * TPM + (qh >> 4));
             pvh[e] = active ? spfx[ms * TPM + (qh >> 4)] : 0u;
           } else {
             pvh[e] = 0;
@@ -984,6 +1075,10 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
             const uint32_t s = sl + lowB;
             pi = (e < 8 ? base0 : base1) + s + (s >> 4);
           }
+          if (active) {
+            BOS_TR(0, 4, pi);
+            BOS_TR(0, 5, pi);
+          }
           rv[e] = active ? srec[pi] : zero_rec<T>();
           tv[e] = active ? stag[pi] : kDummyTag;
         }
@@ -994,6 +1089,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
           for (uint32_t e = 0; e < 16; ++e) {
             // node: q bits 0..LQ-6 cleared; its start and middle are 16-aligned
             const uint32_t qn = (e << (LQ - 4)) | (lb1 << (LQ - 5));
+            BOS_TR(0, 6, ms * TPM + (qn >> 4));
+            BOS_TR(0, 6, ms * TPM + ((qn | half) >> 4));
             const uint32_t P0 = spfx[ms * TPM + (qn >> 4)];
             const uint32_t Ph = spfx[ms * TPM + ((qn | half) >> 4)];
             const bool b = swap_bit(P0, Ph, half, rest);
@@ -1051,6 +1148,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
                 const uint32_t s = sl + lowB;
                 pi = (e < 8 ? base0 : base1) + s + (s >> 4);
               }
+              BOS_TR(0, 4, pi);
+              BOS_TR(0, 5, pi);
               srec[pi] = rv[e];
               stag[pi] = tv[e];
             }
@@ -1059,6 +1158,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
           if (active) {
 #pragma unroll
             for (uint32_t e = 0; e < 16; ++e) {
+              BOS_TR(0, 4, baseA + e);
+              BOS_TR(0, 5, baseA + e);
               srec[baseA + e] = rv[e];
               stag[baseA + e] = tv[e];
             }
@@ -1081,6 +1182,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
             } else {
               gi = (((lt < HALF_LANES) ? ob0 : ob1) << LZ) + sb_load + e;
             }
+            BOS_TR(0, 10, gi);
+            BOS_TR(0, 11, gi);
             RO[gi] = rv[e];
             a.tag_out[gi] = tv[e];
           }

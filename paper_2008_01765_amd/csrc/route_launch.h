@@ -7,6 +7,7 @@ namespace bos {
 
 template <int R, int LZ, int MODE>
 hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hipStream_t s) {
+  BOS_TRACE_BIND();
   const uint32_t m = (1u << LZ) << a.klev;
   uint32_t threads = m >> 4;
   if (threads < 64) threads = 64;
@@ -41,6 +42,7 @@ hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hip
 template <int R, int LZ, int MODE>
 hipError_t launch_route_bt(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs, uint32_t blocks,
                            uint32_t threads, uint32_t lds, hipStream_t s) {
+  BOS_TRACE_BIND();
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&route_kernel_b<R, LZ, MODE>),
@@ -89,6 +91,7 @@ hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t
 // flagged).  *a.tie must be zero on entry.
 template <int R, int LZ, bool EXACT>
 hipError_t launch_orp_finish_e(const FinishArgs& a, uint32_t grid, hipStream_t s) {
+  BOS_TRACE_BIND();
   constexpr uint32_t HL = (1u << LZ) >> 4, BPW = kFinishThreads / HL;
   const uint32_t lds = finish_lds_bytes(R, LZ);
   static bool attr_set = false;

@@ -28,7 +28,10 @@ constexpr uint32_t kSmpLog = R == 8 ? 6u : 5u;
 // its first record can be one.
 template <int R, typename T>
 __device__ __forceinline__ void write_sample(void* smp, uint64_t base, uint64_t n, T first) {
-  if (smp && (base & ((1ull << kSmpLog<R>) - 1)) == 0 && base < n) static_cast<T*>(smp)[base >> kSmpLog<R>] = first;
+  if (smp && (base & ((1ull << kSmpLog<R>) - 1)) == 0 && base < n) {
+    BOS_TR(1, 41, base >> kSmpLog<R>);
+    static_cast<T*>(smp)[base >> kSmpLog<R>] = first;
+  }
 }
 
 __device__ __forceinline__ uint32_t lpad(uint32_t s) { return s + (s >> 5); }
@@ -63,6 +66,8 @@ __device__ __forceinline__ uint64_t merge_path(const T* A, uint64_t la, const T*
   uint64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
+    BOS_TR(1, 42, d - mid - 1);
+    BOS_TR(1, 43, mid);
     if (!rec_less(Bv[d - mid - 1], A[mid]))
       lo = mid + 1;
     else
@@ -90,12 +95,19 @@ __device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t ti
   const uint64_t base = (tile << TLOG) + 16u * lq;
   ElemR<T> v[16];
 #pragma unroll
-  for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
-  const LdsR<T> lds{srec};
+  for (uint32_t e = 0; e < 16; ++e) {
+    if (base + e < n) BOS_TR(1, 40, base + e);
+    v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
+  }
+  LdsR<T> lds{srec};
+  lds.tw = 1;
   bin_bitonic<TLOG>(v, lds, 0u, lq, true);
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e)
-    if (base + e < n) B[base + e] = v[e].r;
+    if (base + e < n) {
+      BOS_TR(1, 40, base + e);
+      B[base + e] = v[e].r;
+    }
   write_sample<R>(smp, base, n, v[0].r);
 }
 
@@ -146,6 +158,7 @@ __device__ __forceinline__ void merge_partition_one(const void* src_, uint64_t n
   const uint64_t lo = o & ~(2 * w - 1);  // run widths are powers of two
   const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
   const uint64_t a = merge_path(src + lo, mid - lo, src + mid, hi - mid, o - lo);
+  BOS_TR(1, 44, 2 * b);
   split[2 * b] = lo + a;
   split[2 * b + 1] = mid + (o - lo - a);
 }
@@ -172,6 +185,8 @@ __device__ __forceinline__ void merge_items(const T* SA, uint32_t na, const T* S
   uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
   while (l < h) {
     const uint32_t md = (l + h) >> 1;
+    BOS_TR(1, 45, dd - md - 1);
+    BOS_TR(1, 46, md);
     if (!rec_less(SB[dd - md - 1], SA[md]))
       l = md + 1;
     else
@@ -180,6 +195,8 @@ __device__ __forceinline__ void merge_items(const T* SA, uint32_t na, const T* S
   uint32_t ia = l, ib = dd - l;
 #pragma unroll
   for (uint32_t k = 0; k < ITEMS; ++k) {
+    BOS_TR(1, 45, ib);
+    BOS_TR(1, 46, ia);
     const bool take_a = ia < na && (ib >= nb || !rec_less(SB[ib], SA[ia]));
     const T va = SA[ia < na ? ia : 0], vb = SB[ib < nb ? ib : 0];
     out[k] = sel(take_a, va, vb);  // per word: a select of whole records goes through scratch
@@ -213,8 +230,10 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
     const uint64_t lo = o0 & ~(2 * w - 1);  // run widths are powers of two
     const uint64_t mid = lo + w < n ? lo + w : n, hi = lo + 2 * w < n ? lo + 2 * w : n;
     const uint64_t o1 = o0 + kMTile<R> < hi ? o0 + kMTile<R> : hi;
+    BOS_TR(1, 44, 2 * b);
     a0 = split[2 * b];
     b0 = split[2 * b + 1];
+    if (o1 != hi) BOS_TR(1, 44, 2 * b + 2);
     const uint64_t a1 = o1 == hi ? mid : split[2 * b + 2], b1 = o1 == hi ? hi : split[2 * b + 3];
     na = uint32_t(a1 - a0);
     nb = uint32_t(b1 - b0);
@@ -232,6 +251,7 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
     for (uint32_t k = 0; k < kMItems<R>; ++k) {
       const uint32_t t = threadIdx.x + k * kMThreads<R>;
       const uint64_t gi = t < na ? a0 + t : b0 + t - na;
+      BOS_TR(1, 48, t < cnt ? gi : a0);
       in[k] = srcv[t < cnt ? gi : a0];
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the stores
@@ -265,7 +285,10 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
 #pragma unroll
   for (uint32_t k = 0; k < kMItems<R>; ++k) {
     const uint32_t t = threadIdx.x + k * kMThreads<R>;
-    if (t < cnt) dst[o0 + t] = s[t + (t >> 4)];
+    if (t < cnt) {
+      BOS_TR(1, 49, o0 + t);
+      dst[o0 + t] = s[t + (t >> 4)];
+    }
   }
 }
 
@@ -387,8 +410,10 @@ template <int R>
 __global__ void sample_gather_kernel(const void* src_, void* smp_, uint64_t n) {
   using T = typename RecOf<R>::T;
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < ((n + (1ull << kSmpLog<R>) - 1) >> kSmpLog<R>))
+  if (i < ((n + (1ull << kSmpLog<R>) - 1) >> kSmpLog<R>)) {
+    BOS_TR(1, 41, i);
     static_cast<T*>(smp_)[i] = static_cast<const T*>(src_)[i << kSmpLog<R>];
+  }
 }
 
 // Ranks of the samples in their group, kSplS<R> samples per thread with all
@@ -416,6 +441,7 @@ __global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, ui
     const uint64_t i = i0 + q < ns ? i0 + q : i0;  // past the end: repeat the first (not stored)
     const uint64_t p = i << LG, gs = (p >> (lw + 2)) << (lw + 2);
     j[q] = uint32_t(p >> lw) & 3u;
+    BOS_TR(1, 41, i);
     e[q] = smp[i];
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) {
@@ -435,6 +461,7 @@ __global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, ui
       for (uint32_t k = 0; k < 4; ++k) {
         if (cl[q][k] == 0) continue;
         const uint32_t half = cl[q][k] >> 1;
+        BOS_TR(1, 41, uint64_t(rb[q][k]) + c[q][k] + half);
         if (precedes(smp[uint64_t(rb[q][k]) + c[q][k] + half], k, e[q], j[q])) {
           c[q][k] += half + 1;
           cl[q][k] -= half + 1;
@@ -453,6 +480,7 @@ __global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, ui
     const uint32_t r = uint32_t(i - own[q]) + c[q][0] + c[q][1] + c[q][2] + c[q][3];
     if (r % kSplM != 0) continue;
     uint64_t* out = spl + 4 * (g * ntf + r / kSplM);
+    BOS_TR(1, 50, 4 * (g * ntf + r / kSplM));
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) out[k] = k == j[q] ? (kSplOwn | i) : uint64_t(c[q][k]);
   }
@@ -492,6 +520,8 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
   }
   if (threadIdx.x < 64) {
     const uint32_t lane = threadIdx.x;
+    BOS_TR(1, 41, base);
+    BOS_TR(1, 41, last);
     const T ef = smp[base], el = smp[last];
     uint32_t lo[4][2], hi[4][2];
 #pragma unroll
@@ -511,6 +541,7 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
 #pragma unroll
         for (uint32_t b = 0; b < 2; ++b) {
           const uint32_t l = lo[k][b], h = hi[k][b], st = (h - l + 63) / 64, q = l + lane * st;
+          BOS_TR(1, 41, l < h ? rb[k] + (q < h ? q : l) : base);
           x[k][b] = smp[l < h ? rb[k] + (q < h ? q : l) : base];  // a closed search rereads a valid sample
         }
 #pragma unroll
@@ -542,13 +573,18 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
   for (uint32_t k = 0; k < 4; ++k) {
     if (k == j || wlen[k] > CAP) continue;
     const uint32_t slot = k < j ? k : k - 1;
-    for (uint32_t t = threadIdx.x; t < wlen[k]; t += 256) win[slot * CAP + t] = smp[rb[k] + wlo[k] + t];
+    for (uint32_t t = threadIdx.x; t < wlen[k]; t += 256) {
+      BOS_TR(1, 41, rb[k] + wlo[k] + t);
+      BOS_TR(1, 51, slot * CAP + t);
+      win[slot * CAP + t] = smp[rb[k] + wlo[k] + t];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (uint32_t q = 0; q < kSplS<R>; ++q) {
     const uint64_t i = base + q * 256u + threadIdx.x;
     if (i > last) continue;
+    BOS_TR(1, 41, i);
     const T e = smp[i];
     uint32_t c[4];
     uint32_t r = uint32_t(i - rb[j]);
@@ -561,6 +597,8 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
       uint32_t l = 0, len = wlen[k];
       while (len > 0) {
         const uint32_t half = len >> 1;
+        if (inl) BOS_TR(1, 51, slot * CAP + l + half);
+        else BOS_TR(1, 41, rb[k] + wlo[k] + l + half);
         const T x = inl ? win[slot * CAP + l + half] : smp[rb[k] + wlo[k] + l + half];
         if (precedes(x, k, e, j)) {
           l += half + 1;
@@ -574,6 +612,7 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
     }
     if (r % kSplM != 0) continue;
     uint64_t* out = spl + 4 * (g * ntf + r / kSplM);
+    BOS_TR(1, 50, 4 * (g * ntf + r / kSplM));
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k) out[k] = k == j ? (kSplOwn | i) : uint64_t(c[k]);
   }
@@ -593,6 +632,7 @@ __global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t
   if (t >= total) return;
   uint64_t wd[4];
   uint32_t j = 0, owners = 0;
+  BOS_TR(1, 50, 4 * t);
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
     wd[k] = spl[4 * t + k];
@@ -615,6 +655,7 @@ __global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t
     for (uint32_t k = 0; k < 4; ++k) spl[4 * t + k] = ~0ull;
     return;
   }
+  BOS_TR(1, 41, i);
   const T e = static_cast<const T*>(smp_)[i];
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
@@ -630,6 +671,7 @@ __global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t
     for (uint32_t k = 0; k < 4; ++k) {
       if (cl[k] == 0) continue;
       const uint64_t half = cl[k] >> 1;
+      BOS_TR(1, 48, st[k] + lb[k] + half);
       if (precedes(src[st[k] + lb[k] + half], k, e, j)) {
         lb[k] += half + 1;
         cl[k] -= half + 1;
@@ -639,6 +681,7 @@ __global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t
       maxl = cl[k] > maxl ? cl[k] : maxl;
     }
   }
+  BOS_TR(1, 50, 4 * t);
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) spl[4 * t + k] = st[k] + lb[k];
 }
@@ -650,7 +693,10 @@ __global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t
 template <bool PAD, typename T, uint32_t ITEMS>
 __device__ __forceinline__ void merge_items_lds(const T* s, uint32_t xa, uint32_t na, uint32_t xb, uint32_t nb,
                                                 uint32_t dd, T (&out)[ITEMS]) {
-  auto at = [&](uint32_t q) { return PAD ? s[q + (q >> 4)] : s[q]; };
+  auto at = [&](uint32_t q) {
+    BOS_TR(1, 47, q);
+    return PAD ? s[q + (q >> 4)] : s[q];
+  };
   uint32_t l = dd > nb ? dd - nb : 0, h = dd < na ? dd : na;
   while (l < h) {
     const uint32_t md = (l + h) >> 1;
@@ -696,6 +742,8 @@ __device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, ui
   const uint64_t ntg = g + 1 < ng ? ntf : ntl;
   uint64_t a[4], e[4], o0 = gs;
   bool ok = b < ntg;
+  BOS_TR(1, 50, 4 * tile);
+  if (b + 1 < ntg) BOS_TR(1, 50, 4 * tile + 4);
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) {
     const uint64_t st = gs + k * w < n ? gs + k * w : n, en = n - st < w ? st + (n - st) : st + w;
@@ -730,6 +778,7 @@ __device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, ui
       const uint32_t t = threadIdx.x + k * NT;
       const uint64_t gi = t < n0 ? a[0] + t : t < nx ? a[1] + (t - n0) : t < nx + n2 ? a[2] + (t - nx)
                                                                                       : a[3] + (t - nx - n2);
+      BOS_TR(1, 48, t < cnt ? gi : fb);
       in[k] = srcv[t < cnt ? gi : fb];
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -768,8 +817,12 @@ __device__ __forceinline__ void merge4_tile_one(const void* src_, void* dst_, ui
     if (t < cnt) {
       const T v = s[t + (t >> 4)];
       const uint64_t o = o0 + t;
+      BOS_TR(1, 49, o);
       dst[o] = v;
-      if (smp && (o & ((1ull << LG) - 1)) == 0) smp[o >> LG] = v;
+      if (smp && (o & ((1ull << LG) - 1)) == 0) {
+        BOS_TR(1, 41, o >> LG);
+        smp[o >> LG] = v;
+      }
     }
   }
 }
@@ -987,6 +1040,7 @@ unsigned long long* comparison_sort_err_word(uint64_t* split, uint64_t n, int re
 template <int R>
 static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                     hipStream_t s, void** result, bool multiway) {
+  BOS_TRACE_BIND();
   static bool attr = false;
   if (!attr) {
     hipError_t e = allow_lds(merge_tile_kernel<R>);
@@ -1209,6 +1263,7 @@ static hipError_t batched_sort_launch_t(int kind, uint32_t tile, const SortSeg* 
 // the segments.
 hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs,
                                uint32_t total, hipStream_t s) {
+  BOS_TRACE_BIND();
   return rec == 8 ? batched_sort_launch_t<8>(kind, tile, segs, nsegs, total, s)
                   : batched_sort_launch_t<16>(kind, tile, segs, nsegs, total, s);
 }

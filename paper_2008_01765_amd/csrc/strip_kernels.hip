@@ -33,17 +33,25 @@ __device__ __forceinline__ void scan_blocks(unsigned long long* v, uint32_t coun
   const uint32_t per = (count + kScanThreads - 1) / kScanThreads;
   const uint32_t b = t * per < count ? t * per : count, e = b + per < count ? b + per : count;
   unsigned long long sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += v[i];
+  for (uint32_t i = b; i < e; ++i) {
+    BOS_TR(0, 30, i);
+    sum += v[i];
+  }
+  BOS_TR(0, 31, t);
   part[t] = sum;
   __syncthreads();
   for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
+    if (t >= off) BOS_TR(0, 31, t - off);
     const unsigned long long x = t >= off ? part[t - off] : 0ull;
     __syncthreads();
+    BOS_TR(0, 31, t);
     part[t] += x;
     __syncthreads();
   }
+  BOS_TR(0, 31, t);
   unsigned long long run = part[t] - sum;
   for (uint32_t i = b; i < e; ++i) {
+    BOS_TR(0, 30, i);
     const unsigned long long x = v[i];
     v[i] = run;
     run += x;
@@ -63,6 +71,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(unsigned long
   __shared__ unsigned long long wsum[kScanThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   const uint64_t idx = uint64_t(blockIdx.x) * kScanThreads + tid;
+  if (idx < count) BOS_TR(0, 30, idx);
   const unsigned long long x = idx < count ? v[idx] : 0ull;
   unsigned long long incl = x;
 #pragma unroll
@@ -70,17 +79,27 @@ __global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(unsigned long
     const unsigned long long y = __shfl_up(incl, o, 64);
     if (lane >= o) incl += y;
   }
-  if (lane == 63) wsum[wv] = incl;
+  if (lane == 63) {
+    BOS_TR(0, 31, wv);
+    wsum[wv] = incl;
+  }
   __syncthreads();
   unsigned long long before = 0, total = 0;
 #pragma unroll
   for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+    BOS_TR(0, 31, w);
     const unsigned long long t = wsum[w];
     before += w < wv ? t : 0ull;
     total += t;
   }
-  if (idx < count) v[idx] = before + incl - x;
-  if (tid == 0) tot[blockIdx.x] = total;
+  if (idx < count) {
+    BOS_TR(0, 30, idx);
+    v[idx] = before + incl - x;
+  }
+  if (tid == 0) {
+    BOS_TR(0, 32, blockIdx.x);
+    tot[blockIdx.x] = total;
+  }
 }
 
 // Bitonic sort of sb[0..P2) by (key, payload) (P2 a power of two), by the
@@ -92,6 +111,8 @@ __device__ __forceinline__ void lds_bitonic(T* sb, uint32_t P2) {
       for (uint32_t t = threadIdx.x; t < P2 / 2; t += kStripThreads) {
         const uint32_t i = ((t & ~(stride - 1u)) << 1) | (t & (stride - 1u)), k = i + stride;
         const bool asc = (i & size) == 0;
+        BOS_TR(0, 33, i);
+        BOS_TR(0, 33, k);
         const T x = sb[i], y = sb[k];
         const bool swap = asc ? rec_less(y, x) : rec_less(x, y);
         sb[i] = sel(swap, y, x);
@@ -119,15 +140,22 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
   T* out = static_cast<T*>(out_);
   const uint32_t tid = threadIdx.x, NB = 1u << klev;
   const uint64_t bin0 = blk << klev;
-  for (uint32_t j = tid; j < NB; j += kStripThreads) pre[j + 1] = loads[bin0 + j];
+  for (uint32_t j = tid; j < NB; j += kStripThreads) {
+    BOS_TR(0, 34, bin0 + j);
+    BOS_TR(0, 35, j + 1);
+    pre[j + 1] = loads[bin0 + j];
+  }
   __syncthreads();
   if (tid == 0) {
     pre[0] = 0;
+    for (uint32_t j = 1; j <= NB; ++j) BOS_TR(0, 35, j);
     for (uint32_t j = 1; j <= NB; ++j) pre[j] += pre[j - 1];
     nstrad = 0;
   }
   __syncthreads();
+  BOS_TR(0, 35, NB);
   const uint32_t total = pre[NB];
+  BOS_TR(0, 36, blk);
   const uint64_t base = boff[blk] + (coff ? coff[blk / kScanThreads] : 0ull);
   if (tile) {
     // the straddling bins, in bin order (tile is a power of two)
@@ -136,7 +164,10 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
       uint32_t c = 0;
       for (uint32_t j = 0; j < NB; ++j) {
         const uint64_t b0 = base + pre[j], b1 = base + pre[j + 1];
-        if (b1 - b0 >= 2 && (b0 >> tl) != ((b1 - 1) >> tl)) strad[c++] = uint16_t(j);
+        if (b1 - b0 >= 2 && (b0 >> tl) != ((b1 - 1) >> tl)) {
+          BOS_TR(0, 37, c);
+          strad[c++] = uint16_t(j);
+        }
       }
       nstrad = c;
     }
@@ -148,12 +179,20 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
       uint32_t P2 = 2;
       while (P2 < ld) P2 <<= 1;
       const T* src = binned + ((bin0 + j) << lz);
-      for (uint32_t i = tid; i < P2; i += kStripThreads) sb[i] = i < ld ? src[i] : max_rec<T>();
+      for (uint32_t i = tid; i < P2; i += kStripThreads) {
+        if (i < ld) BOS_TR(0, 38, ((bin0 + j) << lz) + i);
+        BOS_TR(0, 33, i);
+        sb[i] = i < ld ? src[i] : max_rec<T>();
+      }
       __syncthreads();
       lds_bitonic(sb, P2);
       const uint64_t o = base + pre[j];
       for (uint32_t i = tid; i < ld; i += kStripThreads)
-        if (o + i < n) out[o + i] = sb[i];
+        if (o + i < n) {
+          BOS_TR(0, 33, i);
+          BOS_TR(0, 39, o + i);
+          out[o + i] = sb[i];
+        }
       __syncthreads();
     }
   }
@@ -173,6 +212,7 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
       uint32_t lo = 0, hi = NB;
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
+        BOS_TR(0, 35, mid);
         if (pre[mid] <= qq)
           lo = mid;
         else
@@ -180,13 +220,21 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
       }
       // a straddling bin was written sorted above
       bool done = false;
-      for (uint32_t m = 0; m < ns; ++m) done |= strad[m] == lo;
+      for (uint32_t m = 0; m < ns; ++m) {
+        BOS_TR(0, 37, m);
+        done |= strad[m] == lo;
+      }
+      BOS_TR(0, 35, lo);
+      BOS_TR(0, 38, ((bin0 + lo) << lz) + (qq - pre[lo]));
       v[k] = bv[((bin0 + lo) << lz) + (qq - pre[lo])];
       dst[k] = q < total && !done ? base + q : ~0ull;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kStripItems; ++k)
-      if (dst[k] < n) ov[dst[k]] = v[k];
+      if (dst[k] < n) {
+        BOS_TR(0, 39, dst[k]);
+        ov[dst[k]] = v[k];
+      }
   }
 }
 
@@ -223,6 +271,7 @@ __global__ __launch_bounds__(kStripThreads) void strip_kernel_b(const StripSeg* 
 // Batched scan + strip over nsegs instances (device table segs, `blocks` strip
 // workgroups in all).
 hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, uint32_t blocks, hipStream_t s) {
+  BOS_TRACE_BIND();
   if (nsegs == 0) return hipSuccess;
   hipLaunchKernelGGL(scan_blocks_kernel_b, dim3(nsegs), dim3(kScanThreads), 0, s, segs);
   hipError_t e = hipGetLastError();
@@ -237,6 +286,7 @@ hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, u
 // The two-level scan of the block counts alone (bos_orp's finish reads the
 // offsets): bsum scanned in place within chunks of 1024, coff the chunk offsets.
 hipError_t launch_block_scan(unsigned long long* bsum, unsigned long long* coff, uint32_t nblocks, hipStream_t s) {
+  BOS_TRACE_BIND();
   if (nblocks == 0 || !coff) return hipErrorInvalidValue;
   const uint32_t nchunks = (nblocks + kScanThreads - 1) / kScanThreads;
   hipLaunchKernelGGL(scan_chunks_kernel, dim3(nchunks), dim3(kScanThreads), 0, s, bsum, nblocks, coff);
@@ -252,6 +302,7 @@ hipError_t launch_block_scan(unsigned long long* bsum, unsigned long long* coff,
 hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsigned long long* bsum,
                         unsigned long long* coff, void* out, uint64_t n, uint32_t nblocks, uint32_t klev, uint32_t lz,
                         uint32_t tile, hipStream_t s) {
+  BOS_TRACE_BIND();
   if (klev > 9 || lz > 11 || nblocks == 0 || (tile & (tile - 1u)) || !coff) return hipErrorInvalidValue;
   const uint32_t nchunks = (nblocks + kScanThreads - 1) / kScanThreads;
   hipLaunchKernelGGL(scan_chunks_kernel, dim3(nchunks), dim3(kScanThreads), 0, s, bsum, nblocks, coff);
