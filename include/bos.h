@@ -60,6 +60,14 @@ typedef enum { BOS_REC_U32U32 = 8, BOS_REC_U64U64 = 16 } bos_rec;
 #define BOS_SYNC 1u        /* synchronize and retry on overflow inside the call */
 #define BOS_GENERIC_ROUTING 2u /* test hook: route with the generic (non-specialised)
                                   kernel; same results, slower */
+#define BOS_STRICT 8u          /* strict client (Section 4.1): one butterfly level per
+                                  pass, so a workgroup holds one MergeSplit's 2Z slots
+                                  (the paper's client storage) and keeps no LDS state
+                                  from one level to the next; the per-bin finish works
+                                  on one bin's Z slots.  For a threat model in which
+                                  the working set of a fused block is observable.
+                                  Slower (L passes instead of L/3); same outputs.  k
+                                  must be 0 or 1 (else BOS_ERR_INVALID_ARG). */
 #define BOS_EXACT_FINISH 4u    /* test hook: run bos_orp's per-bin finish through its
                                   exact-comparator launch (otherwise taken only when two
                                   random keys of a bin tie); same results, slower */

@@ -24,6 +24,7 @@ OK, INVALID_ARG, OVERFLOW, WORKSPACE, HIP_ERR, INSECURE_Z, UNSUPPORTED, INTERNAL
 SYNC = 1
 GENERIC_ROUTING = 2
 EXACT_FINISH = 4
+STRICT = 8
 
 
 class BosError(RuntimeError):
@@ -175,7 +176,7 @@ def _check(st):
 
 
 def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=True, generic=False,
-           exact_finish=False, attempt=0):
+           exact_finish=False, attempt=0, strict=False):
     p = Params()
     lib().bos_default_params(C.byref(p))
     p.attempt = attempt
@@ -183,7 +184,8 @@ def params(seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, sync=T
     p.z, p.k, p.tile = z, k, tile
     p.max_retries = max_retries
     p.min_security_bits = min_security_bits
-    p.flags = (SYNC if sync else 0) | (GENERIC_ROUTING if generic else 0) | (EXACT_FINISH if exact_finish else 0)
+    p.flags = (SYNC if sync else 0) | (GENERIC_ROUTING if generic else 0) | (EXACT_FINISH if exact_finish else 0) | \
+        (STRICT if strict else 0)
     return p
 
 
@@ -246,22 +248,23 @@ def _run(fn, t, p, out, stream):
 
 
 def orp(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, stream=None, report=False,
-        generic=False, exact_finish=False, sync=True, attempt=0):
+        generic=False, exact_finish=False, sync=True, attempt=0, strict=False):
     """Bucket ORP of the records in t (Section 3.2).  With sync=False the call
     enqueues attempt `attempt` alone and leaves its overflow status on the
     device (status_word)."""
     p = params(seed, z, k, 0, max_retries, min_security_bits, sync=sync, generic=generic,
-               exact_finish=exact_finish, attempt=attempt)
+               exact_finish=exact_finish, attempt=attempt, strict=strict)
     o, rep = _run(lib().bos_orp, t, p, out, stream)
     return (o, rep) if report else o
 
 
 def sort(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,
-         report=False, generic=False, sync=True, attempt=0):
+         report=False, generic=False, sync=True, attempt=0, strict=False):
     """Bucket oblivious sort of the records in t (Section 3.3).  With
     sync=False the call does not wait for the overflow check (attempt
     `attempt` alone, stream-ordered); status_word reads its outcome."""
-    p = params(seed, z, k, tile, max_retries, min_security_bits, sync=sync, generic=generic, attempt=attempt)
+    p = params(seed, z, k, tile, max_retries, min_security_bits, sync=sync, generic=generic, attempt=attempt,
+               strict=strict)
     o, rep = _run(lib().bos_sort, t, p, out, stream)
     return (o, rep) if report else o
 
@@ -420,8 +423,8 @@ def profile_read():
              "ms": buf[i].ms, "bytes": buf[i].bytes} for i in range(min(cnt, cap))]
 
 
-def plan(n, rec, z=0, k=0, tile=0, min_security_bits=80):
-    p = params(0, z, k, tile, 3, min_security_bits)
+def plan(n, rec, z=0, k=0, tile=0, min_security_bits=80, strict=False):
+    p = params(0, z, k, tile, 3, min_security_bits, strict=strict)
     b, l = C.c_uint64(), C.c_uint32()
     passes = (C.c_uint32 * 33)()
     _check(lib().bos_plan(n, rec, C.byref(p), C.byref(b), C.byref(l), passes))

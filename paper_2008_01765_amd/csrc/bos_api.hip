@@ -259,7 +259,11 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   // workgroup; the tuned or default k is capped at what fits.
   if (q.k > 12) return BOS_ERR_INVALID_ARG;
   if (q.k > kmid) return BOS_ERR_UNSUPPORTED;
-  const uint32_t kreq = q.k ? q.k : (tuned && te.k && te.z == Z ? te.k : 3u);
+  // strict mode (Section 4.1's client of O(1) buckets): one level per pass,
+  // so a workgroup holds one MergeSplit's 2Z slots and nothing across levels
+  const bool strict = (q.flags & BOS_STRICT) != 0;
+  if (strict && q.k > 1) return BOS_ERR_INVALID_ARG;
+  const uint32_t kreq = strict ? 1u : q.k ? q.k : (tuned && te.k && te.z == Z ? te.k : 3u);
   const uint32_t k = std::min(kreq, kmid);
   pl->k = k;
   pl->tile = q.tile ? q.tile : (tuned && te.tile ? te.tile : kDefaultTile);
