@@ -57,6 +57,8 @@ def parse():
                     help="steps per (Z, k) point of the n=2^28 sweep; 0 skips the sweep")
     ap.add_argument("--sweep-seeds", type=int, default=100,
                     help="ORP seeds per Z for the overflow-retry count")
+    ap.add_argument("--dup-steps", type=int, default=10,
+                    help="steps of the duplicate-heavy 2^24 x 16 B leg (bucket and bitonic sort); 0 skips it")
     ap.add_argument("--tuning", default="",
                     help="tuning table for the batched and serving legs (default: the stored table)")
     return ap.parse_args()
@@ -159,6 +161,45 @@ def bench_sweep(args, torch, bos, x, out):
         res["overflow"].append({"z": z, "seeds": args.sweep_seeds, "retries": retries, "failed": failed,
                                 "log2_eps_bound": round(autotune.log2_eps(n, z), 1),
                                 "s": round(time.perf_counter() - t0, 1)})
+    return res
+
+
+def bench_dup(args, torch, bos, inputs):
+    """The duplicate-heavy workload: n = 2^24 records of 16 B, keys uniform on
+    [0, 2^20) (ties broken by the payload), Z = 512, data seed 42.  bos_sort
+    and the bitonic sort of the same resident records, each timed with HIP
+    events over `dup_steps` calls after one warm call; outputs compared."""
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    x = bos.from_numpy(inputs.workload_dup(args.data_seed), dev)
+    n = x.shape[0]
+    out = torch.empty_like(x)
+    bout = torch.empty_like(x)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.dup_steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.dup_steps
+
+    res = {"workload": "n=2^24 records of 16 B, key uniform on [0, 2^20), payload=index, Z=512", "n": n,
+           "tuning": args.tuning_used}
+    for label, kw in (("tuned", {}), ("k3_tile4096", {"k": 3, "tile": 4096})):
+        ms = timed(lambda: bos.sort(x, seed=args.seed, z=512, out=out, **kw))
+        res["bucket_" + label] = {"ms": round(ms, 3), "Melem/s": round(n / ms / 1e3, 1)}
+    bms = timed(lambda: bos.bitonic_sort(x, out=bout))
+    best = min(res["bucket_tuned"]["ms"], res["bucket_k3_tile4096"]["ms"])
+    res["bitonic"] = {"ms": round(bms, 3), "Melem/s": round(n / bms / 1e3, 1)}
+    res["speedup_of_bucket_sort"] = round(bms / best, 3)
+    res["equal_output"] = bool(torch.equal(out, bout))
+    del x, out, bout
+    bos.release_workspaces()
+    torch.cuda.empty_cache()
     return res
 
 
@@ -428,8 +469,16 @@ def main():
         torch.cuda.synchronize()
         bms = e0.elapsed_time(e1) / args.bitonic_steps
         same = bool(torch.equal(bout, out))
+        # per-kernel times in a separate profiled call (events around every launch)
+        bos.profile_enable(True)
+        bos.profile_read()
+        bos.bitonic_sort(x, out=bout)
+        torch.cuda.synchronize()
+        bkinds = per_kind(bos.profile_read(), 1)
+        bos.profile_enable(False)
         bit = {"ms_per_step": round(bms, 3), "Melem/s": round(n / bms / 1e3, 1), "equal_output": same,
-               "speedup_of_bucket_sort": round(bms / ms_per_step, 3)}
+               "speedup_of_bucket_sort": round(bms / ms_per_step, 3),
+               "kernels": bkinds}
         del bout
 
     sweep = None
@@ -459,8 +508,12 @@ def main():
 
     batched = None
     args.tuning_used = None
-    if (args.batched_count > 0 or args.serving_requests > 0) and args.mode == "sort":
+    if (args.batched_count > 0 or args.serving_requests > 0 or args.dup_steps > 0) and args.mode == "sort":
         args.tuning_used = install_tuning(args, bos)
+    dup = None
+    if args.dup_steps > 0 and args.mode == "sort":
+        dup = bench_dup(args, torch, bos, inputs)
+        print("dup: %s" % json.dumps(dup), file=sys.stderr, flush=True)
     if args.batched_count > 0 and args.mode == "sort":
         batched = bench_batched(args, torch, bos, inputs)
         print("batched: %s" % json.dumps(batched), file=sys.stderr, flush=True)
@@ -482,7 +535,7 @@ def main():
                    "n": n, "rec_bytes": args.rec, "z": rep["z"], "k": rep["k"], "levels": rep["levels"],
                    "passes": rep["passes"], "tile": rep["tile"], "parallelism": "1 GPU"},
         "attempts": rep["attempts"], "correct": ok,
-        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "batched": batched, "serving": served, "sweep": sweep,
+        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "dup_workload": dup, "batched": batched, "serving": served, "sweep": sweep,
         "kernels": kern,
         "kernel_sources": kernel_source_digest(),
     }

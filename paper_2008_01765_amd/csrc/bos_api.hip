@@ -51,7 +51,8 @@ hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* 
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
 bool sort_tile_ok(int rec, uint32_t t);
 hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s);
-hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
+uint32_t bitonic_tile(int rec);
+hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N,
                           hipStream_t s);
 }  // namespace bos
 
@@ -109,7 +110,6 @@ using namespace bos;
 constexpr uint64_t kMaxN = 1ull << 31;
 constexpr uint32_t kMaxPasses = 32;
 constexpr uint32_t kDefaultTile = 4096;
-constexpr uint32_t kBitonicTile = 8192;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -1681,7 +1681,7 @@ bos_status bos_sort_step_async(bos_stepper* st, bos_job* jobs, uint32_t count, b
 
 size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec) {
   if (rec != 8 && rec != 16) return 0;
-  uint64_t N = kBitonicTile;
+  uint64_t N = bitonic_tile(int(rec));
   while (N < n) N <<= 1;
   return align_up(size_t(N) * rec);
 }
@@ -1694,9 +1694,9 @@ bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, 
   if (n == 0) return BOS_OK;
   if (!in || !out) return BOS_ERR_INVALID_ARG;
   if (!ws || ws_bytes < bos_bitonic_workspace_bytes(n, rec)) return BOS_ERR_WORKSPACE;
-  uint64_t N = kBitonicTile;
+  uint64_t N = bitonic_tile(int(rec));
   while (N < n) N <<= 1;
-  return hip_status(launch_bitonic(int(rec), in, out, n, ws, N, kBitonicTile, static_cast<hipStream_t>(stream)));
+  return hip_status(launch_bitonic(int(rec), in, out, n, ws, N, static_cast<hipStream_t>(stream)));
 }
 
 bos_status bos_set_tuning(const bos_tune_entry* entries, uint32_t count) {

@@ -6,8 +6,10 @@
 //    memory accesses depend on the relative order of the (randomly permuted)
 //    records only, which is what the paper's composition argument needs.
 // 2. An oblivious bitonic sort (Batcher), the baseline of the paper's Table 1,
-//    on the same records: tiles sorted in LDS, global strides fused four or
-//    five at a time in registers, the remaining strides of every merge in LDS.
+//    on the same records: tiles of 8192 (8-byte records) or 4096 records
+//    sorted by the same register network, global strides fused up to five at
+//    a time in registers, the strides of every merge below the tile in one
+//    register tile pass.
 #include "bos.h"
 #include "bos_common.h"
 #include "bos_prof.h"
@@ -17,7 +19,6 @@
 
 namespace bos {
 
-constexpr uint32_t kTileThreads = 512;
 
 // Every G-th record of a four-way merge pass's input is a sample (G = 2^kSmpLog).
 template <int R>
@@ -292,6 +293,29 @@ __device__ __forceinline__ void merge_tile_one(const void* src_, void* dst_, uin
   }
 }
 
+// Compare-exchange of a lane's 16 records (register sub-tile `sub` of 4096
+// records, lane lq) with those of sub-tile psub: lane 255 - lq, registers in
+// reverse order when `mirror` (the first stage of a merge of two ascending
+// runs), else the same lane and registers.  The lower sub-tile keeps the
+// minima.  Sub-tiles exchange through their padded LDS regions (SP slots each).
+template <typename T, uint32_t SP>
+__device__ __forceinline__ void subtile_cross(ElemR<T> (&v)[16], T* s, uint32_t sub, uint32_t lq, uint32_t psub,
+                                              bool mirror) {
+  __syncthreads();  // the LDS regions are free (the last network stage read them)
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) s[sub * SP + 17u * lq + e] = v[e].r;
+  __syncthreads();
+  const uint32_t plq = mirror ? 255u - lq : lq;
+  const bool keep_min = sub < psub;
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) {
+    const ElemR<T> p{s[psub * SP + 17u * plq + (mirror ? 15u - e : e)]};
+    const bool take = e_less(p, v[e]) == keep_min;
+    v[e] = e_sel(take, p, v[e]);
+  }
+  __syncthreads();
+}
+
 // Tiles of 2^TLOG records for TLOG = 13 or 14: 2^(TLOG - 12) register tiles of
 // 4096 records (256 lanes and one padded LDS region each) are sorted side by
 // side, then merged with the bitonic merge network: a compare-exchange across
@@ -314,25 +338,7 @@ __device__ __forceinline__ void tile_sort_big_one(void* buf, uint64_t n, uint64_
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
   bin_bitonic<12>(v, lds, sub * kSubPad, lq, true);
-  // Compare-exchange of this lane's 16 records with those of sub-tile psub:
-  // lane 255 - lq, registers in reverse order when `mirror` (the first stage of
-  // a merge of two ascending runs), else the same lane and registers.  The
-  // lower sub-tile keeps the minima.
-  auto cross = [&](uint32_t psub, bool mirror) {
-    __syncthreads();  // the LDS regions are free (the last network stage read them)
-#pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) s[sub * kSubPad + 17u * lq + e] = v[e].r;
-    __syncthreads();
-    const uint32_t plq = mirror ? 255u - lq : lq;
-    const bool keep_min = sub < psub;
-#pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) {
-      const ElemR<T> p{s[psub * kSubPad + 17u * plq + (mirror ? 15u - e : e)]};
-      const bool take = e_less(p, v[e]) == keep_min;
-      v[e] = e_sel(take, p, v[e]);
-    }
-    __syncthreads();
-  };
+  auto cross = [&](uint32_t psub, bool mirror) { subtile_cross<T, kSubPad>(v, s, sub, lq, psub, mirror); };
   // runs of 4096 -> 8192: sub-tiles 2j, 2j+1
   cross(sub ^ 1u, true);
   bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
@@ -870,45 +876,81 @@ __global__ void batch_status_kernel(unsigned long long* const* status, uint32_t*
 }
 
 // ---- bitonic baseline ------------------------------------------------------
+//
+// Batcher's bitonic sort over N = 2^m slots: the n records, then maximal
+// records up to N.  Merge phase k2 (blocks of k2 slots, ascending where bit k2
+// of the slot index is 0) runs its strides >= ts in register-fused global
+// passes and its strides < ts in one tile pass; the phases up to ts run in the
+// first tile pass.  A tile pass holds ts = 2^TLOG records in registers, 16 per
+// lane in register sub-tiles of 4096 records (the network of the comparison
+// sort's tile sort), and sorts or merges them ascending; a tile whose direction
+// is descending is stored in reverse.  That is the descending network's output,
+// since records are totally ordered and equal records are byte-identical.
 
-// Local phases: sort tiles of ts records with the global direction rule (the
-// tile's direction alternates with bit ts of its index).
-template <int R>
-__global__ __launch_bounds__(kTileThreads) void bitonic_tile_kernel(void* buf, uint32_t ts) {
+// Tile `tile` of src (slots >= n_src read as the maximal record): MERGE = false
+// sorts it (the phases up to ts), MERGE = true runs the strides ts/2 .. 1 of
+// phase k2 on the bitonic sequence it holds.  Slots below n_dst are stored to
+// dst (in place when dst == src: a workgroup reads its whole tile first).
+template <int R, uint32_t TLOG, bool MERGE>
+__device__ __forceinline__ void bitonic_tile_one(const void* src_, void* dst_, uint64_t n_src, uint64_t n_dst,
+                                                 uint64_t k2, uint64_t tile) {
   using T = typename RecOf<R>::T;
+  constexpr uint32_t kSub = 4096, kSubPad = kSub + kSub / 16, ts = 1u << TLOG;
+  static_assert(TLOG >= 12 && TLOG <= 14, "one, two or four register sub-tiles");
   extern __shared__ __align__(16) unsigned char smem[];
   T* s = reinterpret_cast<T*>(smem);
-  T* B = static_cast<T*>(buf);
-  const uint64_t base = uint64_t(blockIdx.x) * ts;
-  for (uint32_t t = threadIdx.x; t < ts; t += blockDim.x) s[lpad(t)] = B[base + t];
-  __syncthreads();
-  lds_bitonic(s, ts, 2, ts, 1, base);
-  for (uint32_t t = threadIdx.x; t < ts; t += blockDim.x) B[base + t] = s[lpad(t)];
+  const T* S = static_cast<const T*>(src_);
+  T* D = static_cast<T*>(dst_);
+  const uint32_t tid = threadIdx.x, sub = tid / 256u, lq = tid % 256u;
+  const uint64_t tbase = tile << TLOG;
+  const uint32_t p0 = sub * kSub + 16u * lq;
+  const LdsR<T> lds{s};
+  ElemR<T> v[16];
+  if constexpr (MERGE) {  // merge passes read whole tiles of the N slots
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{S[tbase + p0 + e]};
+  } else {
+    const uint64_t in_lane = n_src > tbase + p0 ? n_src - (tbase + p0) : 0;
+    const uint32_t cnt = in_lane < 16 ? uint32_t(in_lane) : 16u;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{e < cnt ? S[tbase + p0 + e] : max_rec<T>()};
+  }
+  if constexpr (!MERGE) {
+    bin_bitonic<12>(v, lds, sub * kSubPad, lq, true);
+    if constexpr (TLOG >= 13) {
+      subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 1u, true);
+      bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+    }
+    if constexpr (TLOG == 14) {
+      subtile_cross<T, kSubPad>(v, s, sub, lq, 3u - sub, true);
+      subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 1u, false);
+      bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+    }
+  } else {
+    if constexpr (TLOG == 14) subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 2u, false);
+    if constexpr (TLOG >= 13) subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 1u, false);
+    bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+  }
+  const bool desc = (tbase & k2) != 0;  // descending: slot p goes to ts - 1 - p
+  const uint64_t o = desc ? tbase + ts - 16u - p0 : tbase + p0;
+  const uint64_t out_lane = n_dst > o ? n_dst - o : 0;
+  const uint32_t cnt = out_lane < 16 ? uint32_t(out_lane) : 16u;
+  if (!desc) {
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e)
+      if (e < cnt) D[o + e] = v[e].r;
+  } else {
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e)
+      if (e < cnt) D[o + e] = v[15u - e].r;
+  }
 }
 
-// Strides j2 < ts of merge phase k2, in LDS.
-template <int R>
-__global__ __launch_bounds__(kTileThreads) void bitonic_tail_kernel(void* buf, uint32_t ts, uint64_t k2) {
-  using T = typename RecOf<R>::T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* s = reinterpret_cast<T*>(smem);
-  T* B = static_cast<T*>(buf);
-  const uint64_t base = uint64_t(blockIdx.x) * ts;
-  for (uint32_t t = threadIdx.x; t < ts; t += blockDim.x) s[lpad(t)] = B[base + t];
-  __syncthreads();
-  const uint32_t tid = threadIdx.x, nthr = blockDim.x;
-  const bool up = (base & k2) == 0;  // constant over the tile since k2 > ts
-  for (uint32_t j2 = ts >> 1; j2 > 0; j2 >>= 1) {
-    for (uint32_t p = tid; p < (ts >> 1); p += nthr) {
-      const uint32_t lo = ((p & ~(j2 - 1u)) << 1) | (p & (j2 - 1u)), hi = lo + j2;
-      const T a = s[lpad(lo)], b = s[lpad(hi)];
-      const bool sw = up ? rec_less(b, a) : rec_less(a, b);
-      s[lpad(lo)] = sel(sw, b, a);
-      s[lpad(hi)] = sel(sw, a, b);
-    }
-    __syncthreads();
-  }
-  for (uint32_t t = threadIdx.x; t < ts; t += blockDim.x) B[base + t] = s[lpad(t)];
+template <int R, uint32_t TLOG, bool MERGE>
+__global__ __launch_bounds__(tile_threads<TLOG>()) void bitonic_tile_kernel(const void* src, void* dst,
+                                                                           uint64_t n_src, uint64_t n_dst,
+                                                                           uint64_t k2) {
+  bitonic_tile_one<R, TLOG, MERGE>(src, dst, n_src, n_dst, k2, blockIdx.x);
 }
 
 // RS consecutive global strides j2 = jtop, jtop/2, ..., jtop/2^(RS-1) of merge
@@ -945,15 +987,6 @@ __global__ __launch_bounds__(256) void bitonic_global_kernel(void* buf, uint64_t
 #pragma unroll
     for (int e = 0; e < (1 << RS); ++e) B[base + uint64_t(e) * jlow] = v[e];
   }
-}
-
-template <int R>
-__global__ void pad_copy_kernel(const void* in_, void* out_, uint64_t n, uint64_t N) {
-  using T = typename RecOf<R>::T;
-  const T* in = static_cast<const T*>(in_);
-  T* out = static_cast<T*>(out_);
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += uint64_t(gridDim.x) * blockDim.x)
-    out[i] = i < n ? in[i] : max_rec<T>();
 }
 
 // ---- launchers -------------------------------------------------------------
@@ -1166,23 +1199,29 @@ hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, u
                   : comparison_sort_t<16>(buf0, buf1, n, ts, split, s, result, multiway);
 }
 
+// Tile of the bitonic baseline: 8192 records of 8 bytes or 4096 of 16, 70 KB
+// of padded LDS per workgroup (at n = 2^28 x 8 B the sort took 52.6 ms with
+// 8192-record tiles, 53.3 with 4096 and 55.9 with 16384).
+uint32_t bitonic_tile(int rec) { return rec == 8 ? 8192u : 4096u; }
+
 template <int R>
-static hipError_t bitonic_t(const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
-                            hipStream_t s) {
+static hipError_t bitonic_t(const void* in, void* out, uint64_t n, void* ws, uint64_t N, hipStream_t s) {
+  constexpr uint32_t TL = R == 8 ? 13u : 12u, ts = 1u << TL;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = allow_lds(bitonic_tile_kernel<R>);
-    if (e == hipSuccess) e = allow_lds(bitonic_tail_kernel<R>);
+    hipError_t e = allow_lds(bitonic_tile_kernel<R, TL, false>);
+    if (e == hipSuccess) e = allow_lds(bitonic_tile_kernel<R, TL, true>);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(pad_copy_kernel<R>, dim3(grid_for(N, 256, 8192)), dim3(256), 0, s, in, ws, n, N);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const uint32_t lds = tile_lds_bytes(R, ts);
+  if (N < ts || (N & (N - 1)) != 0) return hipErrorInvalidValue;
+  const uint32_t lds = tile_sort_lds<R, TL>(), threads = tile_threads<TL>(), tiles = uint32_t(N / ts);
+  hipError_t e;
   uint32_t gpass = 0, tpass = 0;
-  prof_begin(BOS_K_BITONIC_TILE, 0, 2 * N * R, s);
-  hipLaunchKernelGGL(bitonic_tile_kernel<R>, dim3(uint32_t(N / ts)), dim3(kTileThreads), lds, s, ws, ts);
+  // phases up to ts; a single tile is the whole sort
+  prof_begin(BOS_K_BITONIC_TILE, 0, uint64_t(n) * 2 * R, s);
+  hipLaunchKernelGGL((bitonic_tile_kernel<R, TL, false>), dim3(tiles), dim3(threads), lds, s, in,
+                     N == ts ? out : ws, n, N == ts ? n : N, uint64_t(ts));
   prof_end(s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (uint64_t k2 = uint64_t(ts) * 2; k2 <= N; k2 <<= 1) {
@@ -1205,12 +1244,15 @@ static hipError_t bitonic_t(const void* in, void* out, uint64_t n, void* ws, uin
       if ((e = hipGetLastError()) != hipSuccess) return e;
       j2 >>= rs;
     }
+    // strides below ts; the last phase writes the n smallest slots to out
+    const bool last = k2 == N;
     prof_begin(BOS_K_BITONIC_TAIL, tpass++, 2 * N * R, s);
-    hipLaunchKernelGGL(bitonic_tail_kernel<R>, dim3(uint32_t(N / ts)), dim3(kTileThreads), lds, s, ws, ts, k2);
+    hipLaunchKernelGGL((bitonic_tile_kernel<R, TL, true>), dim3(tiles), dim3(threads), lds, s, ws,
+                       last ? out : ws, N, last ? n : N, k2);
     prof_end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return hipMemcpyAsync(out, ws, n * R, hipMemcpyDeviceToDevice, s);
+  return hipSuccess;
 }
 
 template <int R, uint32_t TLOG>
@@ -1280,9 +1322,9 @@ hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out,
   return hipGetLastError();
 }
 
-hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N, uint32_t ts,
+hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N,
                           hipStream_t s) {
-  return rec == 8 ? bitonic_t<8>(in, out, n, ws, N, ts, s) : bitonic_t<16>(in, out, n, ws, N, ts, s);
+  return rec == 8 ? bitonic_t<8>(in, out, n, ws, N, s) : bitonic_t<16>(in, out, n, ws, N, s);
 }
 
 }  // namespace bos

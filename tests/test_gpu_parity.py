@@ -216,7 +216,8 @@ def test_sort_independent_of_seed_z_k():
         np.testing.assert_array_equal(o, cf.sorted_records(a))
 
 
-@pytest.mark.parametrize("n,rec", [(1 << 16, 8), (100000, 16), (8192, 8), (1, 16), (3, 8)])
+@pytest.mark.parametrize("n,rec", [(1 << 16, 8), (100000, 16), (8192, 8), (1, 16), (3, 8), (16385, 8), (8193, 16),
+                                   ((1 << 21) + 123, 8), (3 * (1 << 16) + 5, 16), (1 << 22, 16)])
 def test_bitonic_baseline(n, rec):
     a = _recs(n, rec, key_bits=(9 if rec == 16 else None))
     out = bos.bitonic_sort(_gpu(a))
