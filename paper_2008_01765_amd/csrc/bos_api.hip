@@ -36,7 +36,6 @@ hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsi
 constexpr uint32_t kScanChunk = 1024;  // block counts per workgroup of the strip's first scan
 hipError_t launch_comparison_sort(int rec, void* buf0, void* buf1, uint64_t n, uint32_t ts, uint64_t* split,
                                   hipStream_t s, void** result, bool multiway);
-uint32_t comparison_sort_passes(uint64_t n, uint32_t ts);
 uint32_t comparison_sort_hbm_passes(int rec, uint64_t n, uint32_t ts, bool multiway);
 size_t comparison_sort_split_bytes(uint64_t n, int rec);
 unsigned long long* comparison_sort_err_word(uint64_t* split, uint64_t n, int rec);
@@ -50,7 +49,14 @@ hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* 
                                hipStream_t s);
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s);
 bool sort_tile_ok(int rec, uint32_t t);
-hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s);
+hipError_t launch_batch_status(unsigned long long* const* status, unsigned long long* const* err, uint32_t* out,
+                               uint32_t count, hipStream_t s);
+bool merge_pass_at(int rec, uint64_t n, uint32_t ts, uint32_t p, uint64_t* w_out, bool* four, bool* next_four);
+void* first_pass_samples(int rec, uint64_t n, uint32_t ts, uint64_t* split);
+void merge4_seg(int rec, const void* src, void* dst, uint64_t n, uint64_t* split, uint64_t w, bool gather,
+                bool next_four, M4Seg* sg, uint32_t counts[5]);
+hipError_t launch_merge4_batched(int rec, const M4Seg* segs, uint32_t nsegs, const uint32_t totals[5],
+                                 hipStream_t s);
 uint32_t bitonic_tile(int rec);
 hipError_t launch_bitonic(int rec, const void* in, void* out, uint64_t n, void* ws, uint64_t N,
                           hipStream_t s);
@@ -578,6 +584,47 @@ bool has_gpu() {
 // Z values with batched routing kernels.
 bool batched_lz(uint32_t lz) { return lz == 5 || lz == 8 || lz == 9 || lz == 10; }
 
+// The comparison sort's error word and first four-way samples of a job whose
+// workspace (plan pl) starts at w.
+unsigned long long* err_word(const Plan& pl, char* w, uint64_t n) {
+  return w ? comparison_sort_err_word(reinterpret_cast<uint64_t*>(w + pl.off_split), n, pl.rec) : nullptr;
+}
+void* split_smp(const Plan& pl, char* w, uint64_t n) {
+  return w ? first_pass_samples(pl.rec, n, pl.tile, reinterpret_cast<uint64_t*>(w + pl.off_split)) : nullptr;
+}
+
+// Merge pass `pass` of several instances, launched together: two-way passes
+// as one table of SortSeg, four-way passes as one table of M4Seg.
+struct MergeRound {
+  std::vector<SortSeg> two;
+  std::vector<M4Seg> four;
+  uint32_t two_tiles = 0, m4[5] = {0, 0, 0, 0, 0};
+  void add(int rec, void* src, void* dst, uint64_t n, uint32_t tile, uint32_t pass, uint64_t* split) {
+    uint64_t w = 0;
+    bool f = false, nf = false;
+    if (!merge_pass_at(rec, n, tile, pass, &w, &f, &nf)) return;
+    if (!f) {
+      const uint32_t mt = merge_tile_records(rec);
+      const uint32_t c = uint32_t((n + mt - 1) / mt);
+      two.push_back(SortSeg{src, dst, n, w, split, two_tiles, c});
+      two_tiles += c;
+      return;
+    }
+    // the samples exist unless a two-way pass came just before
+    uint64_t pw = 0;
+    bool pf = true, pnf = false;
+    const bool gather = pass > 0 && merge_pass_at(rec, n, tile, pass - 1, &pw, &pf, &pnf) && !pf;
+    M4Seg sg;
+    uint32_t c[5];
+    merge4_seg(rec, src, dst, n, split, w, gather, nf, &sg, c);
+    for (int k = 0; k < 5; ++k) {
+      sg.first[k] = m4[k];
+      m4[k] += c[k];
+    }
+    four.push_back(sg);
+  }
+};
+
 struct BatchJob {
   const void* in = nullptr;
   void* out = nullptr;
@@ -586,17 +633,19 @@ struct BatchJob {
   char* ws = nullptr;
   void* start = nullptr;  // routing output (where the comparison sort starts)
   void* other = nullptr;
-  uint32_t merges = 0;
+  uint32_t merges = 0;     // HBM passes of the comparison sort's merge phase (two- and four-way)
   bool special = false;   // routed on its own (single bin, or a Z without batched kernels)
   bool split = false;     // last pass in split form, then the batched strip
 };
 
 struct BLaunch {
-  int kind = 0;  // 0 fill, 1 route, 2 tile sort, 3 merge pass, 4 status, 5 plain routing of one job, 6 strip
+  int kind = 0;  // 0 fill, 1 route, 2 tile sort, 3 two-way merge pass, 4 status, 5 plain routing of one job,
+                 // 6 strip, 7 four-way merge pass
   int mode = 0;  // route: bit 0 first, bit 1 last, bit 2 split last pass
   uint32_t lz = 0;    // route: log2 Z of the launch
   uint32_t tile = 0;  // tile sort: records per tile
   uint32_t nsegs = 0, blocks = 0, threads = 0, lds = 0, total = 0, job = 0;
+  uint32_t m4[5] = {0, 0, 0, 0, 0};  // four-way pass: blocks of each of its launches
   size_t tab = 0, aux = 0;
 };
 
@@ -636,7 +685,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     if (st != BOS_OK) return st;
     j.ws = ws ? ws + off : nullptr;
     off = align_up(off + j.pl.total);
-    j.merges = comparison_sort_passes(j.n, j.pl.tile);
+    j.merges = comparison_sort_hbm_passes(rec, j.n, j.pl.tile, true);
     char* tmp = j.ws ? sort_tmp(j.pl, j.ws) : nullptr;
     j.start = (j.merges % 2 == 0) ? j.out : static_cast<void*>(tmp);
     j.other = (j.merges % 2 == 0) ? static_cast<void*>(tmp) : j.out;
@@ -657,6 +706,9 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     for (const BatchJob& j : b->jobs)
       if (j.n && !j.special)
         f.push_back(FillSeg{reinterpret_cast<unsigned long long*>(j.ws + j.pl.off_status), 2 + j.pl.nblocks_last, 0});
+    // comparison-sort error words (set by a four-way tile that fails its bound checks)
+    for (const BatchJob& j : b->jobs)
+      if (j.n > 1) f.push_back(FillSeg{err_word(j.pl, j.ws, j.n), 1, 1});
     BLaunch l;
     l.kind = 0;
     l.nsegs = uint32_t(f.size());
@@ -752,7 +804,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     for (const BatchJob& j : b->jobs) {
       if (j.n <= 1 || j.pl.tile != T) continue;
       const uint32_t c = uint32_t((j.n + T - 1) / T);
-      segs.push_back(SortSeg{j.start, nullptr, j.n, 0, nullptr, tiles, c});
+      segs.push_back(SortSeg{j.start, split_smp(j.pl, j.ws, j.n), j.n, 0, nullptr, tiles, c});
       tiles += c;
     }
     BLaunch l;
@@ -763,39 +815,48 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
     l.tab = push_table(tab, segs);
     if (l.nsegs) b->launches.push_back(l);
   }
-  // 3. merge passes (runs of width tile << pass, merge tiles of
-  //    merge_tile_records(rec) outputs)
+  // 3. merge passes, pass-major: pass p of every instance that has one, as a
+  //    two-way pass (merge tiles of merge_tile_records(rec) outputs) or a
+  //    four-way pass (two merge levels)
   uint32_t maxM = 0;
   for (const BatchJob& j : b->jobs) maxM = std::max(maxM, j.merges);
   for (uint32_t pass = 0; pass < maxM; ++pass) {
-    std::vector<SortSeg> segs;
-    uint32_t tiles = 0;
+    MergeRound mr;
     for (const BatchJob& j : b->jobs) {
       if (pass >= j.merges) continue;
-      const uint32_t mt = merge_tile_records(rec);
-      const uint32_t c = uint32_t((j.n + mt - 1) / mt);
       void* src = (pass % 2 == 0) ? j.start : j.other;
       void* dst = (pass % 2 == 0) ? j.other : j.start;
-      segs.push_back(SortSeg{src, dst, j.n, uint64_t(j.pl.tile) << pass,
-                             reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), tiles, c});
-      tiles += c;
+      mr.add(rec, src, dst, j.n, j.pl.tile, pass, reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split));
     }
-    BLaunch l;
-    l.kind = 3;
-    l.nsegs = uint32_t(segs.size());
-    l.total = tiles;
-    l.tab = push_table(tab, segs);
-    b->launches.push_back(l);
+    if (!mr.two.empty()) {
+      BLaunch l;
+      l.kind = 3;
+      l.nsegs = uint32_t(mr.two.size());
+      l.total = mr.two_tiles;
+      l.tab = push_table(tab, mr.two);
+      b->launches.push_back(l);
+    }
+    if (!mr.four.empty()) {
+      BLaunch l;
+      l.kind = 7;
+      l.nsegs = uint32_t(mr.four.size());
+      std::memcpy(l.m4, mr.m4, sizeof(l.m4));
+      l.tab = push_table(tab, mr.four);
+      b->launches.push_back(l);
+    }
   }
-  // 4. per-instance status
+  // 4. per-instance status (overflow, then the comparison sort's error word)
   {
-    std::vector<unsigned long long*> st;
-    for (const BatchJob& j : b->jobs)
+    std::vector<unsigned long long*> st, er;
+    for (const BatchJob& j : b->jobs) {
       st.push_back(j.n ? reinterpret_cast<unsigned long long*>(j.ws + j.pl.off_status) : nullptr);
+      er.push_back(j.n > 1 ? err_word(j.pl, j.ws, j.n) : nullptr);
+    }
     BLaunch l;
     l.kind = 4;
     l.nsegs = count;
     l.tab = push_table(tab, st);
+    l.aux = push_table(tab, er);
     b->launches.push_back(l);
   }
   (void)dev;
@@ -827,7 +888,11 @@ hipError_t enqueue_batch(const Batch& b, char* tables, hipStream_t s, uint32_t* 
                                   s);
         break;
       case 4:
-        e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(tables + l.tab), d_status, l.nsegs, s);
+        e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(tables + l.tab),
+                                reinterpret_cast<unsigned long long* const*>(tables + l.aux), d_status, l.nsegs, s);
+        break;
+      case 7:
+        e = launch_merge4_batched(b.rec, reinterpret_cast<const M4Seg*>(tables + l.tab), l.nsegs, l.m4, s);
         break;
       case 5: {
         const BatchJob& j = b.jobs[l.job];
@@ -1198,7 +1263,9 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
     for (uint32_t i = 0; i < count; ++i) {
       const BatchJob& j = b.jobs[i];
       uint32_t att = j.n ? 1u : 0u;
-      if (hs[i] != BOS_OK) {
+      if (hs[i] != BOS_OK && hs[i] != BOS_ERR_OVERFLOW) {
+        if (worst == BOS_OK) worst = bos_status(hs[i]);  // a comparison-sort consistency check failed
+      } else if (hs[i] == BOS_ERR_OVERFLOW) {
         uint64_t ovf = kNoOverflow, prev = kNoOverflow;
         if (hipMemcpyAsync(&prev, j.ws + j.pl.off_status, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -1206,17 +1273,23 @@ bos_status bos_sort_batched(const bos_instance* inst, uint32_t count, bos_rec re
         bos_params qi = q;
         qi.seed = inst[i].seed;
         const bos_status rs = run_routing(j.pl, qi, j.in, j.start, 1, j.ws, s, &att, &ovf, 1, prev, j.split);
+        bos_status fs = rs;
         if (rs == BOS_OK) {
           void* result = nullptr;
-          if (launch_comparison_sort(j.pl.rec, j.start, j.other, j.n, j.pl.tile,
-                                     reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split), s, &result, false) != hipSuccess)
+          unsigned long long err = 0;
+          uint64_t* split = reinterpret_cast<uint64_t*>(j.ws + j.pl.off_split);
+          if (launch_comparison_sort(j.pl.rec, j.start, j.other, j.n, j.pl.tile, split, s, &result, true) !=
+                  hipSuccess ||
+              hipMemcpyAsync(&err, err_word(j.pl, j.ws, j.n), 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess)
             return BOS_ERR_HIP;
+          if (err) fs = BOS_ERR_INTERNAL;
         }
-        hs[i] = rs;
+        hs[i] = fs;
         if (hipMemcpyAsync(d_status + i, &hs[i], 4, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
           return BOS_ERR_HIP;
-        if (rs != BOS_OK && worst == BOS_OK) worst = rs;
+        if (fs != BOS_OK && worst == BOS_OK) worst = fs;
       }
       attempts += att;
       bytes += routing_bytes(j.pl) + uint64_t(2 + 2 * j.merges) * j.n * j.pl.rec;
@@ -1255,13 +1328,16 @@ constexpr uint64_t kStepBackfillCap = 1ull << 23;
 size_t step_round_bytes(uint32_t count) {
   // every job adds at most one entry of each kind; each table starts aligned
   // (fill, 2 per route group of at most 5 kinds x 8 Z, strip, 5 tile sizes,
-  // merge)
-  return size_t(count) * (sizeof(FillSeg) + sizeof(PassArgs) + 4 + sizeof(StripSeg) + 2 * sizeof(SortSeg)) +
-         90 * kAlign;
+  // two-way and four-way merge passes)
+  return size_t(count) * (2 * sizeof(FillSeg) + sizeof(PassArgs) + 4 + sizeof(StripSeg) + 2 * sizeof(SortSeg) +
+                          sizeof(M4Seg)) +
+         92 * kAlign;
 }
 
 size_t bos_step_workspace_bytes(uint32_t count) {
-  return align_up(kStepRounds * step_round_bytes(count) + size_t(count) * 12 + 4 * kAlign);
+  // the rounds' tables, then two status entries per job (routing checked, or
+  // comparison sort ended): two pointers and one result word each
+  return align_up(kStepRounds * step_round_bytes(count) + size_t(count) * 40 + 6 * kAlign);
 }
 
 }  // extern "C"
@@ -1276,7 +1352,7 @@ struct bos_stepper {
   };
   struct Finished {
     void* ws;
-    uint32_t attempt;
+    uint32_t attempt, slot;  // slot: index of its error-word check in the step's status words
   };
   struct Half {
     char* tab = nullptr;  // pinned: the step's tables
@@ -1343,7 +1419,7 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
     const bos_status st = make_plan_cached(j.n, R, q, &plans[i]);
     if (st != BOS_OK) return st;
     if (!j.ws || j.ws_bytes < plans[i].total) return BOS_ERR_WORKSPACE;
-    merges[i] = comparison_sort_passes(j.n, plans[i].tile);
+    merges[i] = comparison_sort_hbm_passes(R, j.n, plans[i].tile, true);
     if (j.phase > plans[i].P + merges[i] + (ctx ? 1u : 0u)) return BOS_ERR_INVALID_ARG;
   }
   {
@@ -1383,9 +1459,9 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
     uint32_t blocks = 0, threads = 64, lds = 0, items0 = 0;
   };
   struct Round {
-    size_t o_fill = 0, o_strip = 0, o_tile[5] = {0, 0, 0, 0, 0}, o_merge = 0;
-    uint32_t nfill = 0, nstrip = 0, ntile[5] = {0, 0, 0, 0, 0}, nmerge = 0;
-    uint32_t sblocks = 0, tiles[5] = {0, 0, 0, 0, 0}, mtiles = 0;
+    size_t o_fill = 0, o_strip = 0, o_tile[5] = {0, 0, 0, 0, 0}, o_merge = 0, o_m4 = 0;
+    uint32_t nfill = 0, nstrip = 0, ntile[5] = {0, 0, 0, 0, 0}, nmerge = 0, nm4 = 0;
+    uint32_t sblocks = 0, tiles[5] = {0, 0, 0, 0, 0}, mtiles = 0, m4[5] = {0, 0, 0, 0, 0};
     std::map<uint32_t, RouteGroup> route;  // key: mode * 16 + lz
     std::vector<uint32_t> whole;  // jobs routed by the per-job path in this round
   };
@@ -1398,15 +1474,16 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
   // pending until the step has run (pipelined)
   std::vector<uint32_t> finished;
   auto finish = [&](uint32_t i) -> uint32_t {
-    if (!ctx) return BOS_PHASE_DONE;
     finished.push_back(i);
+    if (!ctx) return BOS_PHASE_DONE;
     return after_last_phase(plans[i], merges[i]);
   };
   for (uint32_t r = 0; r < kStepRounds; ++r) {
     Round rd;
     std::vector<FillSeg> fills;
     std::vector<StripSeg> strips;
-    std::vector<SortSeg> tiles[5], mseg;
+    std::vector<SortSeg> tiles[5];
+    MergeRound mr;
     bool any = false;
     for (uint32_t i = 0; i < count; ++i) {
       if (phase[i] == BOS_PHASE_DONE || allowed[i] <= r) continue;
@@ -1474,19 +1551,16 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
         const uint32_t T = pl.tile;
         const uint32_t c = uint32_t((j.n + T - 1) / T);
         if (j.n > 1) {
-          tiles[ti].push_back(SortSeg{start_buf(i), nullptr, j.n, 0, nullptr, rd.tiles[ti], c});
+          tiles[ti].push_back(SortSeg{start_buf(i), split_smp(pl, w, j.n), j.n, 0, nullptr, rd.tiles[ti], c});
           rd.tiles[ti] += c;
+          fills.push_back(FillSeg{err_word(pl, w, j.n), 1, 1});  // before this round's tile sorts
         }
         phase[i] = merges[i] == 0 ? finish(i) : pl.P + 1;
       } else {
         const uint32_t pass = ph - (pl.P + 1);
-        const uint32_t mt = merge_tile_records(R);
-        const uint32_t c = uint32_t((j.n + mt - 1) / mt);
         void* src = (pass % 2 == 0) ? start_buf(i) : other_buf(i);
         void* dst = (pass % 2 == 0) ? other_buf(i) : start_buf(i);
-        mseg.push_back(SortSeg{src, dst, j.n, uint64_t(pl.tile) << pass, reinterpret_cast<uint64_t*>(w + pl.off_split),
-                               rd.mtiles, c});
-        rd.mtiles += c;
+        mr.add(R, src, dst, j.n, pl.tile, pass, reinterpret_cast<uint64_t*>(w + pl.off_split));
         phase[i] = pass + 1 >= merges[i] ? finish(i) : ph + 1;
       }
     }
@@ -1503,19 +1577,31 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
       rd.ntile[ti] = uint32_t(tiles[ti].size());
       rd.o_tile[ti] = push_table(tab, tiles[ti]);
     }
-    rd.nmerge = uint32_t(mseg.size());
-    rd.o_merge = push_table(tab, mseg);
+    rd.nmerge = uint32_t(mr.two.size());
+    rd.mtiles = mr.two_tiles;
+    rd.o_merge = push_table(tab, mr.two);
+    rd.nm4 = uint32_t(mr.four.size());
+    std::memcpy(rd.m4, mr.m4, sizeof(rd.m4));
+    rd.o_m4 = push_table(tab, mr.four);
     rounds.push_back(std::move(rd));
   }
-  // status pointers of the jobs whose routing finished in this step
-  std::vector<unsigned long long*> st_ptr;
+  // status checks: the overflow word of every job whose routing finished in
+  // this step (entries 0 .. st_job.size() - 1), then the comparison sort's
+  // error word of every job that ended in it
+  std::vector<unsigned long long*> st_ptr, er_ptr;
   std::vector<uint32_t> st_job;
   for (uint32_t i = 0; i < count; ++i)
     if (routed[i]) {
       st_ptr.push_back(reinterpret_cast<unsigned long long*>(static_cast<char*>(jobs[i].ws) + plans[i].off_status));
+      er_ptr.push_back(nullptr);
       st_job.push_back(i);
     }
+  for (uint32_t i : finished) {
+    st_ptr.push_back(nullptr);
+    er_ptr.push_back(jobs[i].n > 1 ? err_word(plans[i], static_cast<char*>(jobs[i].ws), jobs[i].n) : nullptr);
+  }
   const size_t o_stp = push_table(tab, st_ptr);
+  const size_t o_erp = push_table(tab, er_ptr);
   const size_t o_sto = align_up(tab.size());
   if (o_sto + align_up(st_ptr.size() * 4) > step_ws_bytes) return BOS_ERR_WORKSPACE;
   char* dtab = static_cast<char*>(step_ws);
@@ -1565,14 +1651,17 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
       if (e == hipSuccess)
         e = launch_sort_batched(R, 2, 0, reinterpret_cast<const SortSeg*>(dtab + rd.o_merge), rd.nmerge, rd.mtiles, s);
     }
+    if (e == hipSuccess && rd.nm4)
+      e = launch_merge4_batched(R, reinterpret_cast<const M4Seg*>(dtab + rd.o_m4), rd.nm4, rd.m4, s);
   }
   uint32_t* st_host_ptr = nullptr;
   std::vector<uint32_t> st_host(ctx ? 0 : st_ptr.size(), 0);
   if (e == hipSuccess && !st_ptr.empty()) {
     uint32_t* d_out = reinterpret_cast<uint32_t*>(dtab + o_sto);
     st_host_ptr = hf ? hf->st : st_host.data();
-    e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(dtab + o_stp), d_out,
-                            uint32_t(st_ptr.size()), s);
+    e = launch_batch_status(reinterpret_cast<unsigned long long* const*>(dtab + o_stp),
+                            reinterpret_cast<unsigned long long* const*>(dtab + o_erp), d_out, uint32_t(st_ptr.size()),
+                            s);
     if (e == hipSuccess) e = hipMemcpyAsync(st_host_ptr, d_out, st_ptr.size() * 4, hipMemcpyDeviceToHost, s);
   }
   auto overflowed = [&](bos_job& j) {
@@ -1596,6 +1685,11 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
     }
     for (size_t t = 0; t < st_job.size(); ++t)
       if (st_host[t] != 0) overflowed(jobs[st_job[t]]);
+    for (size_t t = 0; t < finished.size(); ++t) {
+      bos_job& j = jobs[finished[t]];
+      if (j.phase == BOS_PHASE_DONE && j.status == BOS_OK && st_host[st_job.size() + t] != 0)
+        j.status = BOS_ERR_INTERNAL;  // a four-way tile failed its bound checks
+    }
     return BOS_OK;
   }
   // Pipelined: this step stays in flight; the previous one is waited for and
@@ -1629,7 +1723,7 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
       bos_job& j = jobs[it->second];
       if (j.phase == BOS_PHASE_DONE || j.attempt != f.attempt || j.reserved != 1) continue;
       j.phase = BOS_PHASE_DONE;
-      j.status = BOS_OK;
+      j.status = prev.st[f.slot] != 0 ? BOS_ERR_INTERNAL : BOS_OK;
     }
     prev.routed.clear();
     prev.finished.clear();
@@ -1638,7 +1732,8 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
   hf->finished.clear();
   for (size_t t = 0; t < st_job.size(); ++t)
     hf->routed.push_back({jobs[st_job[t]].ws, jobs[st_job[t]].attempt, uint32_t(t)});
-  for (uint32_t i : finished) hf->finished.push_back({jobs[i].ws, jobs[i].attempt});
+  for (size_t t = 0; t < finished.size(); ++t)
+    hf->finished.push_back({jobs[finished[t]].ws, jobs[finished[t]].attempt, uint32_t(st_job.size() + t)});
   ctx->pending = enqueued;
   ++ctx->calls;
   return BOS_OK;

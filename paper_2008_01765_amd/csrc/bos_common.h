@@ -112,12 +112,29 @@ struct PassArgs {
 // One instance of a batched comparison-sort launch (tile sort or merge pass).
 struct SortSeg {
   void* src;         // tile sort: the buffer sorted in place; merge pass: source runs
-  void* dst;         // merge pass: destination
+  void* dst;         // merge pass: destination; tile sort: the first four-way pass's samples (or null)
   uint64_t n;        // records of the instance
   uint64_t w;        // merge pass: run width
   uint64_t* split;   // merge pass: this instance's split array
   uint32_t first;    // first block (and first partition thread) of the segment in the launch
   uint32_t count;    // blocks of the instance in the launch (tiles of the tile sort or merge)
+};
+
+// One instance of a batched four-way merge pass (two merge levels in one HBM
+// pass).  Launch k of the pass (0 sample gather, 1 per-sample ranks,
+// 2 workgroup-wide ranks, 3 tile starts, 4 tile merges) gives the instance
+// its blocks first[k] .. first[k] + count - 1 (count 0: not in that launch).
+struct M4Seg {
+  const void* src;            // runs of width 2^lw
+  void* dst;
+  void* smp;                  // samples of src (every 2^kSmpLog-th record)
+  void* next_smp;             // the next pass's samples, written by the tiles (null: none)
+  uint64_t* spl;              // sample ranks, then tile starts
+  unsigned long long* err;    // the instance's comparison-sort error word
+  uint64_t n, ntf, ng, ntl, total;  // records; tiles per full group, groups, tiles of the last group, all tiles
+  uint32_t lw, pad;
+  uint32_t first[5];
+  uint32_t pad2;
 };
 
 // One instance of a batched scan + strip after a split last pass.
@@ -150,9 +167,9 @@ struct FinishArgs {
 
 // One instance's status words to initialise before its first routing pass.
 struct FillSeg {
-  unsigned long long* p;  // status word, ticket, look-back words
+  unsigned long long* p;  // status word, ticket, look-back words (or an error word)
   uint32_t count;
-  uint32_t pad;
+  uint32_t zero_first;    // 1: p[0] = 0 too (an error word), else p[0] = no overflow
 };
 
 // ---- address digests (test build) ------------------------------------------

@@ -15,6 +15,7 @@
 #include "bos_prof.h"
 #include "route_impl.h"
 
+#include <cstring>
 #include <utility>
 
 namespace bos {
@@ -134,7 +135,7 @@ template <int R, uint32_t TLOG>
 __global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_reg_kernel_b(const SortSeg* segs,
                                                                               uint32_t nsegs) {
   const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
-  tile_sort_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first, nullptr);
+  tile_sort_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first, sg.dst);
 }
 
 // Merge tiles: kMTile outputs per workgroup of 256 threads, kMItems per thread
@@ -364,7 +365,7 @@ template <int R, uint32_t TLOG>
 __global__ __launch_bounds__(tile_threads<TLOG>()) void tile_sort_big_kernel_b(const SortSeg* segs,
                                                                               uint32_t nsegs) {
   const SortSeg sg = segs[find_seg(segs, nsegs, blockIdx.x)];
-  tile_sort_big_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first, nullptr);
+  tile_sort_big_one<R, TLOG>(sg.src, sg.n, blockIdx.x - sg.first, sg.dst);
 }
 
 template <int R>
@@ -413,13 +414,17 @@ __device__ __forceinline__ bool precedes(T x, uint32_t kx, T e, uint32_t ke) {
 // Samples of a four-way pass's input, smp[i] = src[i*G], when a two-way pass
 // produced it (the tile sort and the four-way tile kernel write their own).
 template <int R>
-__global__ void sample_gather_kernel(const void* src_, void* smp_, uint64_t n) {
+__device__ __forceinline__ void sample_gather_one(const void* src_, void* smp_, uint64_t n, uint64_t blk) {
   using T = typename RecOf<R>::T;
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t i = blk * blockDim.x + threadIdx.x;
   if (i < ((n + (1ull << kSmpLog<R>) - 1) >> kSmpLog<R>)) {
     BOS_TR(1, 41, i);
     static_cast<T*>(smp_)[i] = static_cast<const T*>(src_)[i << kSmpLog<R>];
   }
+}
+template <int R>
+__global__ void sample_gather_kernel(const void* src_, void* smp_, uint64_t n) {
+  sample_gather_one<R>(src_, smp_, n, blockIdx.x);
 }
 
 // Ranks of the samples in their group, kSplS<R> samples per thread with all
@@ -431,13 +436,14 @@ template <int R>
 constexpr uint32_t kSplS = R == 8 ? 4u : 2u;  // (more would spill registers)
 constexpr uint64_t kSplOwn = 1ull << 63;
 template <int R>
-__global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf, uint64_t* spl) {
+__device__ __forceinline__ void merge4_rank_one(const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf,
+                                                uint64_t* spl, uint64_t blk) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t LG = kSmpLog<R>;
   constexpr uint64_t G = 1ull << LG;
   const T* smp = static_cast<const T*>(smp_);
   const uint64_t ns = (n + G - 1) >> LG, w = 1ull << lw;
-  const uint64_t i0 = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) * kSplS<R>;
+  const uint64_t i0 = (blk * blockDim.x + threadIdx.x) * kSplS<R>;
   if (i0 >= ns) return;
   T e[kSplS<R>];
   uint32_t j[kSplS<R>], own[kSplS<R>], c[kSplS<R>][4], cl[kSplS<R>][4], rb[kSplS<R>][4];
@@ -492,6 +498,11 @@ __global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, ui
   }
 }
 
+template <int R>
+__global__ void merge4_rank_kernel(const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf, uint64_t* spl) {
+  merge4_rank_one<R>(smp_, n, lw, ntf, spl, blockIdx.x);
+}
+
 // The same ranks when a workgroup's kSplW<R> samples lie in one run (the
 // sample runs hold at least kSplW<R> samples).  One wave finds, for each other
 // run k, how many of its samples precede the workgroup's first and last sample
@@ -503,8 +514,8 @@ constexpr uint32_t kSplW = 256u * kSplS<R>;
 template <int R>
 constexpr uint32_t kSplCap = R == 8 ? 2048u : 1024u;
 template <int R>
-__global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_, uint64_t n, uint32_t lw,
-                                                               uint64_t ntf, uint64_t* spl) {
+__device__ __forceinline__ void merge4_rank_wide_one(const void* smp_, uint64_t n, uint32_t lw, uint64_t ntf,
+                                                     uint64_t* spl, uint64_t blk) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t LG = kSmpLog<R>, CAP = kSplCap<R>;
   constexpr uint64_t G = 1ull << LG;
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
   __shared__ uint32_t wlo[4], wlen[4];
   const T* smp = static_cast<const T*>(smp_);
   const uint64_t ns = (n + G - 1) >> LG, w = 1ull << lw;
-  const uint64_t base = uint64_t(blockIdx.x) * kSplW<R>;
+  const uint64_t base = blk * kSplW<R>;
   const uint64_t last = (base + kSplW<R> < ns ? base + kSplW<R> : ns) - 1;
   const uint64_t p0 = base << LG, g = p0 >> (lw + 2), gs = g << (lw + 2);
   const uint32_t j = uint32_t(p0 >> lw) & 3u;
@@ -624,17 +635,23 @@ __global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_,
   }
 }
 
+template <int R>
+__global__ __launch_bounds__(256) void merge4_rank_wide_kernel(const void* smp_, uint64_t n, uint32_t lw,
+                                                               uint64_t ntf, uint64_t* spl) {
+  merge4_rank_wide_one<R>(smp_, n, lw, ntf, spl, blockIdx.x);
+}
+
 // One thread per tile: the tile's exact start in each run.  Samples c-1 and
 // c of run k bracket the opening sample e, so the search covers the records
 // between them; the three searches advance together.
 template <int R>
-__global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t n, uint32_t lw, uint64_t total,
-                                    uint64_t* spl) {
+__device__ __forceinline__ void merge4_bound_one(const void* src_, const void* smp_, uint64_t n, uint32_t lw,
+                                                 uint64_t total, uint64_t* spl, uint64_t blk) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t LG = kSmpLog<R>;
   constexpr uint64_t G = 1ull << LG;
   const T* src = static_cast<const T*>(src_);
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t t = blk * blockDim.x + threadIdx.x;
   if (t >= total) return;
   uint64_t wd[4];
   uint32_t j = 0, owners = 0;
@@ -690,6 +707,12 @@ __global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t
   BOS_TR(1, 50, 4 * t);
 #pragma unroll
   for (uint32_t k = 0; k < 4; ++k) spl[4 * t + k] = st[k] + lb[k];
+}
+
+template <int R>
+__global__ void merge4_bound_kernel(const void* src_, const void* smp_, uint64_t n, uint32_t lw, uint64_t total,
+                                    uint64_t* spl) {
+  merge4_bound_one<R>(src_, smp_, n, lw, total, spl, blockIdx.x);
 }
 
 // ITEMS outputs, from output dd on, of the merge of A (na records at slot
@@ -840,6 +863,48 @@ __global__ __launch_bounds__(kM4Threads<R>) void merge4_tile_kernel(const void* 
   merge4_tile_one<R>(src, dst, n, lw, spl, ntf, ng, ntl, smp, blockIdx.x, err);
 }
 
+// Batched four-way passes: one table entry (M4Seg) per instance; launch k
+// (0 gather, 1 per-sample ranks, 2 workgroup-wide ranks, 3 tile starts,
+// 4 tiles) gives the instance blocks first[k] .. first[k] + count[k] - 1.
+__device__ __forceinline__ uint32_t m4_find(const M4Seg* segs, uint32_t nsegs, uint32_t x, uint32_t k) {
+  uint32_t lo = 0, hi = nsegs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segs[mid].first[k] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int R>
+__global__ void sample_gather_kernel_b(const M4Seg* segs, uint32_t nsegs) {
+  const M4Seg& sg = segs[m4_find(segs, nsegs, blockIdx.x, 0)];
+  sample_gather_one<R>(sg.src, sg.smp, sg.n, blockIdx.x - sg.first[0]);
+}
+template <int R>
+__global__ void merge4_rank_kernel_b(const M4Seg* segs, uint32_t nsegs) {
+  const M4Seg& sg = segs[m4_find(segs, nsegs, blockIdx.x, 1)];
+  merge4_rank_one<R>(sg.smp, sg.n, sg.lw, sg.ntf, sg.spl, blockIdx.x - sg.first[1]);
+}
+template <int R>
+__global__ __launch_bounds__(256) void merge4_rank_wide_kernel_b(const M4Seg* segs, uint32_t nsegs) {
+  const M4Seg& sg = segs[m4_find(segs, nsegs, blockIdx.x, 2)];
+  merge4_rank_wide_one<R>(sg.smp, sg.n, sg.lw, sg.ntf, sg.spl, blockIdx.x - sg.first[2]);
+}
+template <int R>
+__global__ void merge4_bound_kernel_b(const M4Seg* segs, uint32_t nsegs) {
+  const M4Seg& sg = segs[m4_find(segs, nsegs, blockIdx.x, 3)];
+  merge4_bound_one<R>(sg.src, sg.smp, sg.n, sg.lw, sg.total, sg.spl, blockIdx.x - sg.first[3]);
+}
+template <int R>
+__global__ __launch_bounds__(kM4Threads<R>) void merge4_tile_kernel_b(const M4Seg* segs, uint32_t nsegs) {
+  const M4Seg& sg = segs[m4_find(segs, nsegs, blockIdx.x, 4)];
+  merge4_tile_one<R>(sg.src, sg.dst, sg.n, sg.lw, sg.spl, sg.ntf, sg.ng, sg.ntl, sg.next_smp,
+                     blockIdx.x - sg.first[4], sg.err);
+}
+
 // Tiles of a four-way pass over runs of width 2^lw: per full group (ntf), in
 // the last group (ntl), the group count (ng) and the total.
 struct Merge4Tiles {
@@ -866,13 +931,20 @@ static Merge4Tiles merge4_tiles(int rec, uint64_t n, uint32_t lw) {
 __global__ void fill_status_kernel_b(const FillSeg* segs, uint32_t nsegs) {
   if (blockIdx.x >= nsegs) return;
   const FillSeg sg = segs[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < sg.count; i += blockDim.x) sg.p[i] = i == 0 ? kNoOverflow : 0ull;
+  for (uint32_t i = threadIdx.x; i < sg.count; i += blockDim.x)
+    sg.p[i] = i == 0 && !sg.zero_first ? kNoOverflow : 0ull;
 }
 
-// Per-instance outcome of a batch: BOS_OK (0) or BOS_ERR_OVERFLOW (2).
-__global__ void batch_status_kernel(unsigned long long* const* status, uint32_t* out, uint32_t count) {
+// Per-instance outcome of a batch: BOS_ERR_OVERFLOW (2) when its status word
+// shows an overflow, else BOS_ERR_INTERNAL (7) when its comparison-sort error
+// word is set, else BOS_OK (0); a null pointer skips that check.
+__global__ void batch_status_kernel(unsigned long long* const* status, unsigned long long* const* err, uint32_t* out,
+                                    uint32_t count) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) out[i] = (status[i] == nullptr || *status[i] == kNoOverflow) ? 0u : 2u;
+  if (i >= count) return;
+  const bool ovf = status[i] != nullptr && *status[i] != kNoOverflow;
+  const bool bad = err != nullptr && err[i] != nullptr && *err[i] != 0ull;
+  out[i] = ovf ? 2u : bad ? 7u : 0u;
 }
 
 // ---- bitonic baseline ------------------------------------------------------
@@ -1161,14 +1233,6 @@ static hipError_t comparison_sort_t(void* buf0, void* buf1, uint64_t n, uint32_t
   return hipSuccess;
 }
 
-// Number of merge passes the comparison sort runs for n records and tile ts.
-uint32_t comparison_sort_passes(uint64_t n, uint32_t ts) {
-  uint32_t c = 0;
-  if (n <= 1) return 0;
-  for (uint64_t w = ts; w < n; w *= 2) ++c;
-  return c;
-}
-
 // HBM passes of the comparison sort with four-way passes (multiway) or
 // two-way passes only.
 uint32_t comparison_sort_hbm_passes(int rec, uint64_t n, uint32_t ts, bool multiway) {
@@ -1189,6 +1253,93 @@ unsigned long long* comparison_sort_err_word(uint64_t* split, uint64_t n, int re
   char* region = reinterpret_cast<char*>(split);
   return reinterpret_cast<unsigned long long*>(region + align256(split2_bytes(n)) + align256(sample_bytes(rec, n)) +
                                                align256(spl4_bytes(rec, n)));
+}
+
+// Merge pass p (0-based) of the comparison sort of n records after tiles of
+// ts (with four-way passes where they apply): its input run width, whether it
+// is four-way, and whether the pass after it is.  False when p is past the
+// last pass.
+bool merge_pass_at(int rec, uint64_t n, uint32_t ts, uint32_t p, uint64_t* w_out, bool* four, bool* next_four) {
+  if (n <= 1) return false;
+  uint64_t w = ts;
+  for (uint32_t c = 0; w < n; ++c) {
+    const bool f = four_way_next(rec, n, w);
+    if (c == p) {
+      *w_out = w;
+      *four = f;
+      *next_four = f && four_way_next(rec, n, w << 2);
+      return true;
+    }
+    w <<= f ? 2 : 1;
+  }
+  return false;
+}
+
+// Samples of the first merge pass, when it is four-way (the tile sort writes
+// them), else null.
+void* first_pass_samples(int rec, uint64_t n, uint32_t ts, uint64_t* split) {
+  if (n <= 1 || ts >= n || !four_way_next(rec, n, ts)) return nullptr;
+  return reinterpret_cast<char*>(split) + align256(split2_bytes(n));
+}
+
+// Table entry of one instance in a batched four-way pass over runs of width w
+// whose samples are already written (gather = false: by the tile sort or the
+// previous four-way pass) or not; counts[k] = its blocks in launch k.
+void merge4_seg(int rec, const void* src, void* dst, uint64_t n, uint64_t* split, uint64_t w, bool gather,
+                bool next_four, M4Seg* sg, uint32_t counts[5]) {
+  char* region = reinterpret_cast<char*>(split);
+  uint32_t lw = 0;
+  while ((1ull << lw) < w) ++lw;
+  const Merge4Tiles t = merge4_tiles(rec, n, lw);
+  const uint32_t lg = rec == 8 ? kSmpLog<8> : kSmpLog<16>;
+  const uint64_t nsmp = (n + (1ull << lg) - 1) >> lg;
+  const uint32_t sw = rec == 8 ? kSplW<8> : kSplW<16>, ss = rec == 8 ? kSplS<8> : kSplS<16>;
+  std::memset(sg, 0, sizeof(*sg));
+  sg->src = src;
+  sg->dst = dst;
+  sg->smp = region + align256(split2_bytes(n));
+  sg->next_smp = next_four ? sg->smp : nullptr;
+  sg->spl = reinterpret_cast<uint64_t*>(region + align256(split2_bytes(n)) + align256(sample_bytes(rec, n)));
+  sg->err = comparison_sort_err_word(split, n, rec);
+  sg->n = n;
+  sg->ntf = t.ntf;
+  sg->ng = t.ng;
+  sg->ntl = t.ntl;
+  sg->total = t.total;
+  sg->lw = lw;
+  const bool wide = (w >> lg) >= sw;
+  counts[0] = gather ? uint32_t((nsmp + 255) / 256) : 0u;
+  counts[1] = wide ? 0u : uint32_t(((nsmp + ss - 1) / ss + 255) / 256);
+  counts[2] = wide ? uint32_t((nsmp + sw - 1) / sw) : 0u;
+  counts[3] = uint32_t((t.total + 255) / 256);
+  counts[4] = uint32_t(t.total);
+}
+
+template <int R>
+static hipError_t merge4_batched_t(const M4Seg* segs, uint32_t nsegs, const uint32_t totals[5], hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = allow_lds(merge4_tile_kernel_b<R>);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  if (nsegs == 0) return hipSuccess;
+  if (totals[0]) hipLaunchKernelGGL(sample_gather_kernel_b<R>, dim3(totals[0]), dim3(256), 0, s, segs, nsegs);
+  if (totals[1]) hipLaunchKernelGGL(merge4_rank_kernel_b<R>, dim3(totals[1]), dim3(256), 0, s, segs, nsegs);
+  if (totals[2]) hipLaunchKernelGGL(merge4_rank_wide_kernel_b<R>, dim3(totals[2]), dim3(256), 0, s, segs, nsegs);
+  if (totals[3]) hipLaunchKernelGGL(merge4_bound_kernel_b<R>, dim3(totals[3]), dim3(256), 0, s, segs, nsegs);
+  const uint32_t lds = (kMTile<R> + (kMTile<R> >> 4)) * uint32_t(R);
+  if (totals[4])
+    hipLaunchKernelGGL(merge4_tile_kernel_b<R>, dim3(totals[4]), dim3(kM4Threads<R>), lds, s, segs, nsegs);
+  return hipGetLastError();
+}
+
+// One batched four-way pass over the instances of segs (totals[k]: blocks of
+// launch k summed over them).
+hipError_t launch_merge4_batched(int rec, const M4Seg* segs, uint32_t nsegs, const uint32_t totals[5],
+                                 hipStream_t s) {
+  BOS_TRACE_BIND();
+  return rec == 8 ? merge4_batched_t<8>(segs, nsegs, totals, s) : merge4_batched_t<16>(segs, nsegs, totals, s);
 }
 
 // multiway: four-way passes where they apply (split must then hold
@@ -1316,9 +1467,10 @@ hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_batch_status(unsigned long long* const* status, uint32_t* out, uint32_t count, hipStream_t s) {
+hipError_t launch_batch_status(unsigned long long* const* status, unsigned long long* const* err, uint32_t* out,
+                               uint32_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_status_kernel, dim3((count + 255) / 256), dim3(256), 0, s, status, out, count);
+  hipLaunchKernelGGL(batch_status_kernel, dim3((count + 255) / 256), dim3(256), 0, s, status, err, out, count);
   return hipGetLastError();
 }
 

@@ -112,8 +112,9 @@ class Server:
     """Continuous-batching server of bucket oblivious sorts on one device.
 
     hbm_budget_bytes bounds the sum of the resident requests' footprints;
-    z, k, max_retries and min_security_bits are shared by every request (the
-    step entry point takes one parameter block).  All requests must use the
+    z, k, tile (the comparison sort's tile), max_retries and min_security_bits
+    are shared by every request (the step entry point takes one parameter
+    block; 0 = the tuning table's choice per request size).  All requests must use the
     same record type.  pipeline=True drives the steps through a stepper
     (bos_sort_step_async): the device runs one step while the host plans the
     next, and a request is reported finished one call after its last step
@@ -127,12 +128,12 @@ class Server:
     """
 
     def __init__(self, hbm_budget_bytes=64 << 30, z=0, k=0, max_retries=3, min_security_bits=80,
-                 device=None, stream=None, clock=time.perf_counter, pipeline=True):
+                 device=None, stream=None, clock=time.perf_counter, pipeline=True, tile=0):
         self.budget = int(hbm_budget_bytes)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
         self.clock = clock
-        self.params = bos.params(0, z, k, 0, max_retries, min_security_bits, sync=True)
+        self.params = bos.params(0, z, k, tile, max_retries, min_security_bits, sync=True)
         self.rec = None
         self.queue = deque()
         self.active = []

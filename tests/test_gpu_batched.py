@@ -39,6 +39,26 @@ def test_batched_equals_alone_and_oracle(rec, z):
         np.testing.assert_array_equal(got, alone)
 
 
+@pytest.mark.parametrize("rec,tile", [(8, 1024), (16, 2048), (8, 4096)])
+def test_batched_four_way_passes(rec, tile):
+    # Merge phases that start with a four-way pass (even level counts), that
+    # start with a two-way pass (odd counts: the four-way samples are then
+    # gathered), that never reach a merge tile, with runs wide enough for the
+    # workgroup-wide rank kernel, ragged tails, and instances with no merge
+    # pass: every instance equals the same instance sorted alone and numpy's
+    # sort.
+    sizes = [1 << 18, 300000, 5000, 70001, 4 * tile + 3, 1, 0, tile, 1 << 16, 2 * tile + 1]
+    hosts = _batch(sizes, rec, 77)
+    seeds = [300 + i for i in range(len(hosts))]
+    outs = bos.sort_batched([bos.from_numpy(h) for h in hosts], seeds, tile=tile)
+    for h, o, s in zip(hosts, outs, seeds):
+        got = bos.to_numpy(o)
+        np.testing.assert_array_equal(got, cf.sorted_records(h))
+        if len(h):
+            alone = bos.to_numpy(bos.sort(bos.from_numpy(h), seed=s, tile=tile))
+            np.testing.assert_array_equal(got, alone)
+
+
 def test_graph_replays_with_new_inputs():
     sizes = [5000, 20000, 777, 1 << 14]
     for rnd in range(3):

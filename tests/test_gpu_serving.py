@@ -48,6 +48,30 @@ def test_mix_equals_alone(rec, z, pipeline):
     assert srv.used == 0
 
 
+@pytest.mark.parametrize("rec,tile,pipeline", [(8, 1024, True), (16, 2048, False), (16, 1024, True)])
+def test_mix_four_way_merge_phases(rec, tile, pipeline):
+    # Jobs whose merge phases are four-way passes from the start, two-way then
+    # four-way, or two-way only, admitted while others run: each equals the
+    # request sorted alone.
+    sizes = [1 << 18, 300000, 5000, 70001, 4 * tile + 3, 1 << 16, 2 * tile + 1, 1]
+    hosts = _hosts(sizes, rec, 520)
+    srv = serving.Server(hbm_budget_bytes=1 << 34, z=512, tile=tile, pipeline=pipeline)
+    ts = [bos.from_numpy(h) for h in hosts]
+    futs = []
+    for i, t in enumerate(ts):
+        futs.append(srv.submit(t, seed=90 + i))
+        if i % 2 == 1:
+            srv.step()
+    srv.run_until_idle()
+    for h, t, f in zip(hosts, ts, futs):
+        assert f.status == bos.OK
+        got = bos.to_numpy(f.result())
+        np.testing.assert_array_equal(got, cf.sorted_records(h))
+        alone = bos.to_numpy(bos.sort(t, seed=f.seed, z=512, tile=tile))
+        np.testing.assert_array_equal(got, alone)
+    assert srv.used == 0
+
+
 @pytest.mark.parametrize("pipeline", [True, False])
 def test_side_stream_server(pipeline):
     # The server runs on a stream of its own: inputs produced on the caller's
