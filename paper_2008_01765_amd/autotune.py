@@ -93,6 +93,16 @@ class Workload:
             bos.release_workspaces()
         return dt / (self.count * self.n)
 
+    def seconds_or_inf(self, z, k, tile, reps=3):
+        """seconds_per_record, or infinity for a combination the kernels do not
+        cover (e.g. a block of 2^k Z slots beyond a workgroup's LDS)."""
+        try:
+            return self.seconds_per_record(z, k, tile, reps)
+        except bos.BosError as e:
+            if e.status != bos.UNSUPPORTED:
+                raise
+            return math.inf
+
 
 def tune(classes_by_rec=None, min_security_bits=80, reps=3, log=print):
     """Run the search; returns the table (a list of entries)."""
@@ -106,9 +116,9 @@ def tune(classes_by_rec=None, min_security_bits=80, reps=3, log=print):
                 continue
             t0 = time.perf_counter()
             w = Workload(rec, c)
-            zk = [((z, k), w.seconds_per_record(z, k, 4096, reps)) for z in zs for k in K_CANDIDATES]
+            zk = [((z, k), w.seconds_or_inf(z, k, 4096, reps)) for z in zs for k in K_CANDIDATES]
             z, k = best(zk)
-            tl = [(t, w.seconds_per_record(z, k, t, reps)) for t in tile_candidates(rec)]
+            tl = [(t, w.seconds_or_inf(z, k, t, reps)) for t in tile_candidates(rec)]
             tile = best(tl)
             ns = min(v for _, v in tl) * 1e9
             entry = {"rec": rec, "log2n": c, "z": z, "k": k, "tile": tile, "ns_per_record": round(ns, 4),
