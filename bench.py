@@ -59,6 +59,10 @@ def parse():
                     help="ORP seeds per Z for the overflow-retry count")
     ap.add_argument("--dup-steps", type=int, default=10,
                     help="steps of the duplicate-heavy 2^24 x 16 B leg (bucket and bitonic sort); 0 skips it")
+    ap.add_argument("--ooc-steps", type=int, default=1,
+                    help="timed calls of the out-of-core ORP and sort (headline workload in host memory); 0 skips")
+    ap.add_argument("--ooc-dev-gib", type=float, default=2.0,
+                    help="device workspace of the out-of-core calls, GiB")
     ap.add_argument("--tuning", default="",
                     help="tuning table for the batched and serving legs (default: the stored table)")
     return ap.parse_args()
@@ -198,6 +202,73 @@ def bench_dup(args, torch, bos, inputs):
     res["speedup_of_bucket_sort"] = round(bms / best, 3)
     res["equal_output"] = bool(torch.equal(out, bout))
     del x, out, bout
+    bos.release_workspaces()
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_ooc(args, torch, bos, inputs):
+    """Out-of-core bucket ORP and sort (Section 4.3) of the headline workload
+    held in pinned host memory, streamed through a device workspace of
+    `ooc_dev_gib` GiB; beside them the pinned host<->device copy rates."""
+    import numpy as np
+
+    n = 1 << args.log2n
+    rec = args.rec
+    dt = torch.int32 if rec == 8 else torch.int64
+    a = inputs.records(n, rec, args.data_seed)
+    host_in = bos.pinned_empty((n, 2), dt)
+    host_in.numpy()[:] = a.view(np.int32 if rec == 8 else np.int64)
+    del a
+    host_out = bos.pinned_empty((n, 2), dt)
+    p = bos.params(args.seed, args.z, args.k, args.tile)
+    import ctypes as C
+    hws = bos.pinned_empty((bos.lib().bos_host_workspace_bytes(n, rec, C.byref(p)),), torch.uint8)
+    dev_bytes = int(args.ooc_dev_gib * (1 << 30))
+    stream = torch.cuda.current_stream()
+    # copy rates of the host link (pinned, 1 GiB each way)
+    blk = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    hblk = bos.pinned_empty((1 << 30,), torch.uint8)
+    rates = {}
+    for name, fn in (("h2d", lambda: blk.copy_(hblk, non_blocking=True)),
+                     ("d2h", lambda: hblk.copy_(blk, non_blocking=True))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        rates[name + "_GB/s"] = round(3 * (1 << 30) / (time.perf_counter() - t0) / 1e9, 1)
+    del blk, hblk
+    res = {"workload": "n=2^%d records of %d B in pinned host memory, Z=%d" % (args.log2n, rec, args.z),
+           "device_workspace_GiB": args.ooc_dev_gib, "host_link": rates}
+    bz = None
+    for mode, fn in (("orp", bos.orp_host), ("sort", bos.sort_host)):
+        kw = {"z": args.z, "k": args.k, "out": host_out, "host_ws": hws, "dev_ws_bytes": dev_bytes}
+        if mode == "sort":
+            kw["tile"] = args.tile
+        _, rep = fn(host_in, seed=args.seed, report=True, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.ooc_steps):
+            fn(host_in, seed=args.seed, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.ooc_steps
+        bz = rep["buckets"] * rep["z"]
+        # bytes over the host link per call: every routing pass reads and writes
+        # the slot arrays (the first reads the n records, the last writes the
+        # bins' records), then the finish or strip reads the bins and writes n
+        # records; the sort's comparison phase reads and writes them twice more
+        link = (n * rec + 2 * (rep["passes"] - 1) * bz * (rec + 4) + bz * (rec + 4) + bz * rec
+                + bz * rec + n * rec)
+        if mode == "sort":
+            link += 4 * n * rec
+        res[mode] = {"ms": round(ms, 1), "Melem/s": round(n / ms / 1e3, 1), "passes": rep["passes"],
+                     "attempts": rep["attempts"], "host_link_bytes": int(link),
+                     "host_link_GB/s": round(link / ms / 1e6, 1)}
+    res["sorted"] = bool(np.all(np.diff(host_out.numpy()[:, 0].view(np.uint32 if rec == 8 else np.uint64)
+                                        .astype(np.float64)) >= 0))
+    del host_in, host_out, hws
     bos.release_workspaces()
     torch.cuda.empty_cache()
     return res
@@ -510,6 +581,10 @@ def main():
     args.tuning_used = None
     if (args.batched_count > 0 or args.serving_requests > 0 or args.dup_steps > 0) and args.mode == "sort":
         args.tuning_used = install_tuning(args, bos)
+    ooc = None
+    if args.ooc_steps > 0 and args.mode == "sort":
+        ooc = bench_ooc(args, torch, bos, inputs)
+        print("ooc: %s" % json.dumps(ooc), file=sys.stderr, flush=True)
     dup = None
     if args.dup_steps > 0 and args.mode == "sort":
         dup = bench_dup(args, torch, bos, inputs)
@@ -535,7 +610,7 @@ def main():
                    "n": n, "rec_bytes": args.rec, "z": rep["z"], "k": rep["k"], "levels": rep["levels"],
                    "passes": rep["passes"], "tile": rep["tile"], "parallelism": "1 GPU"},
         "attempts": rep["attempts"], "correct": ok,
-        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "dup_workload": dup, "batched": batched, "serving": served, "sweep": sweep,
+        "roofline": roof, "cpu_baseline": cpu, "bitonic": bit, "dup_workload": dup, "out_of_core": ooc, "batched": batched, "serving": served, "sweep": sweep,
         "kernels": kern,
         "kernel_sources": kernel_source_digest(),
     }

@@ -273,6 +273,44 @@ size_t bos_bitonic_workspace_bytes(uint64_t n, bos_rec rec);
 bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* ---- out-of-core (Section 4.3) --------------------------------------------- */
+
+/* Bucket ORP (bos_orp_host) and bucket oblivious sort (bos_sort_host) of n
+ * records held in HOST memory, for n beyond what the device holds (n <= 2^36).
+ * Same results as bos_orp / bos_sort with the same arguments: bos_orp_host's
+ * output is the one bos_orp gives for (input, seed, Z), bos_sort_host's is the
+ * sorted input.
+ *
+ * The slot arrays of Algorithm 3.1 live in host memory (host_ws).  Every
+ * routing pass streams them through the device once, in chunks of
+ * consecutive routing blocks: a chunk reads one contiguous range of buckets
+ * when it covers whole groups of 2^(i+k) buckets (2^k contiguous segments
+ * otherwise) and writes one contiguous range, the consecutive-bucket
+ * structure Section 4.3 builds its locality on.  The per-bin finish (ORP) or
+ * the strip (sort) streams the bins once more; the sort's comparison phase
+ * then sorts device-sized runs and merges them by sample splitters (one
+ * further read and write of the records).  Host-memory addresses, like device
+ * addresses, depend on (n, Z, k) in the routing phase, on the bin loads in the
+ * strip, and on comparisons of the permuted records in the comparison phase.
+ *
+ * in, out: host, n records each (not overlapping).  host_ws: host,
+ * bos_host_workspace_bytes(n, rec, p) bytes.  dev_ws: device, at least
+ * bos_host_device_bytes(n, rec, p) bytes; a larger one gives larger chunks.
+ * Host buffers allocated with hipHostMalloc (pinned) are copied at full DMA
+ * rate and let copies overlap kernels; pageable memory works, slower.
+ * The call orders itself after `stream`, runs on two internal streams of the
+ * current device and returns when `out` is written (overflow retries as with
+ * BOS_SYNC, whatever params->flags says).  Errors: INVALID_ARG (as bos_sort,
+ * n > 2^36), WORKSPACE (a workspace too small), UNSUPPORTED (a plan of one
+ * routing pass, or Z = 8: use the in-core calls), OVERFLOW, INSECURE_Z, HIP,
+ * INTERNAL (a consistency check of the comparison phase failed). */
+size_t bos_host_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p);
+size_t bos_host_device_bytes(uint64_t n, bos_rec rec, const bos_params* p);
+bos_status bos_orp_host(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* host_ws,
+                        size_t host_ws_bytes, void* dev_ws, size_t dev_ws_bytes, void* stream, bos_report* rep);
+bos_status bos_sort_host(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* host_ws,
+                         size_t host_ws_bytes, void* dev_ws, size_t dev_ws_bytes, void* stream, bos_report* rep);
+
 /* ---- tuning table --------------------------------------------------------- */
 
 /* One autotuner result: for records of `rec` bytes and n in size class

@@ -81,7 +81,8 @@ EXPORTS = ["bos_default_params", "bos_workspace_bytes", "bos_orp", "bos_sort", "
            "bos_status_string", "bos_debug_levels", "bos_debug_labels", "bos_plan", "bos_profile_enable",
            "bos_profile_read", "bos_step_workspace_bytes", "bos_sort_step", "bos_set_tuning", "bos_get_tuning",
            "bos_stepper_create", "bos_stepper_destroy", "bos_sort_step_async", "bos_sort_noalloc",
-           "bos_status_offset", "bos_trace_bind"]
+           "bos_status_offset", "bos_trace_bind", "bos_host_workspace_bytes", "bos_host_device_bytes",
+           "bos_orp_host", "bos_sort_host"]
 
 _lib = None
 _loaded = {}
@@ -127,6 +128,12 @@ def _load(path):
     for fn in (L.bos_orp, L.bos_sort):
         fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, R]
         fn.restype = C.c_int
+    for fn in (L.bos_orp_host, L.bos_sort_host):
+        fn.argtypes = [vp, vp, u64, C.c_int, P, vp, C.c_size_t, vp, C.c_size_t, vp, R]
+        fn.restype = C.c_int
+    for fn in (L.bos_host_workspace_bytes, L.bos_host_device_bytes):
+        fn.argtypes = [u64, C.c_int, P]
+        fn.restype = C.c_size_t
     L.bos_sort_noalloc.argtypes = [vp, vp, u64, C.c_int, P, vp, R]
     L.bos_sort_noalloc.restype = C.c_int
     L.bos_batched_workspace_bytes.argtypes = [C.POINTER(u64), u32, C.c_int, P]
@@ -284,6 +291,60 @@ def status_word(t, z=0, k=0, tile=0, min_security_bits=80):
     if w == 0xFFFFFFFFFFFFFFFF:
         return None
     return (w >> 32, w & 0xFFFFFFFF)
+
+
+def host_rec_bytes(t):
+    if t.dim() != 2 or t.shape[1] != 2 or t.is_cuda or not t.is_contiguous():
+        raise ValueError("records must be a contiguous (n, 2) host tensor")
+    if t.dtype == torch.int32:
+        return 8
+    if t.dtype == torch.int64:
+        return 16
+    raise ValueError("records must be int32 (8-byte) or int64 (16-byte) pairs")
+
+
+def pinned_empty(shape, dtype):
+    """A host tensor in pinned memory (copied at full DMA rate)."""
+    return torch.empty(shape, dtype=dtype, pin_memory=True)
+
+
+def _run_host(fn, t, p, out, host_ws, dev_ws_bytes, stream):
+    rec = host_rec_bytes(t)
+    n = t.shape[0]
+    if out is None:
+        out = pinned_empty(t.shape, t.dtype)
+    hb = lib().bos_host_workspace_bytes(n, rec, C.byref(p))
+    db = lib().bos_host_device_bytes(n, rec, C.byref(p))
+    if hb == 0 or db == 0:
+        raise BosError(INVALID_ARG, "libbos: no out-of-core workspace size for these arguments")
+    if host_ws is None or host_ws.numel() < hb:
+        host_ws = pinned_empty((hb,), torch.uint8)
+    db = max(db, dev_ws_bytes or 0)
+    dws = workspace(db)  # (the cached buffer may be larger; the call gets db bytes of it)
+    rep = Report()
+    _check(fn(C.c_void_p(t.data_ptr()), C.c_void_p(out.data_ptr()), n, rec, C.byref(p),
+              C.c_void_p(host_ws.data_ptr()), host_ws.numel(), C.c_void_p(dws.data_ptr()), db,
+              _stream(stream), C.byref(rep)))
+    return out, rep.as_dict()
+
+
+def orp_host(t, seed=0, z=0, k=0, max_retries=3, min_security_bits=80, out=None, host_ws=None, dev_ws_bytes=0,
+             stream=None, report=False, exact_finish=False):
+    """Out-of-core bucket ORP (Section 4.3) of the host records in t: the slot
+    arrays stay in host memory (host_ws, pinned if None) and stream through a
+    device workspace of dev_ws_bytes (at least the library's minimum).  Equals
+    orp() on the same records, seed and Z."""
+    p = params(seed, z, k, 0, max_retries, min_security_bits, exact_finish=exact_finish)
+    o, rep = _run_host(lib().bos_orp_host, t, p, out, host_ws, dev_ws_bytes, stream)
+    return (o, rep) if report else o
+
+
+def sort_host(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, host_ws=None,
+              dev_ws_bytes=0, stream=None, report=False):
+    """Out-of-core bucket oblivious sort (Section 4.3) of the host records in t."""
+    p = params(seed, z, k, tile, max_retries, min_security_bits)
+    o, rep = _run_host(lib().bos_sort_host, t, p, out, host_ws, dev_ws_bytes, stream)
+    return (o, rep) if report else o
 
 
 def sort_noalloc(t, seed=0, z=0, k=0, tile=0, max_retries=3, min_security_bits=80, out=None, stream=None,

@@ -44,6 +44,11 @@ hipError_t launch_route_batched(int rec, uint32_t lz, bool first, bool last, con
                                 uint32_t lds, hipStream_t s, bool split);
 hipError_t launch_strip_batched(int rec, const StripSeg* segs, uint32_t nsegs, uint32_t blocks, hipStream_t s);
 hipError_t launch_block_scan(unsigned long long* bsum, unsigned long long* coff, uint32_t nblocks, hipStream_t s);
+hipError_t launch_strip_staged(int rec, const void* binned, const uint32_t* loads, const unsigned long long* bsum,
+                               const unsigned long long* coff, void* out, uint64_t n, uint32_t klev, uint32_t lz,
+                               uint32_t tile, uint64_t blk0, uint32_t nblk, uint64_t bin_slot0, uint64_t out0,
+                               hipStream_t s);
+hipError_t launch_or_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s);
 hipError_t launch_orp_finish(int rec, uint32_t lz, const FinishArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* segs, uint32_t nsegs, uint32_t total,
                                hipStream_t s);
@@ -227,9 +232,9 @@ uint32_t levels_for(uint64_t n, uint32_t Z, uint64_t* B_out) {
   return L;
 }
 
-bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last, Plan* pl) {
+bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last, Plan* pl, uint64_t max_n = kMaxN) {
   if (rec != 8 && rec != 16) return BOS_ERR_INVALID_ARG;
-  if (n > kMaxN) return BOS_ERR_INVALID_ARG;
+  if (n > max_n) return BOS_ERR_INVALID_ARG;
   bos_tune_entry te;
   std::memset(&te, 0, sizeof(te));
   const bool tuned = (q.z == 0 || q.k == 0 || q.tile == 0) && tuned_for(n, rec, &te);
@@ -1939,3 +1944,530 @@ bos_status sort_batched_sequential(const bos_instance* inst, uint32_t count, bos
   return worst;
 }
 }  // namespace
+
+// ---- out-of-core bucket ORP and sort (Section 4.3) --------------------------
+//
+// The records, the output and the two slot arrays of Algorithm 3.1 stay in host
+// memory; the device holds the small per-run arrays (overflow word, bin loads,
+// block counts) and staging buffers.  Every routing pass streams the slot
+// arrays through the device once: a chunk of the pass's blocks is a range of
+// consecutive block indices, whose input is one contiguous range of buckets
+// when the chunk covers whole groups of 2^(i+k) buckets and 2^k contiguous
+// segments otherwise, and whose output is one contiguous range of buckets
+// (the consecutive-bucket structure of Section 4.3).  Chunks alternate between
+// two streams and two staging sets, so one chunk's copies overlap another's
+// kernels.  The per-bin finish (bos_orp) or strip (bos_sort) streams the bins
+// the same way; the sort's comparison phase is a two-pass external sort: runs
+// sorted on the device, then output segments cut by sample splitters, each
+// gathered from the runs, sorted on the device and written once.
+namespace {
+
+constexpr uint64_t kMaxNHost = 1ull << 36;
+constexpr int kOocDevices = 64;
+
+struct OocStreams {
+  hipStream_t st[2] = {nullptr, nullptr};
+  hipEvent_t ev = nullptr;
+};
+std::mutex g_ooc_mu;
+OocStreams g_ooc[kOocDevices];
+
+// Host workspace: slot arrays 0 and 1 (records, then the two tag arrays side
+// by side: after routing they hold the sort's runs, 2 B Z 4 >= n R bytes).
+struct HostLayout {
+  size_t off_rec[2], off_tag[2], total;
+};
+HostLayout host_layout(const Plan& pl) {
+  HostLayout h;
+  const size_t slots = size_t(pl.B) * pl.Z;
+  h.off_rec[0] = 0;
+  h.off_rec[1] = align_up(slots * pl.rec);
+  h.off_tag[0] = h.off_rec[1] + align_up(slots * pl.rec);
+  h.off_tag[1] = h.off_tag[0] + align_up(slots * 4);
+  h.total = h.off_tag[1] + align_up(slots * 4);
+  return h;
+}
+
+// Device workspace: status word, ticket and block counts; bin loads; chunk
+// offsets of the block scan and the finish's tie flag; the external sort's
+// error word; then the staging area.
+struct DevLayout {
+  size_t off_status, off_loads, off_coff, off_err, off_stage, stage;
+};
+constexpr size_t kOocMinStage = size_t(16) << 20;
+DevLayout dev_layout(const Plan& pl, size_t dws_bytes) {
+  DevLayout d;
+  d.off_status = 0;
+  d.off_loads = align_up(16 + size_t(pl.nblocks_last) * 8);
+  d.off_coff = d.off_loads + align_up(size_t(pl.B) * 4);
+  d.off_err = d.off_coff + align_up((size_t(pl.nblocks_last) / kScanChunk + 2) * 8);
+  d.off_stage = d.off_err + align_up(8);  // the OR of the external sort's error words
+  d.stage = dws_bytes > d.off_stage ? dws_bytes - d.off_stage : 0;
+  return d;
+}
+
+bos_status ooc_streams(OocStreams** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kOocDevices) return BOS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_ooc_mu);
+  OocStreams& o = g_ooc[dev];
+  if (!o.st[0]) {
+    // default priority (no priority variants)
+    if (hipStreamCreateWithFlags(&o.st[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&o.st[1], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&o.ev, hipEventDisableTiming) != hipSuccess)
+      return BOS_ERR_HIP;
+  }
+  *out = &o;
+  return BOS_OK;
+}
+
+uint64_t pow2_floor(uint64_t x) {
+  uint64_t p = 1;
+  while (p * 2 <= x) p *= 2;
+  return x ? p : 0;
+}
+uint32_t log2u(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+hipError_t h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
+  return bytes ? hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+}
+hipError_t d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
+  return bytes ? hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+}
+hipError_t sync2(OocStreams* o) {
+  hipError_t e = hipStreamSynchronize(o->st[0]);
+  if (e == hipSuccess) e = hipStreamSynchronize(o->st[1]);
+  return e;
+}
+
+// One attempt's routing passes, chunk by chunk (the last in split form: bins
+// compacted into host slot array (P - 1) & 1, loads and block counts on the
+// device).
+hipError_t ooc_route(const Plan& pl, const bos_params& q, uint32_t attempt, const char* in, char* hws,
+                     const HostLayout& hl, char* dws, const DevLayout& dl, OocStreams* o) {
+  const int R = pl.rec;
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(dws + dl.off_status);
+  hipError_t e = launch_fill_u64(status, 2 + pl.nblocks_last, 0, o->st[0]);
+  if (e == hipSuccess) e = launch_fill_u64(status, 1, kNoOverflow, o->st[0]);
+  if (e == hipSuccess) e = hipStreamSynchronize(o->st[0]);
+  if (e != hipSuccess) return e;
+  // staging: two sets of input records, input tags, output records, output tags
+  const uint64_t cap = pow2_floor(dl.stage / (4 * size_t(R + 4)));  // slots per buffer
+  for (uint32_t t = 0; t < pl.P; ++t) {
+    const uint32_t i0 = pl.lev0[t], k = pl.klev[t];
+    const bool first = t == 0, last = t + 1 == pl.P;
+    const uint64_t items = pl.B >> k, blk_slots = uint64_t(pl.Z) << k;
+    const uint64_t cb = std::min<uint64_t>(items, cap / blk_slots);
+    const char* hin_rec = hws + hl.off_rec[(t + 1) & 1];
+    const char* hin_tag = hws + hl.off_tag[(t + 1) & 1];
+    char* hout_rec = hws + hl.off_rec[t & 1];
+    char* hout_tag = hws + hl.off_tag[t & 1];
+    uint32_t c = 0;
+    for (uint64_t it0 = 0; it0 < items; it0 += cb, ++c) {
+      const int b = int(c & 1u);
+      hipStream_t s = o->st[b];
+      char* set = dws + dl.off_stage + size_t(b) * 2 * cap * (R + 4);
+      char* d_in_rec = set;
+      uint32_t* d_in_tag = reinterpret_cast<uint32_t*>(set + cap * R);
+      char* d_out_rec = set + cap * (R + 4);
+      uint32_t* d_out_tag = reinterpret_cast<uint32_t*>(set + cap * (R + 4) + cap * R);
+      PassArgs a;
+      std::memset(&a, 0, sizeof(a));
+      if (first) {
+        // groups [it0 2^k, (it0 + cb) 2^k) hold X[x_lo, x_hi)
+        const uint64_t j_lo = it0 << k, j_hi = (it0 + cb) << k;
+        const uint64_t x_lo = (j_lo * pl.n) >> pl.L, x_hi = (j_hi * pl.n) >> pl.L;
+        e = h2d(d_in_rec, in + x_lo * R, (x_hi - x_lo) * R, s);
+        a.x_in = d_in_rec;
+        a.x_off = x_lo;
+      } else {
+        const uint64_t g = 1ull << i0, h0 = it0 >> i0;
+        a.staged = 1;
+        a.in_h0 = h0;
+        if (cb >= g) {  // whole groups: one contiguous range of buckets
+          const uint64_t slot0 = (h0 << (i0 + k)) << pl.lz, ns = cb * blk_slots;
+          e = h2d(d_in_rec, hin_rec + slot0 * R, ns * R, s);
+          if (e == hipSuccess) e = h2d(d_in_tag, hin_tag + slot0 * 4, ns * 4, s);
+          a.in_r0 = 0;
+          a.in_lseg = i0;
+        } else {  // inside one group: 2^k segments of cb buckets
+          const uint64_t r0 = it0 & (g - 1), seg = cb << pl.lz;
+          for (uint64_t m = 0; m < (1ull << k) && e == hipSuccess; ++m) {
+            const uint64_t slot0 = ((h0 << (i0 + k)) + (m << i0) + r0) << pl.lz;
+            e = h2d(d_in_rec + m * seg * R, hin_rec + slot0 * R, seg * R, s);
+            if (e == hipSuccess) e = h2d(d_in_tag + m * seg, hin_tag + slot0 * 4, seg * 4, s);
+          }
+          a.in_r0 = r0;
+          a.in_lseg = log2u(cb);
+        }
+        a.rec_in = d_in_rec;
+        a.tag_in = d_in_tag;
+      }
+      if (e != hipSuccess) return e;
+      const uint64_t out_slot0 = (it0 << k) << pl.lz, ns_out = cb * blk_slots;
+      a.rec_out = d_out_rec;
+      a.tag_out = d_out_tag;
+      a.out_slot0 = out_slot0;
+      a.status = status;
+      a.ticket = reinterpret_cast<uint32_t*>(status + 1);
+      a.scan = status + 2;
+      a.n = pl.n;
+      a.buckets = pl.B;
+      a.seed = q.seed;
+      a.z = pl.Z;
+      a.lz = pl.lz;
+      a.levels = pl.L;
+      a.level0 = i0;
+      a.klev = k;
+      a.attempt = attempt;
+      a.fin = 1;
+      a.item_off = uint32_t(it0);
+      if (last) a.loads = reinterpret_cast<uint32_t*>(dws + dl.off_loads);
+      const uint32_t kind = first ? BOS_K_ROUTE_FIRST : last ? BOS_K_ROUTE_LAST : BOS_K_ROUTE_MID;
+      const uint64_t slot_bytes = ns_out * (uint64_t(R) + 4);
+      prof_begin(kind, t, slot_bytes * 2, s);
+      e = launch_route(R, a, first, last, uint32_t(cb), num_cus(), s, last);
+      prof_end(s);
+      if (e == hipSuccess) e = d2h(hout_rec + out_slot0 * R, d_out_rec, ns_out * R, s);
+      if (e == hipSuccess && !last) e = d2h(hout_tag + out_slot0 * 4, d_out_tag, ns_out * 4, s);
+      if (e != hipSuccess) return e;
+    }
+    e = sync2(o);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Output offset of every routing block (exclusive scan of the block counts),
+// read back to the host.
+hipError_t ooc_block_offsets(const Plan& pl, char* dws, const DevLayout& dl, hipStream_t s,
+                             std::vector<uint64_t>* boff) {
+  unsigned long long* scan = reinterpret_cast<unsigned long long*>(dws + dl.off_status) + 2;
+  unsigned long long* coff = reinterpret_cast<unsigned long long*>(dws + dl.off_coff);
+  const uint32_t nb = pl.nblocks_last, nch = (nb + kScanChunk - 1) / kScanChunk;
+  hipError_t e = launch_block_scan(scan, coff, nb, s);
+  std::vector<uint64_t> sc(nb), co(nch);
+  if (e == hipSuccess) e = d2h(sc.data(), scan, size_t(nb) * 8, s);
+  if (e == hipSuccess) e = d2h(co.data(), coff, size_t(nch) * 8, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  boff->resize(size_t(nb) + 1);
+  for (uint32_t b = 0; b < nb; ++b) (*boff)[b] = sc[b] + co[b / kScanChunk];
+  (*boff)[nb] = pl.n;
+  return hipSuccess;
+}
+
+// bos_orp's per-bin finish, or bos_sort's strip (into `dst`, host), over
+// chunks of whole routing blocks.
+hipError_t ooc_finish(const Plan& pl, const bos_params& q, uint32_t attempt, bool sort, char* dst, char* hws,
+                      const HostLayout& hl, char* dws, const DevLayout& dl, OocStreams* o,
+                      const std::vector<uint64_t>& boff) {
+  const int R = pl.rec;
+  const uint32_t klast = pl.klev[pl.P - 1];
+  const char* binned = hws + hl.off_rec[(pl.P - 1) & 1];
+  unsigned long long* scan = reinterpret_cast<unsigned long long*>(dws + dl.off_status) + 2;
+  unsigned long long* coff = reinterpret_cast<unsigned long long*>(dws + dl.off_coff);
+  unsigned long long* tie = coff + pl.nblocks_last / kScanChunk + 1;
+  const uint32_t* loads = reinterpret_cast<const uint32_t*>(dws + dl.off_loads);
+  hipError_t e = hipSuccess;
+  if (!sort) {
+    e = launch_fill_u64(tie, 1, (q.flags & BOS_EXACT_FINISH) ? 1ull : 0ull, o->st[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(o->st[0]);
+    if (e != hipSuccess) return e;
+  }
+  // two sets of (bin slots, output records)
+  const uint64_t cap = pow2_floor(dl.stage / (4 * size_t(R)));
+  const uint64_t bslots = uint64_t(pl.Z) << klast;  // slots per routing block
+  const uint64_t cblk = std::min<uint64_t>(pl.nblocks_last, cap / bslots);
+  uint32_t c = 0;
+  for (uint64_t b0 = 0; b0 < pl.nblocks_last; b0 += cblk, ++c) {
+    const uint64_t b1 = std::min<uint64_t>(b0 + cblk, pl.nblocks_last);
+    const int sb = int(c & 1u);
+    hipStream_t s = o->st[sb];
+    char* d_bin = dws + dl.off_stage + size_t(sb) * 2 * cap * R;
+    char* d_out = d_bin + cap * R;
+    const uint64_t slot0 = b0 * bslots, out0 = boff[b0], out1 = boff[b1];
+    e = h2d(d_bin, binned + slot0 * R, (b1 - b0) * bslots * R, s);
+    if (e != hipSuccess) return e;
+    if (sort) {
+      prof_begin(BOS_K_STRIP, c, 2 * (out1 - out0) * R, s);
+      e = launch_strip_staged(R, d_bin, loads, scan, coff, d_out, pl.n, klast, pl.lz, pl.tile, b0, uint32_t(b1 - b0),
+                              slot0, out0, s);
+    } else {
+      FinishArgs f;
+      std::memset(&f, 0, sizeof(f));
+      f.binned = d_bin;
+      f.loads = loads;
+      f.boff = scan;
+      f.coff = coff;
+      f.out = d_out;
+      f.n = pl.n;
+      f.nbins = pl.B;
+      f.seed = q.seed;
+      f.klev = klast;
+      f.attempt = attempt;
+      f.tie = tie;
+      f.gb_lo = b0 << klast;
+      f.gb_hi = b1 << klast;
+      f.bin_slot0 = slot0;
+      f.out0 = out0;
+      prof_begin(BOS_K_ORP_FINISH, c, 2 * (out1 - out0) * R, s);
+      e = launch_orp_finish(R, pl.lz, f, num_cus(), s);
+    }
+    prof_end(s);
+    if (e == hipSuccess) e = d2h(dst + out0 * R, d_out, (out1 - out0) * R, s);
+    if (e != hipSuccess) return e;
+  }
+  return sync2(o);
+}
+
+// Unsigned lexicographic (key, payload) order of two host records.
+bool host_rec_less(const char* a, const char* b, int R) {
+  if (R == 8) {
+    uint32_t ka, kb, pa, pb;
+    std::memcpy(&ka, a, 4);
+    std::memcpy(&kb, b, 4);
+    if (ka != kb) return ka < kb;
+    std::memcpy(&pa, a + 4, 4);
+    std::memcpy(&pb, b + 4, 4);
+    return pa < pb;
+  }
+  uint64_t ka, kb, pa, pb;
+  std::memcpy(&ka, a, 8);
+  std::memcpy(&kb, b, 8);
+  if (ka != kb) return ka < kb;
+  std::memcpy(&pa, a + 8, 8);
+  std::memcpy(&pb, b + 8, 8);
+  return pa < pb;
+}
+
+// Comparison phase of the out-of-core sort (Section 3.3 applied to host
+// arrays): the permuted records in `a` (host, n records) are sorted into
+// `out` (host).  Runs of rl records (a multiple of the tile, so their tile
+// sorts cover the tiles the strip prepared) are sorted on the device in
+// place; then every q-th record of each run is a sample, the samples are
+// ordered by (record, run, position), every t-th opens an output segment, and
+// each run is cut at each splitter by binary search (a total order, so equal
+// records split consistently).  A segment holds at most t q + m (q - 1) <= rl
+// records; its run slices are gathered, sorted on the device and written to
+// their place in `out`.  Every access depends on comparisons of the permuted
+// records only.
+bos_status ooc_comparison_sort(const Plan& pl, char* a, char* out, char* dws, const DevLayout& dl, OocStreams* o) {
+  const int R = pl.rec;
+  const uint64_t n = pl.n;
+  // two sets of (buffer, buffer, merge splits) of rl records
+  uint64_t rl = pow2_floor(dl.stage / 2 / (2 * size_t(R)));
+  while (rl >= pl.tile && 2 * (align_up(2 * rl * R) + align_up(comparison_sort_split_bytes(rl, R))) > dl.stage)
+    rl /= 2;
+  if (rl < pl.tile || rl < 2) return BOS_ERR_WORKSPACE;
+  const size_t set_bytes = align_up(2 * rl * R) + align_up(comparison_sort_split_bytes(rl, R));
+  unsigned long long* err = reinterpret_cast<unsigned long long*>(dws + dl.off_err);
+  auto sort_on_device = [&](int sb, uint64_t len, hipStream_t s, void** result) -> hipError_t {
+    char* set = dws + dl.off_stage + size_t(sb) * set_bytes;
+    uint64_t* split = reinterpret_cast<uint64_t*>(set + align_up(2 * rl * R));
+    *result = set;
+    if (len <= 1) return hipSuccess;
+    hipError_t e = launch_comparison_sort(R, set, set + rl * R, len, pl.tile, split, s, result, true);
+    if (e == hipSuccess) e = launch_or_u64(err, comparison_sort_err_word(split, len, R), s);
+    return e;
+  };
+  hipError_t e = launch_fill_u64(err, 1, 0ull, o->st[0]);
+  if (e == hipSuccess) e = hipStreamSynchronize(o->st[0]);
+  if (e != hipSuccess) return BOS_ERR_HIP;
+  const uint64_t m = (n + rl - 1) / rl;
+  char* dst_runs = m == 1 ? out : a;  // a single run goes straight to out
+  for (uint64_t r = 0; r < m; ++r) {
+    const int sb = int(r & 1u);
+    hipStream_t s = o->st[sb];
+    const uint64_t len = std::min(rl, n - r * rl);
+    char* set = dws + dl.off_stage + size_t(sb) * set_bytes;
+    void* result = nullptr;
+    e = h2d(set, a + r * rl * R, len * R, s);
+    if (e == hipSuccess) e = sort_on_device(sb, len, s, &result);
+    if (e == hipSuccess) e = d2h(dst_runs + r * rl * R, result, len * R, s);
+    if (e != hipSuccess) return BOS_ERR_HIP;
+  }
+  if (sync2(o) != hipSuccess) return BOS_ERR_HIP;
+  if (m > 1) {
+    // samples every q records of every run, q the largest power of two with m q <= rl / 2
+    uint64_t q = pow2_floor(rl / (2 * m));
+    if (q == 0) return BOS_ERR_WORKSPACE;
+    struct Smp {
+      const char* p;
+      uint64_t run, pos;
+    };
+    std::vector<Smp> smp;
+    for (uint64_t r = 0; r < m; ++r) {
+      const uint64_t len = std::min(rl, n - r * rl);
+      for (uint64_t i = 0; i < len; i += q) smp.push_back(Smp{a + (r * rl + i) * R, r, i});
+    }
+    std::sort(smp.begin(), smp.end(), [&](const Smp& x, const Smp& y) {
+      if (host_rec_less(x.p, y.p, R)) return true;
+      if (host_rec_less(y.p, x.p, R)) return false;
+      return x.run != y.run ? x.run < y.run : x.pos < y.pos;
+    });
+    const uint64_t t = (rl - m * q) / q;
+    // cut[j * m + r]: first position of run r in segment j
+    std::vector<uint64_t> cut;
+    for (uint64_t r = 0; r < m; ++r) cut.push_back(0);
+    for (uint64_t si = t; si < smp.size(); si += t) {
+      const Smp& sp = smp[si];
+      for (uint64_t r = 0; r < m; ++r) {
+        const char* run = a + r * rl * R;
+        const uint64_t len = std::min(rl, n - r * rl);
+        uint64_t pos;
+        if (r == sp.run) {
+          pos = sp.pos;
+        } else {
+          // records before (sp, run, pos) in the order (record, run, position)
+          uint64_t lo = 0, hi = len;
+          while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            const char* x = run + mid * R;
+            const bool before = r < sp.run ? !host_rec_less(sp.p, x, R) : host_rec_less(x, sp.p, R);
+            if (before)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          pos = lo;
+        }
+        cut.push_back(pos);
+      }
+    }
+    for (uint64_t r = 0; r < m; ++r) cut.push_back(std::min(rl, n - r * rl));
+    const uint64_t nseg = cut.size() / m - 1;
+    uint64_t base = 0;
+    for (uint64_t j = 0; j < nseg; ++j) {
+      const int sb = int(j & 1u);
+      hipStream_t s = o->st[sb];
+      char* set = dws + dl.off_stage + size_t(sb) * set_bytes;
+      uint64_t len = 0;
+      for (uint64_t r = 0; r < m && e == hipSuccess; ++r) {
+        const uint64_t c0 = cut[j * m + r], c1 = cut[(j + 1) * m + r];
+        if (c1 < c0 || len + (c1 - c0) > rl) return BOS_ERR_INTERNAL;  // the segment bound above
+        e = h2d(set + len * R, a + (r * rl + c0) * R, (c1 - c0) * R, s);
+        len += c1 - c0;
+      }
+      void* result = nullptr;
+      if (e == hipSuccess) e = sort_on_device(sb, len, s, &result);
+      if (e == hipSuccess) e = d2h(out + base * R, result, len * R, s);
+      if (e != hipSuccess) return BOS_ERR_HIP;
+      base += len;
+    }
+    if (base != n) return BOS_ERR_INTERNAL;
+    if (sync2(o) != hipSuccess) return BOS_ERR_HIP;
+  }
+  unsigned long long eh = 0;
+  if (d2h(&eh, err, 8, o->st[0]) != hipSuccess || hipStreamSynchronize(o->st[0]) != hipSuccess) return BOS_ERR_HIP;
+  return eh ? BOS_ERR_INTERNAL : BOS_OK;
+}
+
+bos_status ooc_impl(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* hws,
+                    size_t hws_bytes, void* dws, size_t dws_bytes, void* stream, bos_report* rep, bool sort) {
+  if (!has_gpu()) return BOS_ERR_UNSUPPORTED;
+  bos_params q = resolve(p);
+  q.flags |= BOS_SYNC;
+  Plan pl;
+  bos_status st = make_plan(n, int(rec), q, true, &pl, kMaxNHost);
+  if (st != BOS_OK) return st;
+  if (n == 0) {
+    fill_report(rep, pl, 0, kNoOverflow, 0);
+    return BOS_OK;
+  }
+  if (!in || !out || in == out) return BOS_ERR_INVALID_ARG;
+  if (!split_last(pl)) return BOS_ERR_UNSUPPORTED;  // one routing pass: the in-core calls cover it
+  for (uint32_t t = 0; t < pl.P; ++t)
+    if (!use_route_kernel(pl, t)) return BOS_ERR_UNSUPPORTED;
+  const HostLayout hl = host_layout(pl);
+  if (!hws || hws_bytes < hl.total) return BOS_ERR_WORKSPACE;
+  const DevLayout dl = dev_layout(pl, dws_bytes);
+  const uint64_t blk_max = uint64_t(pl.Z) << pl.k;
+  if (!dws || dl.stage < kOocMinStage || dl.stage < 4 * blk_max * (uint64_t(pl.rec) + 4)) return BOS_ERR_WORKSPACE;
+  OocStreams* o = nullptr;
+  st = ooc_streams(&o);
+  if (st != BOS_OK) return st;
+  // order after the caller's stream
+  hipStream_t cs = static_cast<hipStream_t>(stream);
+  if (hipEventRecord(o->ev, cs) != hipSuccess || hipStreamWaitEvent(o->st[0], o->ev, 0) != hipSuccess ||
+      hipStreamWaitEvent(o->st[1], o->ev, 0) != hipSuccess)
+    return BOS_ERR_HIP;
+  char* h = static_cast<char*>(hws);
+  char* d = static_cast<char*>(dws);
+  uint32_t attempts = 0;
+  uint64_t ovf = kNoOverflow, last_ovf = kNoOverflow;
+  bool ok = false;
+  uint32_t att = q.attempt;
+  for (; att <= std::max(q.max_retries, q.attempt); ++att) {
+    if (ooc_route(pl, q, att, static_cast<const char*>(in), h, hl, d, dl, o) != hipSuccess) return BOS_ERR_HIP;
+    attempts = att + 1;
+    uint64_t sw = 0;
+    if (d2h(&sw, d + dl.off_status, 8, o->st[0]) != hipSuccess || hipStreamSynchronize(o->st[0]) != hipSuccess)
+      return BOS_ERR_HIP;
+    if (sw == kNoOverflow) {
+      ok = true;
+      ovf = last_ovf;
+      break;
+    }
+    last_ovf = sw;
+  }
+  if (!ok) {
+    fill_report(rep, pl, attempts, last_ovf, 0);
+    return BOS_ERR_OVERFLOW;
+  }
+  std::vector<uint64_t> boff;
+  if (ooc_block_offsets(pl, d, dl, o->st[0], &boff) != hipSuccess) return BOS_ERR_HIP;
+  if (!sort) {
+    if (ooc_finish(pl, q, att, false, static_cast<char*>(out), h, hl, d, dl, o, boff) != hipSuccess)
+      return BOS_ERR_HIP;
+    fill_report(rep, pl, attempts, ovf, 0);
+    return BOS_OK;
+  }
+  // strip into the tag arrays (dead after routing), then the comparison phase
+  char* a = h + hl.off_tag[0];
+  if (ooc_finish(pl, q, att, true, a, h, hl, d, dl, o, boff) != hipSuccess) return BOS_ERR_HIP;
+  st = ooc_comparison_sort(pl, a, static_cast<char*>(out), d, dl, o);
+  fill_report(rep, pl, attempts, ovf, 6 * n * uint64_t(pl.rec));
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bos_host_workspace_bytes(uint64_t n, bos_rec rec, const bos_params* p) {
+  if (!has_gpu()) return 0;
+  Plan pl;
+  bos_params q = resolve(p);
+  q.min_security_bits = 0;
+  if (make_plan(n, int(rec), q, true, &pl, kMaxNHost) != BOS_OK) return 0;
+  return host_layout(pl).total;
+}
+
+size_t bos_host_device_bytes(uint64_t n, bos_rec rec, const bos_params* p) {
+  if (!has_gpu()) return 0;
+  Plan pl;
+  bos_params q = resolve(p);
+  q.min_security_bits = 0;
+  if (make_plan(n, int(rec), q, true, &pl, kMaxNHost) != BOS_OK) return 0;
+  const DevLayout dl = dev_layout(pl, 0);
+  const uint64_t blk_max = uint64_t(pl.Z) << pl.k;
+  return dl.off_stage + std::max<size_t>(kOocMinStage, 4 * blk_max * (size_t(pl.rec) + 4));
+}
+
+bos_status bos_orp_host(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* host_ws,
+                        size_t host_ws_bytes, void* dev_ws, size_t dev_ws_bytes, void* stream, bos_report* rep) {
+  return ooc_impl(in, out, n, rec, p, host_ws, host_ws_bytes, dev_ws, dev_ws_bytes, stream, rep, false);
+}
+
+bos_status bos_sort_host(const void* in, void* out, uint64_t n, bos_rec rec, const bos_params* p, void* host_ws,
+                         size_t host_ws_bytes, void* dev_ws, size_t dev_ws_bytes, void* stream, bos_report* rep) {
+  return ooc_impl(in, out, n, rec, p, host_ws, host_ws_bytes, dev_ws, dev_ws_bytes, stream, rep, true);
+}
+
+}  // extern "C"

@@ -107,6 +107,15 @@ struct PassArgs {
   uint32_t fin;               // fused last pass: 0 = random permutation of each bin, 1 = sort each bin
   uint32_t pad;
   uint32_t* loads;            // split last pass: real count of every final bin
+  // Staged (out-of-core) launches run a chunk of the pass's blocks on copies
+  // of its slots; all zero otherwise.  Blocks keep their global index
+  // (item_off + launch index) for labels, overflow pairs and bins.
+  uint32_t item_off;          // global index of the launch's first block
+  uint32_t staged;            // 1: rec_in/tag_in hold the chunk's input segments (in_h0, in_r0, in_lseg)
+  uint64_t in_h0, in_r0;      // the chunk's first group h and (for a chunk inside one group) first r
+  uint32_t in_lseg, pad2;     // log2 of the buckets per staged input segment
+  uint64_t x_off;             // first pass: global index of the first staged input record
+  uint64_t out_slot0;         // global index of the first staged output slot (rec_out, tag_out)
 };
 
 // One instance of a batched comparison-sort launch (tile sort or merge pass).
@@ -163,6 +172,10 @@ struct FinishArgs {
   uint32_t klev;                    // levels of the last pass: a block holds 2^klev bins
   uint32_t attempt;
   unsigned long long* tie;          // raised when a bin's random keys tie (cleared before the finish)
+  // Staged (out-of-core) launches finish bins [gb_lo, gb_hi) from a copy of
+  // their slots (binned index minus bin_slot0) into a copy of their output
+  // range (out index minus out0); 0, 0, nbins, 0 otherwise.
+  uint64_t gb_lo, gb_hi, bin_slot0, out0;
 };
 
 // One instance's status words to initialise before its first routing pass.

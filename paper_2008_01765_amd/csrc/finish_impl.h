@@ -245,9 +245,10 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
   if constexpr (EXACT) {
     if (__hip_atomic_load(a.tie, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0ull) return;
   }
-  for (uint64_t g0 = uint64_t(blockIdx.x) * BPW; g0 < a.nbins; g0 += uint64_t(gridDim.x) * BPW) {
+  const uint64_t gend = a.gb_hi ? a.gb_hi : a.nbins;  // bins [gb_lo, gend)
+  for (uint64_t g0 = a.gb_lo + uint64_t(blockIdx.x) * BPW; g0 < gend; g0 += uint64_t(gridDim.x) * BPW) {
     const uint64_t gb = g0 + S;
-    const bool act = gb < a.nbins;
+    const bool act = gb < gend;
     uint32_t load = 0;
     uint64_t off = 0;
     if (act) {
@@ -264,7 +265,8 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
         off += a.loads[j];
       }
     }
-    const uint64_t src = (gb << LZ) + 16u * lq;
+    // slot index of the staged copy (global index minus bin_slot0)
+    const uint64_t src = (gb << LZ) + 16u * lq - a.bin_slot0;
     if constexpr (LZ <= 10) {
       // 1. record order, dummies (maximal record) last
       FE1<R> v[16];
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
           const uint32_t p = 16u * lq + e;
           if (p < load && off + p < a.n) {
             BOS_TR(0, 21, off + p);
-            out[off + p] = f_store(w[e].r);
+            out[off + p - a.out0] = f_store(w[e].r);
           }
         }
       }
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
           const uint32_t p = 16u * lq + e;
           if (p < load && off + p < a.n) {
             BOS_TR(0, 21, off + p);
-            out[off + p] = w[e].r;
+            out[off + p - a.out0] = w[e].r;
           }
         }
       }

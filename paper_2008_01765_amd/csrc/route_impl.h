@@ -650,7 +650,7 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
       const uint32_t p = 16u * lq + e;
       if (p < kept) {
         BOS_TR(0, 12, (gb << LZ) + p);
-        BO[(gb << LZ) + p] = outr[e];
+        BO[(gb << LZ) + p - a.out_slot0] = outr[e];
       }
     }
   }
@@ -801,14 +801,18 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     if constexpr (!FIRST) {
       const uint64_t bucket = (h << (i0 + klev)) + (uint64_t(S_load) << i0) + r;
       const uint64_t gi = (bucket << LZ) + sb_load;
+      // staged chunk: input segment S_load holds buckets (S_load, r in0 ..)
+      const uint64_t si = a.staged ? ((((h - a.in_h0) << (i0 + klev)) + (uint64_t(S_load) << a.in_lseg) +
+                                       (r - a.in_r0)) << LZ) + sb_load
+                                   : gi;
 #pragma unroll
       for (uint32_t e = 0; e < 16; ++e) {
         if (active) {
           BOS_TR(0, 1, gi + e);
           BOS_TR(0, 2, gi + e);
         }
-        dr[e] = active ? RI[gi + e] : zero_rec<T>();
-        dt[e] = active ? a.tag_in[gi + e] : kDummyTag;
+        dr[e] = active ? RI[si + e] : zero_rec<T>();
+        dt[e] = active ? a.tag_in[si + e] : kDummyTag;
       }
     } else {
       // group j = h*NB + S_load holds X[floor(jn/B), floor((j+1)n/B))
@@ -818,7 +822,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       for (uint32_t e = 0; e < 16; ++e) {
         const bool real = active && (sb_load + e) < gz;
         if (real) BOS_TR(0, 3, gs + sb_load + e);
-        dr[e] = real ? X[gs + sb_load + e] : zero_rec<T>();
+        dr[e] = real ? X[gs + sb_load + e - a.x_off] : zero_rec<T>();
         dt[e] = real ? 0u : kDummyTag;  // label filled in by finish_load
       }
     }
@@ -901,7 +905,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         BOS_TR(0, 3, x);
         BOS_TR(0, 4, pi);
         BOS_TR(0, 5, pi);
-        srec[pi] = X[x];
+        srec[pi] = X[x - a.x_off];
         stag[pi] = L ? (word >> (32u - L)) : 0u;
       }
     }
@@ -1184,8 +1188,8 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
             }
             BOS_TR(0, 10, gi);
             BOS_TR(0, 11, gi);
-            RO[gi] = rv[e];
-            a.tag_out[gi] = tv[e];
+            RO[gi - a.out_slot0] = rv[e];
+            a.tag_out[gi - a.out_slot0] = tv[e];
           }
         }
       }
@@ -1193,6 +1197,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   };
 
   if constexpr (BATCH && (!LAST || SPLIT)) {
+    item0 += a.item_off;
     if (FIRST && !aligned) {
       staged_first_load(item0);
     } else {
@@ -1207,8 +1212,11 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     // prefetch registers a pass runs three workgroups per CU at 2^3 Z slots
     // per block, and their interleaving hides the loads better than a
     // register prefetch with fewer workgroups did.
-    uint32_t item = item0;
-    if (item >= nitems) return;
+    // items are global block indices: a staged launch runs blocks
+    // item_off .. item_off + nitems - 1
+    const uint32_t ioff = a.item_off, iend = ioff + nitems;
+    uint32_t item = item0 + ioff;
+    if (item >= iend) return;
     if (FIRST && !aligned) {
       staged_first_load(item);
     } else {
@@ -1217,7 +1225,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     }
     for (;;) {
       const uint32_t next = item + gridDim.x;
-      const bool has_next = next < nitems;
+      const bool has_next = next < iend;
       process(item);
       if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item, klev, srec, stag, srhi, saux, sload, spfx, swave);
       if (!has_next) break;

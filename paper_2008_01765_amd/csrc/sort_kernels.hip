@@ -935,6 +935,10 @@ __global__ void fill_status_kernel_b(const FillSeg* segs, uint32_t nsegs) {
     sg.p[i] = i == 0 && !sg.zero_first ? kNoOverflow : 0ull;
 }
 
+__global__ void or_u64_kernel(unsigned long long* dst, const unsigned long long* src) {
+  if (threadIdx.x == 0) *dst |= *src;
+}
+
 // Per-instance outcome of a batch: BOS_ERR_OVERFLOW (2) when its status word
 // shows an overflow, else BOS_ERR_INTERNAL (7) when its comparison-sort error
 // word is set, else BOS_OK (0); a null pointer skips that check.
@@ -1464,6 +1468,12 @@ hipError_t launch_sort_batched(int rec, int kind, uint32_t tile, const SortSeg* 
 hipError_t launch_fill_status_batched(const FillSeg* segs, uint32_t nsegs, hipStream_t s) {
   if (nsegs == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_status_kernel_b, dim3(nsegs), dim3(256), 0, s, segs, nsegs);
+  return hipGetLastError();
+}
+
+// *dst |= *src, stream-ordered (one thread).
+hipError_t launch_or_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s) {
+  hipLaunchKernelGGL(or_u64_kernel, dim3(1), dim3(64), 0, s, dst, src);
   return hipGetLastError();
 }
 

@@ -126,11 +126,14 @@ __device__ __forceinline__ void lds_bitonic(T* sb, uint32_t P2) {
 // One routing block's bins (NB = 2^klev of them) to out[boff[blk] + coff[blk /
 // 1024] ..) (coff null: boff alone); bins that straddle a multiple of `tile`
 // are sorted first (tile = 0: none).
+// Staged (out-of-core) launches read a copy of the blocks' slots (binned
+// index minus bin_slot0) and write a copy of their output range (out index
+// minus out0); both are 0 otherwise.
 template <int R>
 __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t* loads,
                                             const unsigned long long* boff, const unsigned long long* coff,
                                             void* out_, uint64_t n, uint32_t klev, uint32_t lz, uint64_t blk,
-                                            uint32_t tile) {
+                                            uint32_t tile, uint64_t bin_slot0 = 0, uint64_t out0 = 0) {
   using T = typename RecOf<R>::T;
   __shared__ uint32_t pre[513];  // NB <= 512: a block has at most 8192 slots, Z >= 16
   __shared__ uint16_t strad[512];
@@ -178,7 +181,7 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
       const uint32_t j = strad[k], ld = pre[j + 1] - pre[j];
       uint32_t P2 = 2;
       while (P2 < ld) P2 <<= 1;
-      const T* src = binned + ((bin0 + j) << lz);
+      const T* src = binned + ((bin0 + j) << lz) - bin_slot0;
       for (uint32_t i = tid; i < P2; i += kStripThreads) {
         if (i < ld) BOS_TR(0, 38, ((bin0 + j) << lz) + i);
         BOS_TR(0, 33, i);
@@ -191,7 +194,7 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
         if (o + i < n) {
           BOS_TR(0, 33, i);
           BOS_TR(0, 39, o + i);
-          out[o + i] = sb[i];
+          out[o + i - out0] = sb[i];
         }
       __syncthreads();
     }
@@ -226,14 +229,14 @@ __device__ __forceinline__ void strip_block(const void* binned_, const uint32_t*
       }
       BOS_TR(0, 35, lo);
       BOS_TR(0, 38, ((bin0 + lo) << lz) + (qq - pre[lo]));
-      v[k] = bv[((bin0 + lo) << lz) + (qq - pre[lo])];
+      v[k] = bv[((bin0 + lo) << lz) + (qq - pre[lo]) - bin_slot0];
       dst[k] = q < total && !done ? base + q : ~0ull;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kStripItems; ++k)
       if (dst[k] < n) {
         BOS_TR(0, 39, dst[k]);
-        ov[dst[k]] = v[k];
+        ov[dst[k] - out0] = v[k];
       }
   }
 }
@@ -244,6 +247,17 @@ __global__ __launch_bounds__(kStripThreads) void strip_kernel(const void* binned
                                                               const unsigned long long* coff, void* out, uint64_t n,
                                                               uint32_t klev, uint32_t lz, uint32_t tile) {
   strip_block<R>(binned, loads, boff, coff, out, n, klev, lz, blockIdx.x, tile);
+}
+
+// Strip of blocks blk0 .. blk0 + gridDim.x - 1 from staged copies (out-of-core).
+template <int R>
+__global__ __launch_bounds__(kStripThreads) void strip_kernel_staged(const void* binned, const uint32_t* loads,
+                                                                     const unsigned long long* boff,
+                                                                     const unsigned long long* coff, void* out,
+                                                                     uint64_t n, uint32_t klev, uint32_t lz,
+                                                                     uint32_t tile, uint64_t blk0, uint64_t bin_slot0,
+                                                                     uint64_t out0) {
+  strip_block<R>(binned, loads, boff, coff, out, n, klev, lz, blk0 + blockIdx.x, tile, bin_slot0, out0);
 }
 
 // Batched forms: one scan workgroup per instance; the strip workgroups of
@@ -317,6 +331,30 @@ hipError_t launch_strip(int rec, const void* binned, const uint32_t* loads, unsi
   else
     hipLaunchKernelGGL(strip_kernel<16>, dim3(nblocks), dim3(kStripThreads), 0, s, binned, loads, bsum, coff, out, n,
                        klev, lz, tile);
+  return hipGetLastError();
+}
+
+}  // namespace bos
+
+namespace bos {
+
+// Strip of routing blocks [blk0, blk0 + nblk) of an out-of-core sort: their
+// bins' slots staged at `binned` (global slot index minus bin_slot0), their
+// output range staged at `out` (global record index minus out0); bsum and coff
+// already scanned (launch_block_scan).
+hipError_t launch_strip_staged(int rec, const void* binned, const uint32_t* loads, const unsigned long long* bsum,
+                               const unsigned long long* coff, void* out, uint64_t n, uint32_t klev, uint32_t lz,
+                               uint32_t tile, uint64_t blk0, uint32_t nblk, uint64_t bin_slot0, uint64_t out0,
+                               hipStream_t s) {
+  BOS_TRACE_BIND();
+  if (klev > 9 || lz > 11 || (tile & (tile - 1u)) || !coff) return hipErrorInvalidValue;
+  if (nblk == 0) return hipSuccess;
+  if (rec == 8)
+    hipLaunchKernelGGL(strip_kernel_staged<8>, dim3(nblk), dim3(kStripThreads), 0, s, binned, loads, bsum, coff, out,
+                       n, klev, lz, tile, blk0, bin_slot0, out0);
+  else
+    hipLaunchKernelGGL(strip_kernel_staged<16>, dim3(nblk), dim3(kStripThreads), 0, s, binned, loads, bsum, coff,
+                       out, n, klev, lz, tile, blk0, bin_slot0, out0);
   return hipGetLastError();
 }
 
