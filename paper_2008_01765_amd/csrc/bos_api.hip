@@ -202,12 +202,14 @@ bool tuned_for(uint64_t n, int rec, bos_tune_entry* out) {
 }
 
 // Largest k such that a block of 2^k buckets fits in LDS and in 512 threads.
-uint32_t max_klev(int rec, uint32_t z, bool last_shuffle) {
+// Most levels per pass whose block fits a workgroup and its LDS (full_rec:
+// whole records in LDS, as in the fused last pass and the generic kernel).
+uint32_t max_klev(int rec, uint32_t z, bool last_shuffle, bool full_rec) {
   uint32_t best = 0;
   for (uint32_t k = 1; k <= 12; ++k) {
     const uint64_t m = uint64_t(z) << k;
     if (m / 16 > uint64_t(kMaxThreads)) break;
-    if (pass_lds_bytes(rec, z, k, last_shuffle) > lds_max()) break;
+    if (pass_lds_bytes(rec, z, k, last_shuffle, full_rec) > lds_max()) break;
     best = k;
   }
   return best;
@@ -262,7 +264,8 @@ bos_status make_plan(uint64_t n, int rec, const bos_params& q, bool shuffle_last
   while ((1u << pl->lz) < Z) ++pl->lz;
   pl->B = B;
   pl->L = L;
-  const uint32_t kmid = max_klev(rec, Z, false), klast = max_klev(rec, Z, shuffle_last);
+  // the last pass is sized as the fused form (whole records in LDS)
+  const uint32_t kmid = max_klev(rec, Z, false, pl->generic), klast = max_klev(rec, Z, shuffle_last, true);
   if (kmid == 0 || klast == 0) return BOS_ERR_UNSUPPORTED;
   // default: 3 levels per pass (a block of 2^3 Z slots leaves LDS for three
   // workgroups per CU at Z = 512, which outruns fewer, larger passes)
@@ -762,7 +765,7 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
           starts.push_back(blocks);
           blocks += uint32_t(pl.B >> pl.klev[t]);
           threads = std::max(threads, uint32_t((pl.Z << pl.klev[t]) >> 4));
-          lds = std::max(lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false));
+          lds = std::max(lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false, (mode & 2) && !(mode & 4)));
         }
         if (segs.empty()) continue;
         BLaunch l;
@@ -1543,7 +1546,7 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
         g.starts.push_back(g.blocks);
         g.blocks += items;
         g.threads = std::max(g.threads, uint32_t((pl.Z << pl.klev[ph]) >> 4));
-        g.lds = std::max(g.lds, pass_lds_bytes(R, pl.Z, pl.klev[ph], false));
+        g.lds = std::max(g.lds, pass_lds_bytes(R, pl.Z, pl.klev[ph], false, (mode & 2) && !(mode & 4)));
         if (last) {
           phase[i] = pl.P;  // on to the tile sort; the check is at the end of the step
           routed[i] = 1;

@@ -245,10 +245,20 @@ __device__ __forceinline__ void trace_idx(uint32_t which, uint32_t cls, uint64_t
 #endif
 
 // Dynamic LDS bytes of a routing block (must match the carve in the kernel).
-__host__ __device__ inline uint32_t pass_lds_bytes(int rec, uint32_t z, uint32_t klev, bool last_shuffle) {
+// LDS bytes per slot of a routing pass's records.  16-byte records at
+// 64 <= Z <= 512 go through LDS in two 8-byte halves (the second after the
+// first has been read), so a block needs 12 bytes of LDS per slot as with
+// 8-byte records; the fused last pass keeps whole records (its per-bin sorts
+// hold them in LDS).
+__host__ __device__ constexpr uint32_t lds_rec_bytes(int rec, uint32_t z, bool fused) {
+  return (rec == 16 && z >= 64 && z <= 512 && !fused) ? 8u : uint32_t(rec);
+}
+
+__host__ __device__ inline uint32_t pass_lds_bytes(int rec, uint32_t z, uint32_t klev, bool last_shuffle,
+                                                   bool fused) {
   const uint32_t m = z << klev;
   const uint32_t mp = m + (m >> 4);
-  uint32_t b = mp * uint32_t(rec) + mp * 4u + (m >> 4) * 4u + (1u << klev) * 12u + 64u * 4u + 64u;
+  uint32_t b = mp * lds_rec_bytes(rec, z, fused) + mp * 4u + (m >> 4) * 4u + (1u << klev) * 12u + 64u * 4u + 64u;
   if (last_shuffle) b += mp * 4u + mp * 2u;
   return (b + 15u) & ~15u;
 }

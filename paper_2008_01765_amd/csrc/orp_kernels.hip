@@ -443,7 +443,7 @@ static hipError_t launch_pass_t(const PassArgs& a, uint32_t nblocks, hipStream_t
   const uint32_t m = a.z << a.klev;
   uint32_t threads = m >> 4;
   if (threads < 64) threads = 64;
-  const uint32_t lds = pass_lds_bytes(R, a.z, a.klev, (MODE & 2) && a.fin == 0);
+  const uint32_t lds = pass_lds_bytes(R, a.z, a.klev, (MODE & 2) && a.fin == 0, true);  // whole records in LDS
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&orp_pass_kernel<R, MODE>),

@@ -77,6 +77,23 @@ __device__ __forceinline__ uint4 dpp(uint4 v) {
 
 __device__ __forceinline__ uint32_t brev_k(uint32_t x, uint32_t k) { return k ? (__brev(x) >> (32u - k)) : 0u; }
 
+// Halves of a 16-byte record for two-half LDS exchanges (identity for 8-byte
+// records, which never take that path).
+__device__ __forceinline__ uint2 rec_lo(uint4 v) { return make_uint2(v.x, v.y); }
+__device__ __forceinline__ uint2 rec_hi(uint4 v) { return make_uint2(v.z, v.w); }
+__device__ __forceinline__ void set_lo(uint4& v, uint2 l) {
+  v.x = l.x;
+  v.y = l.y;
+}
+__device__ __forceinline__ void set_hi(uint4& v, uint2 h) {
+  v.z = h.x;
+  v.w = h.y;
+}
+__device__ __forceinline__ uint2 rec_lo(uint2 v) { return v; }
+__device__ __forceinline__ uint2 rec_hi(uint2 v) { return v; }
+__device__ __forceinline__ void set_lo(uint2& v, uint2 l) { v = l; }
+__device__ __forceinline__ void set_hi(uint2&, uint2) {}
+
 // Swap decision of the compaction network for the pair at offset i of a node
 // of 2*half slots whose marks prefix is P0 at its start and Ph at its middle.
 __device__ __forceinline__ bool swap_bit(uint32_t P0, uint32_t Ph, uint32_t half, uint32_t i) {
@@ -504,24 +521,28 @@ __device__ __forceinline__ void compact_xstage(T (&rv)[16], uint32_t (&tv)[16], 
 // distances below 16 pair registers, those up to 256 pair lanes by swizzles,
 // and longer ones exchange through the bin's own LDS slots.  On return rv
 // holds this lane's 16 slots after the compaction.
-template <int R, int LZ, bool FULL>
+// LOAD: read the bin's slots from LDS first; else rv and tv already hold
+// them (layout P).
+template <int R, int LZ, bool FULL, bool LOAD>
 __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* spfx,
-                                            uint32_t* swave, uint32_t klev, typename RecOf<R>::T (&rv)[16]) {
+                                            uint32_t* swave, uint32_t klev, typename RecOf<R>::T (&rv)[16],
+                                            uint32_t (&tv)[16]) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, ZP = Z + (Z >> 4), HL = Z >> 4;
   const uint32_t tid = threadIdx.x, m = Z << klev;
   const bool active = FULL || tid < (m >> 4);
   const uint32_t S = active ? tid / HL : 0u, lq = active ? tid % HL : 0u;
   const uint32_t bbase = S * ZP;
-  uint32_t tv[16];
+  if constexpr (LOAD) {
 #pragma unroll
-  for (uint32_t e = 0; e < 16; ++e) {
-    if (active) {
-      BOS_TR(0, 4, bbase + 17u * lq + e);
-      BOS_TR(0, 5, bbase + 17u * lq + e);
+    for (uint32_t e = 0; e < 16; ++e) {
+      if (active) {
+        BOS_TR(0, 4, bbase + 17u * lq + e);
+        BOS_TR(0, 5, bbase + 17u * lq + e);
+      }
+      rv[e] = active ? srec[bbase + 17u * lq + e] : zero_rec<T>();
+      tv[e] = active ? stag[bbase + 17u * lq + e] : kDummyTag;
     }
-    rv[e] = active ? srec[bbase + 17u * lq + e] : zero_rec<T>();
-    tv[e] = active ? stag[bbase + 17u * lq + e] : kDummyTag;
   }
   // prefix counts of the reals
   uint32_t pm[16];
@@ -608,11 +629,15 @@ __device__ __forceinline__ void compact_bin(typename RecOf<R>::T* srec, uint32_t
 // concatenate the bins (the addresses of both depend on the loads only, which
 // the method reveals).  FIN = 3: the bins are compacted, not sorted (their
 // reals keep the order the last level left).
-template <int R, int LZ, int FIN, bool FULL>
+// LOADED (FIN = 3): rv and tv already hold every bin's slots (layout P:
+// lane lq of bin S holds slots 16 lq .. 16 lq + 15); else they are read from
+// LDS.  rv and tv are scratch registers of the caller.
+template <int R, int LZ, int FIN, bool FULL, bool LOADED>
 __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, uint32_t klev,
                                              typename RecOf<R>::T* srec, uint32_t* stag, uint32_t* srhi,
                                              uint16_t* saux, const uint32_t* sload, uint32_t* spfx,
-                                             uint32_t* swave) {
+                                             uint32_t* swave, typename RecOf<R>::T (&rv)[16],
+                                             uint32_t (&tv)[16]) {
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, HL = Z >> 4;
   const uint32_t tid = threadIdx.x, NB = 1u << klev, m = Z << klev;
@@ -627,13 +652,14 @@ __device__ __forceinline__ void finish_split(const PassArgs& a, uint32_t blk, ui
     BOS_TR(0, 14, blk);
     a.scan[blk] = agg;
   }
-  T outr[16];
+  T (&outr)[16] = rv;
   uint32_t load = 0;
   if constexpr (FIN == 3) {
-    compact_bin<R, LZ, FULL>(srec, stag, spfx, swave, klev, outr);
+    compact_bin<R, LZ, FULL, !LOADED>(srec, stag, spfx, swave, klev, outr, tv);
     if (active) BOS_TR(0, 7, S);
     load = active ? sload[S] : 0u;
   } else {
+    static_assert(!LOADED, "the per-bin sorts read their bins from LDS");
     sort_bins<R, LZ, FIN, FULL>(a, blk, klev, srec, stag, srhi, saux, sload, outr, &load);
   }
   if (active) {
@@ -763,10 +789,15 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   constexpr bool HAS_B = LQ > 6;
   constexpr uint32_t HALF_LANES = TPM / 2;  // lanes per bucket in layout A
 
+  // 16-byte records exchange through LDS in two 8-byte halves (the tags go
+  // with the first): LDS holds 12 bytes per slot, as for 8-byte records.
+  constexpr bool HALF = lds_rec_bytes(R, Z, LAST && !SPLIT) == 8u && R == 16;
+  static_assert(!HALF || HAS_B, "two-half exchanges use layout B (Z >= 64)");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t klev = a.klev, NB = 1u << klev, m = Z << klev, mp = NB * ZP;
   T* srec = reinterpret_cast<T*>(smem);
-  uint32_t* stag = reinterpret_cast<uint32_t*>(smem + size_t(mp) * R);
+  uint2* shalf = reinterpret_cast<uint2*>(smem);  // HALF: one 8-byte half per slot
+  uint32_t* stag = reinterpret_cast<uint32_t*>(smem + size_t(mp) * lds_rec_bytes(R, Z, LAST && !SPLIT));
   uint32_t* spfx = stag + mp;          // m/16 marks-prefix entries (16-slot granularity)
   uint32_t* sload = spfx + (m >> 4);   // NB bin loads (last pass)
   uint32_t* soff = sload + NB;         // 2*NB words: output offsets (last pass)
@@ -881,50 +912,123 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   // layout A back (the generic placement of Algorithm 3.1)
   auto staged_first_load = [&](uint32_t item) {
     const uint64_t h = uint64_t(item) >> i0;
-    for (uint32_t t = tid; t < mp; t += nthr) {
-      BOS_TR(0, 4, t);
-      BOS_TR(0, 5, t);
-      srec[t] = zero_rec<T>();
-      stag[t] = kDummyTag;
-    }
-    lds_barrier();
     const uint64_t j_lo = h * NB;
     const uint64_t x_lo = (j_lo * n) >> L, x_hi = ((j_lo + NB) * n) >> L;
     const uint64_t c_lo = x_lo >> 3, c_hi = (x_hi + 7) >> 3;
-    for (uint64_t c = c_lo + tid; c < c_hi; c += nthr) {
-      const Philox4 ph = philox4x64_10(c, a.attempt, a.seed, 0);
-#pragma unroll
-      for (uint32_t w = 0; w < 8; ++w) {
-        const uint64_t x = c * 8 + w;
-        if (x < x_lo || x >= x_hi) continue;
-        const uint32_t word = uint32_t(ph.v[w >> 1] >> (32u * (w & 1u)));
-        const uint64_t j = ((x + 1) * B - 1) / n;
-        const uint64_t gs = (j * n) >> L;
-        const uint32_t S = uint32_t(j - j_lo), s = uint32_t(x - gs);
-        const uint32_t pi = S * ZP + s + (s >> 4);
-        BOS_TR(0, 3, x);
-        BOS_TR(0, 4, pi);
-        BOS_TR(0, 5, pi);
-        srec[pi] = X[x - a.x_off];
-        stag[pi] = L ? (word >> (32u - L)) : 0u;
+    // HALF: round 0 stages the first halves and the tags, round 1 the second
+    // halves; otherwise one round stages whole records
+    for (uint32_t round = 0; round < (HALF ? 2u : 1u); ++round) {
+      for (uint32_t t = tid; t < mp; t += nthr) {
+        BOS_TR(0, 4, t);
+        if constexpr (HALF) {
+          shalf[t] = make_uint2(0u, 0u);
+        } else {
+          srec[t] = zero_rec<T>();
+        }
+        if (round == 0) {
+          BOS_TR(0, 5, t);
+          stag[t] = kDummyTag;
+        }
       }
-    }
-    lds_barrier();
+      lds_barrier();
+      for (uint64_t c = c_lo + tid; c < c_hi; c += nthr) {
+        const Philox4 ph = philox4x64_10(c, a.attempt, a.seed, 0);
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) {
-      const uint32_t s = sb_load + e;
-      const uint32_t pi = S_load * ZP + s + (s >> 4);
-      if (active) {
-        BOS_TR(0, 4, pi);
-        BOS_TR(0, 5, pi);
+        for (uint32_t w = 0; w < 8; ++w) {
+          const uint64_t x = c * 8 + w;
+          if (x < x_lo || x >= x_hi) continue;
+          const uint32_t word = uint32_t(ph.v[w >> 1] >> (32u * (w & 1u)));
+          const uint64_t j = ((x + 1) * B - 1) / n;
+          const uint64_t gs = (j * n) >> L;
+          const uint32_t S = uint32_t(j - j_lo), s = uint32_t(x - gs);
+          const uint32_t pi = S * ZP + s + (s >> 4);
+          BOS_TR(0, 3, x);
+          BOS_TR(0, 4, pi);
+          if constexpr (HALF) {
+            shalf[pi] = round == 0 ? rec_lo(X[x - a.x_off]) : rec_hi(X[x - a.x_off]);
+          } else {
+            srec[pi] = X[x - a.x_off];
+          }
+          if (round == 0) {
+            BOS_TR(0, 5, pi);
+            stag[pi] = L ? (word >> (32u - L)) : 0u;
+          }
+        }
       }
-      rv[e] = active ? srec[pi] : zero_rec<T>();
-      tv[e] = active ? stag[pi] : kDummyTag;
+      lds_barrier();
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        const uint32_t s = sb_load + e;
+        const uint32_t pi = S_load * ZP + s + (s >> 4);
+        if (active) BOS_TR(0, 4, pi);
+        if constexpr (HALF) {
+          if (round == 0) {
+            if (active) BOS_TR(0, 5, pi);
+            set_lo(rv[e], active ? shalf[pi] : make_uint2(0u, 0u));
+            tv[e] = active ? stag[pi] : kDummyTag;
+          } else {
+            set_hi(rv[e], active ? shalf[pi] : make_uint2(0u, 0u));
+          }
+        } else {
+          if (active) BOS_TR(0, 5, pi);
+          rv[e] = active ? srec[pi] : zero_rec<T>();
+          tv[e] = active ? stag[pi] : kDummyTag;
+        }
+      }
+      lds_barrier();
     }
-    lds_barrier();
   };
 
   // ---- one block -----------------------------------------------------------
+  // padded LDS index of this lane's slot e in layout B of the MergeSplit of
+  // buckets at base0 / base1 (bB0, bB1: their layout-B lane bases; lB: the
+  // lane's low slot bits)
+  auto b_index = [&](uint32_t e, uint32_t b0, uint32_t b1, uint32_t bB0, uint32_t bB1, uint32_t lB) -> uint32_t {
+    const uint32_t sl = (e & 7u) << (LQ - 4);
+    // padded index of slot s = sl + lB: s + s/16 = sl + sl/16 + lB + lB/16
+    // holds because sl is a multiple of 16 whenever LQ >= 8; for smaller Z
+    // compute it directly
+    if constexpr (LQ >= 8) {
+      return ((e < 8) ? bB0 : bB1) + sl + (sl >> 4);
+    } else {
+      const uint32_t s2 = sl + lB;
+      return (e < 8 ? b0 : b1) + s2 + (s2 >> 4);
+    }
+  };
+  // HALF: second half of an exchange whose first halves (and tags) every
+  // lane has stored at its indices src(e): read the first halves and tags at
+  // dst(e), wait for the group, store this lane's second halves (still in rv)
+  // at src(e), wait, read them at dst(e).
+  // (the new first halves replace the stored ones in rv, which keeps the
+  // second halves until they are stored: no extra registers)
+  auto half_finish = [&](auto src, auto dst, auto sync) {
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      if (active) {
+        BOS_TR(0, 4, dst(e));
+        BOS_TR(0, 5, dst(e));
+      }
+      set_lo(rv[e], active ? shalf[dst(e)] : make_uint2(0u, 0u));
+      tv[e] = active ? stag[dst(e)] : kDummyTag;
+    }
+    sync();
+    if (active) {
+#pragma unroll
+      for (uint32_t e = 0; e < 16; ++e) {
+        BOS_TR(0, 4, src(e));
+        shalf[src(e)] = rec_hi(rv[e]);
+      }
+    }
+    sync();
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      if (active) BOS_TR(0, 4, dst(e));
+      set_hi(rv[e], active ? shalf[dst(e)] : make_uint2(0u, 0u));
+    }
+  };
+  // where the previous level left this lane's slots (layout B), for HALF
+  uint32_t pb0 = 0, pb1 = 0, pbB0 = 0, pbB1 = 0, plB = 0;
+
   auto process = [&](uint32_t item) {
     const uint64_t r = uint64_t(item) & ((1ull << i0) - 1ull), h = uint64_t(item) >> i0;
     for (uint32_t d = 0; d < klev; ++d) {
@@ -935,14 +1039,19 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       // slots 16*(lt mod TPM/2) + e
       const uint32_t baseA = (lt < HALF_LANES ? base0 : base1) + 17u * (lt % HALF_LANES);
       if (d > 0) {
+        if constexpr (HALF) {
+          half_finish([&](uint32_t e) { return b_index(e, pb0, pb1, pbB0, pbB1, plB); },
+                      [&](uint32_t e) { return baseA + e; }, [] { lds_barrier(); });
+        } else {
 #pragma unroll
-        for (uint32_t e = 0; e < 16; ++e) {
-          if (active) {
-            BOS_TR(0, 4, baseA + e);
-            BOS_TR(0, 5, baseA + e);
+          for (uint32_t e = 0; e < 16; ++e) {
+            if (active) {
+              BOS_TR(0, 4, baseA + e);
+              BOS_TR(0, 5, baseA + e);
+            }
+            rv[e] = active ? srec[baseA + e] : zero_rec<T>();
+            tv[e] = active ? stag[baseA + e] : kDummyTag;
           }
-          rv[e] = active ? srec[baseA + e] : zero_rec<T>();
-          tv[e] = active ? stag[baseA + e] : kDummyTag;
         }
       }
       // prefix counts of (class-0 reals, dummies) in 16-bit halves
@@ -1031,13 +1140,16 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       // lane lt in layout B: q = e << (LQ-4) | lb1 << (LQ-5) | lb0 << (LQ-6) | rest
       uint32_t baseB0 = 0, baseB1 = 0, lowB = 0;
       if constexpr (HAS_B) {
-        // A -> LDS
+        // A -> LDS (HALF: the first halves)
         if (active) {
 #pragma unroll
           for (uint32_t e = 0; e < 16; ++e) {
             BOS_TR(0, 4, baseA + e);
             BOS_TR(0, 5, baseA + e);
-            srec[baseA + e] = rv[e];
+            if constexpr (HALF)
+              shalf[baseA + e] = rec_lo(rv[e]);
+            else
+              srec[baseA + e] = rv[e];
             stag[baseA + e] = tv[e];
           }
         }
@@ -1048,6 +1160,12 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         lowB = (LQ >= 11) ? ((lb1 << (LQ - 5)) | (lb0 << (LQ - 6)) | rest) : lt;
         baseB0 = base0 + lowB + (lowB >> 4);
         baseB1 = base1 + lowB + (lowB >> 4);
+        // HALF: the exchange first (its registers are free before the prefixes load)
+        if constexpr (HALF) {
+          half_finish([&](uint32_t e) { return baseA + e; },
+                      [&](uint32_t e) { return b_index(e, base0, base1, baseB0, baseB1, lowB); },
+                      [] { lds_group_sync<TPM>(); });
+        }
         // marks prefix at node boundaries (multiples of 16 slots)
         uint32_t pv[16], pvh[16];
 #pragma unroll
@@ -1064,27 +1182,17 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
             pvh[e] = 0;
           }
         }
+        if constexpr (!HALF) {
 #pragma unroll
-        for (uint32_t e = 0; e < 16; ++e) {
-          const uint32_t sl = (e & 7u) << (LQ - 4);
-          const uint32_t off = sl + (sl >> 4);  // lowB + sl: padding adds (lowB + sl) >> 4
-          const uint32_t bb = (e < 8) ? baseB0 : baseB1;
-          // padded index of slot s = sl + lowB: s + s/16 = sl + sl/16 + lowB + lowB/16
-          // holds because sl is a multiple of 16 whenever LQ >= 8; for
-          // smaller Z compute it directly
-          uint32_t pi;
-          if constexpr (LQ >= 8) {
-            pi = bb + off;
-          } else {
-            const uint32_t s = sl + lowB;
-            pi = (e < 8 ? base0 : base1) + s + (s >> 4);
+          for (uint32_t e = 0; e < 16; ++e) {
+            const uint32_t pi = b_index(e, base0, base1, baseB0, baseB1, lowB);
+            if (active) {
+              BOS_TR(0, 4, pi);
+              BOS_TR(0, 5, pi);
+            }
+            rv[e] = active ? srec[pi] : zero_rec<T>();
+            tv[e] = active ? stag[pi] : kDummyTag;
           }
-          if (active) {
-            BOS_TR(0, 4, pi);
-            BOS_TR(0, 5, pi);
-          }
-          rv[e] = active ? srec[pi] : zero_rec<T>();
-          tv[e] = active ? stag[pi] : kDummyTag;
         }
         // -- layout B, q bit LQ-6 (lane bit 0), only for Z = 2048
         if constexpr (LQ - 6 >= 6) {
@@ -1140,24 +1248,27 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       // -- hand the level's output to LDS (next level or last-pass finish)
       if (d + 1 < klev || LAST) {
         if constexpr (HAS_B) {
-          // every lane rewrites exactly the layout-B slots it read: no barrier
+          // every lane rewrites exactly the layout-B slots it read: no
+          // barrier (HALF: the first halves; the next level's start, or the
+          // last pass's finish, completes the exchange)
           if (active) {
 #pragma unroll
             for (uint32_t e = 0; e < 16; ++e) {
-              const uint32_t sl = (e & 7u) << (LQ - 4);
-              uint32_t pi;
-              if constexpr (LQ >= 8) {
-                pi = ((e < 8) ? baseB0 : baseB1) + sl + (sl >> 4);
-              } else {
-                const uint32_t s = sl + lowB;
-                pi = (e < 8 ? base0 : base1) + s + (s >> 4);
-              }
+              const uint32_t pi = b_index(e, base0, base1, baseB0, baseB1, lowB);
               BOS_TR(0, 4, pi);
               BOS_TR(0, 5, pi);
-              srec[pi] = rv[e];
+              if constexpr (HALF)
+                shalf[pi] = rec_lo(rv[e]);
+              else
+                srec[pi] = rv[e];
               stag[pi] = tv[e];
             }
           }
+          pb0 = base0;
+          pb1 = base1;
+          pbB0 = baseB0;
+          pbB1 = baseB1;
+          plB = lowB;
         } else {
           if (active) {
 #pragma unroll
@@ -1196,6 +1307,21 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
     }
   };
 
+  // split last pass: every bin's slots in layout P, then compaction and
+  // the write of its reals
+  auto finish_bins_split = [&](uint32_t blk) {
+    if constexpr (HALF) {
+      const uint32_t HLn = Z >> 4;
+      const uint32_t S = active ? tid / HLn : 0u, lq = active ? tid % HLn : 0u;
+      const uint32_t pbase = S * ZP + 17u * lq;
+      half_finish([&](uint32_t e) { return b_index(e, pb0, pb1, pbB0, pbB1, plB); },
+                  [&](uint32_t e) { return pbase + e; }, [] { lds_barrier(); });
+      finish_split<R, LZ, SPLIT_FIN, FULL, true>(a, blk, klev, srec, stag, srhi, saux, sload, spfx, swave, rv, tv);
+    } else {
+      finish_split<R, LZ, SPLIT_FIN, FULL, false>(a, blk, klev, srec, stag, srhi, saux, sload, spfx, swave, rv, tv);
+    }
+  };
+
   if constexpr (BATCH && (!LAST || SPLIT)) {
     item0 += a.item_off;
     if (FIRST && !aligned) {
@@ -1205,7 +1331,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       finish_load(item0, tv);
     }
     process(item0);
-    if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item0, klev, srec, stag, srhi, saux, sload, spfx, swave);
+    if constexpr (SPLIT) finish_bins_split(item0);
   } else if constexpr (!LAST || SPLIT) {
     // persistent walk over blocks: item = blockIdx.x, + gridDim.x, ...  The
     // next block's loads are issued after the current one is done: with no
@@ -1227,7 +1353,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       const uint32_t next = item + gridDim.x;
       const bool has_next = next < iend;
       process(item);
-      if constexpr (SPLIT) finish_split<R, LZ, SPLIT_FIN, FULL>(a, item, klev, srec, stag, srhi, saux, sload, spfx, swave);
+      if constexpr (SPLIT) finish_bins_split(item);
       if (!has_next) break;
       item = next;
       lds_barrier();  // LDS of the previous block is no longer read
@@ -1263,11 +1389,25 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t
   route_run<R, LZ, MODE, false>(a, nitems, blockIdx.x);
 }
 
+// The passes after the first of 16-byte records whose LDS exchanges go in two
+// halves (kW3 below): compiled for three waves per SIMD (at most 168 VGPRs),
+// so that three workgroups of 2^3 Z slots share a CU, as their LDS allows.
+// The first pass, which also computes the labels, keeps the default
+// allocation (at three waves per SIMD it spills).
+template <int R, int LZ, int MODE>
+constexpr bool kW3 = R == 16 && lds_rec_bytes(R, 1u << LZ, (MODE & 2) && !(MODE & 4)) == 8u && LZ >= 6 &&
+                     !(MODE & 1);
+
+template <int R, int LZ, int MODE>
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void route_kernel_w3(
+    PassArgs a, uint32_t nitems) {
+  route_run<R, LZ, MODE, false>(a, nitems, blockIdx.x);
+}
+
 // Batched routing: segment s of the launch is one instance's pass; its blocks
 // are blockIdx.x in [blk_start[s], blk_start[s+1]).
-template <int R, int LZ, int MODE>
-__global__ __launch_bounds__(kMaxThreads) void route_kernel_b(const PassArgs* segs, const uint32_t* blk_start,
-                                                              uint32_t nsegs) {
+template <int R, int LZ, int MODE, bool W3>
+__device__ __forceinline__ void route_b_body(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs) {
   uint32_t lo = 0, hi = nsegs;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -1278,6 +1418,16 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel_b(const PassArgs* se
   }
   const PassArgs a = segs[lo];
   route_run<R, LZ, MODE, true>(a, 0u, blockIdx.x - blk_start[lo]);
+}
+template <int R, int LZ, int MODE>
+__global__ __launch_bounds__(kMaxThreads) void route_kernel_b(const PassArgs* segs, const uint32_t* blk_start,
+                                                              uint32_t nsegs) {
+  route_b_body<R, LZ, MODE, false>(segs, blk_start, nsegs);
+}
+template <int R, int LZ, int MODE>
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void route_kernel_b_w3(
+    const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs) {
+  route_b_body<R, LZ, MODE, true>(segs, blk_start, nsegs);
 }
 
 }  // namespace bos

@@ -5,25 +5,40 @@
 
 namespace bos {
 
+// The kernel a routing launch runs (route_kernel, or its three-waves form).
+template <int R, int LZ, int MODE>
+const void* route_fn() {
+  if constexpr (kW3<R, LZ, MODE>)
+    return reinterpret_cast<const void*>(&route_kernel_w3<R, LZ, MODE>);
+  else
+    return reinterpret_cast<const void*>(&route_kernel<R, LZ, MODE>);
+}
+template <int R, int LZ, int MODE>
+const void* route_b_fn() {
+  if constexpr (kW3<R, LZ, MODE>)
+    return reinterpret_cast<const void*>(&route_kernel_b_w3<R, LZ, MODE>);
+  else
+    return reinterpret_cast<const void*>(&route_kernel_b<R, LZ, MODE>);
+}
+
 template <int R, int LZ, int MODE>
 hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hipStream_t s) {
   BOS_TRACE_BIND();
   const uint32_t m = (1u << LZ) << a.klev;
   uint32_t threads = m >> 4;
   if (threads < 64) threads = 64;
-  const uint32_t lds = pass_lds_bytes(R, 1u << LZ, a.klev, (MODE & 2) && a.fin == 0);
+  const uint32_t lds = pass_lds_bytes(R, 1u << LZ, a.klev, (MODE & 2) && a.fin == 0, (MODE & 2) && !(MODE & 4));
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&route_kernel<R, LZ, MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute(route_fn<R, LZ, MODE>(), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   static uint32_t occ_lds = 0, occ_blocks = 0;
   if (occ_lds != lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&route_kernel<R, LZ, MODE>),
-                                                     int(threads), lds) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, route_fn<R, LZ, MODE>(), int(threads), lds) != hipSuccess ||
+        nb < 1)
       nb = 1;
     occ_lds = lds;
     occ_blocks = uint32_t(nb);
@@ -33,7 +48,10 @@ hipError_t launch_route_t(const PassArgs& a, uint32_t nitems, uint32_t grid, hip
   // other pass is a persistent walk over the blocks
   const bool ticketed = (MODE & 2) && !(MODE & 4);
   const uint32_t g = ticketed ? nitems : (persistent < nitems ? persistent : nitems);
-  hipLaunchKernelGGL((route_kernel<R, LZ, MODE>), dim3(g), dim3(threads), lds, s, a, nitems);
+  if constexpr (kW3<R, LZ, MODE>)
+    hipLaunchKernelGGL((route_kernel_w3<R, LZ, MODE>), dim3(g), dim3(threads), lds, s, a, nitems);
+  else
+    hipLaunchKernelGGL((route_kernel<R, LZ, MODE>), dim3(g), dim3(threads), lds, s, a, nitems);
   return hipGetLastError();
 }
 
@@ -45,12 +63,16 @@ hipError_t launch_route_bt(const PassArgs* segs, const uint32_t* blk_start, uint
   BOS_TRACE_BIND();
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&route_kernel_b<R, LZ, MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute(route_b_fn<R, LZ, MODE>(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((route_kernel_b<R, LZ, MODE>), dim3(blocks), dim3(threads), lds, s, segs, blk_start, nsegs);
+  if constexpr (kW3<R, LZ, MODE>)
+    hipLaunchKernelGGL((route_kernel_b_w3<R, LZ, MODE>), dim3(blocks), dim3(threads), lds, s, segs, blk_start,
+                       nsegs);
+  else
+    hipLaunchKernelGGL((route_kernel_b<R, LZ, MODE>), dim3(blocks), dim3(threads), lds, s, segs, blk_start, nsegs);
   return hipGetLastError();
 }
 
@@ -106,7 +128,8 @@ hipError_t launch_orp_finish_e(const FinishArgs& a, uint32_t grid, hipStream_t s
     occ = uint32_t(nb);
     attr_set = true;
   }
-  const uint64_t groups = (a.nbins + BPW - 1) / BPW;
+  const uint64_t nb = a.gb_hi ? a.gb_hi - a.gb_lo : a.nbins;  // a staged launch finishes bins [gb_lo, gb_hi)
+  const uint64_t groups = (nb + BPW - 1) / BPW;
   const uint64_t cap = uint64_t(grid) * occ;
   const uint32_t g = uint32_t(groups < cap ? groups : cap);
   if (g == 0) return hipSuccess;
