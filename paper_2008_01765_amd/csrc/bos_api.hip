@@ -728,58 +728,69 @@ bos_status build_batch(const bos_instance* inst, const uint64_t* ns, uint32_t co
   for (const BatchJob& j : b->jobs)
     if (j.n && !j.special) maxP = std::max(maxP, j.pl.P);
   for (uint32_t t = 0; t < maxP; ++t) {
-    for (int mode : {3, 1, 0, 2, 6}) {
-      for (uint32_t lz = 4; lz <= 11; ++lz) {
-        std::vector<PassArgs> segs;
-        std::vector<uint32_t> starts;
-        uint32_t blocks = 0, threads = 64, lds = 0;
-        for (const BatchJob& j : b->jobs) {
-          if (!j.n || j.special || t >= j.pl.P || j.pl.lz != lz) continue;
-          const bool first = t == 0, last = t + 1 == j.pl.P;
-          if (((first ? 1 : 0) | (last ? 2 : 0) | (last && j.split ? 4 : 0)) != mode) continue;
-          PassArgs a;
-          std::memset(&a, 0, sizeof(a));
-          const Plan& pl = j.pl;
-          unsigned long long* status = reinterpret_cast<unsigned long long*>(j.ws + pl.off_status);
-          a.x_in = j.in;
-          a.out = j.start;
-          a.rec_in = j.ws + pl.off_rec[(t + 1) & 1];
-          a.tag_in = reinterpret_cast<const uint32_t*>(j.ws + pl.off_tag[(t + 1) & 1]);
-          a.rec_out = j.ws + pl.off_rec[t & 1];
-          a.tag_out = reinterpret_cast<uint32_t*>(j.ws + pl.off_tag[t & 1]);
-          a.status = status;
-          a.ticket = reinterpret_cast<uint32_t*>(status + 1);
-          a.scan = status + 2;
-          a.n = pl.n;
-          a.buckets = pl.B;
-          a.seed = j.seed;
-          a.z = pl.Z;
-          a.lz = pl.lz;
-          a.levels = pl.L;
-          a.level0 = pl.lev0[t];
-          a.klev = pl.klev[t];
-          a.attempt = 0;
-          a.fin = 1;
-          if (last && j.split) a.loads = reinterpret_cast<uint32_t*>(j.ws + pl.off_loads);
-          segs.push_back(a);
-          starts.push_back(blocks);
-          blocks += uint32_t(pl.B >> pl.klev[t]);
-          threads = std::max(threads, uint32_t((pl.Z << pl.klev[t]) >> 4));
-          lds = std::max(lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false, (mode & 2) && !(mode & 4)));
-        }
-        if (segs.empty()) continue;
-        BLaunch l;
-        l.kind = 1;
-        l.mode = mode;
-        l.lz = lz;
-        l.nsegs = uint32_t(segs.size());
-        l.blocks = blocks;
-        l.threads = threads;
-        l.lds = lds;
-        l.tab = push_table(tab, segs);
-        l.aux = push_table(tab, starts);
-        b->launches.push_back(l);
-      }
+    // one launch per (pass kind, Z, levels of the pass): every block of a
+    // launch has the same LDS size, so none is held to a larger block's
+    // occupancy.  Groups are keyed (kind rank, log2 Z, levels) and launched
+    // in key order.
+    struct Group {
+      std::vector<PassArgs> segs;
+      std::vector<uint32_t> starts;
+      uint32_t blocks = 0, threads = 64, lds = 0;
+      int mode = 0;
+      uint32_t lz = 0;
+    };
+    std::map<uint32_t, Group> groups;
+    for (const BatchJob& j : b->jobs) {
+      if (!j.n || j.special || t >= j.pl.P) continue;
+      const bool first = t == 0, last = t + 1 == j.pl.P;
+      const int mode = (first ? 1 : 0) | (last ? 2 : 0) | (last && j.split ? 4 : 0);
+      const uint32_t rank = mode == 3 ? 0u : mode == 1 ? 1u : mode == 0 ? 2u : mode == 2 ? 3u : 4u;
+      const Plan& pl = j.pl;
+      Group& g = groups[(rank * 16u + pl.lz) * 16u + pl.klev[t]];
+      g.mode = mode;
+      g.lz = pl.lz;
+      PassArgs a;
+      std::memset(&a, 0, sizeof(a));
+      unsigned long long* status = reinterpret_cast<unsigned long long*>(j.ws + pl.off_status);
+      a.x_in = j.in;
+      a.out = j.start;
+      a.rec_in = j.ws + pl.off_rec[(t + 1) & 1];
+      a.tag_in = reinterpret_cast<const uint32_t*>(j.ws + pl.off_tag[(t + 1) & 1]);
+      a.rec_out = j.ws + pl.off_rec[t & 1];
+      a.tag_out = reinterpret_cast<uint32_t*>(j.ws + pl.off_tag[t & 1]);
+      a.status = status;
+      a.ticket = reinterpret_cast<uint32_t*>(status + 1);
+      a.scan = status + 2;
+      a.n = pl.n;
+      a.buckets = pl.B;
+      a.seed = j.seed;
+      a.z = pl.Z;
+      a.lz = pl.lz;
+      a.levels = pl.L;
+      a.level0 = pl.lev0[t];
+      a.klev = pl.klev[t];
+      a.attempt = 0;
+      a.fin = 1;
+      if (last && j.split) a.loads = reinterpret_cast<uint32_t*>(j.ws + pl.off_loads);
+      g.segs.push_back(a);
+      g.starts.push_back(g.blocks);
+      g.blocks += uint32_t(pl.B >> pl.klev[t]);
+      g.threads = std::max(g.threads, uint32_t((pl.Z << pl.klev[t]) >> 4));
+      g.lds = std::max(g.lds, pass_lds_bytes(rec, pl.Z, pl.klev[t], false, (mode & 2) && !(mode & 4)));
+    }
+    for (const auto& kv : groups) {
+      const Group& g = kv.second;
+      BLaunch l;
+      l.kind = 1;
+      l.mode = g.mode;
+      l.lz = g.lz;
+      l.nsegs = uint32_t(g.segs.size());
+      l.blocks = g.blocks;
+      l.threads = g.threads;
+      l.lds = g.lds;
+      l.tab = push_table(tab, g.segs);
+      l.aux = push_table(tab, g.starts);
+      b->launches.push_back(l);
     }
   }
   {
@@ -1335,11 +1346,13 @@ constexpr uint64_t kStepBackfillCap = 1ull << 23;
 
 size_t step_round_bytes(uint32_t count) {
   // every job adds at most one entry of each kind; each table starts aligned
-  // (fill, 2 per route group of at most 5 kinds x 8 Z, strip, 5 tile sizes,
-  // two-way and four-way merge passes)
+  // (fill, 2 per route group -- at most one group per job, and at most 5
+  // kinds x 8 Z x 12 levels --, strip, 5 tile sizes, two-way and four-way
+  // merge passes)
+  const size_t groups = std::min<size_t>(count, 5 * 8 * 12);
   return size_t(count) * (2 * sizeof(FillSeg) + sizeof(PassArgs) + 4 + sizeof(StripSeg) + 2 * sizeof(SortSeg) +
                           sizeof(M4Seg)) +
-         92 * kAlign;
+         (2 * groups + 12) * kAlign;
 }
 
 size_t bos_step_workspace_bytes(uint32_t count) {
@@ -1470,7 +1483,7 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
     size_t o_fill = 0, o_strip = 0, o_tile[5] = {0, 0, 0, 0, 0}, o_merge = 0, o_m4 = 0;
     uint32_t nfill = 0, nstrip = 0, ntile[5] = {0, 0, 0, 0, 0}, nmerge = 0, nm4 = 0;
     uint32_t sblocks = 0, tiles[5] = {0, 0, 0, 0, 0}, mtiles = 0, m4[5] = {0, 0, 0, 0, 0};
-    std::map<uint32_t, RouteGroup> route;  // key: mode * 16 + lz
+    std::map<uint32_t, RouteGroup> route;  // key: (mode * 16 + lz) * 16 + levels of the pass
     std::vector<uint32_t> whole;  // jobs routed by the per-job path in this round
   };
   const uint32_t kTiles[5] = {4096, 2048, 1024, 8192, 16384};
@@ -1540,7 +1553,7 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
           rd.sblocks += pl.nblocks_last;
         }
         const uint32_t items = uint32_t(pl.B >> pl.klev[ph]);
-        RouteGroup& g = rd.route[uint32_t(mode) * 16u + pl.lz];
+        RouteGroup& g = rd.route[(uint32_t(mode) * 16u + pl.lz) * 16u + pl.klev[ph]];
         if (g.args.empty()) g.items0 = items;
         g.args.push_back(a);
         g.starts.push_back(g.blocks);
@@ -1638,8 +1651,8 @@ bos_status step_impl(bos_job* jobs, uint32_t count, bos_rec rec, const bos_param
     }
     for (const auto& kv : rd.route) {
       if (e != hipSuccess) break;
-      const int m = int(kv.first / 16u);
-      const uint32_t lz = kv.first % 16u;
+      const int m = int(kv.first / 256u);
+      const uint32_t lz = (kv.first / 16u) % 16u;
       const RouteGroup& g = kv.second;
       if (g.args.size() == 1)  // one job: the persistent kernel of the single-sort path
         e = launch_route(R, g.args[0], (m & 1) != 0, (m & 2) != 0, g.items0, num_cus(), s, (m & 4) != 0);
