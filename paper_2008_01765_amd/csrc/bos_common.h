@@ -245,13 +245,12 @@ __device__ __forceinline__ void trace_idx(uint32_t which, uint32_t cls, uint64_t
 #endif
 
 // Dynamic LDS bytes of a routing block (must match the carve in the kernel).
-// LDS bytes per slot of a routing pass's records.  16-byte records at
-// 64 <= Z <= 512 go through LDS in two 8-byte halves (the second after the
-// first has been read), so a block needs 12 bytes of LDS per slot as with
-// 8-byte records; the fused last pass keeps whole records (its per-bin sorts
-// hold them in LDS).
+// LDS bytes per slot of a routing pass's records.  At 64 <= Z <= 512 records
+// go through LDS in two halves (the second after the first has been read),
+// so a block needs half a record and a tag of LDS per slot; the fused last
+// pass keeps whole records (its per-bin sorts hold them in LDS).
 __host__ __device__ constexpr uint32_t lds_rec_bytes(int rec, uint32_t z, bool fused) {
-  return (rec == 16 && z >= 64 && z <= 512 && !fused) ? 8u : uint32_t(rec);
+  return (z >= 64 && z <= 512 && !fused) ? uint32_t(rec) / 2u : uint32_t(rec);
 }
 
 __host__ __device__ inline uint32_t pass_lds_bytes(int rec, uint32_t z, uint32_t klev, bool last_shuffle,

@@ -77,8 +77,8 @@ __device__ __forceinline__ uint4 dpp(uint4 v) {
 
 __device__ __forceinline__ uint32_t brev_k(uint32_t x, uint32_t k) { return k ? (__brev(x) >> (32u - k)) : 0u; }
 
-// Halves of a 16-byte record for two-half LDS exchanges (identity for 8-byte
-// records, which never take that path).
+// Halves of a record for two-half LDS exchanges (8 bytes of a 16-byte
+// record, 4 of an 8-byte one).
 __device__ __forceinline__ uint2 rec_lo(uint4 v) { return make_uint2(v.x, v.y); }
 __device__ __forceinline__ uint2 rec_hi(uint4 v) { return make_uint2(v.z, v.w); }
 __device__ __forceinline__ void set_lo(uint4& v, uint2 l) {
@@ -89,10 +89,19 @@ __device__ __forceinline__ void set_hi(uint4& v, uint2 h) {
   v.z = h.x;
   v.w = h.y;
 }
-__device__ __forceinline__ uint2 rec_lo(uint2 v) { return v; }
-__device__ __forceinline__ uint2 rec_hi(uint2 v) { return v; }
-__device__ __forceinline__ void set_lo(uint2& v, uint2 l) { v = l; }
-__device__ __forceinline__ void set_hi(uint2&, uint2) {}
+__device__ __forceinline__ uint32_t rec_lo(uint2 v) { return v.x; }
+__device__ __forceinline__ uint32_t rec_hi(uint2 v) { return v.y; }
+__device__ __forceinline__ void set_lo(uint2& v, uint32_t l) { v.x = l; }
+__device__ __forceinline__ void set_hi(uint2& v, uint32_t h) { v.y = h; }
+template <typename T> struct HalfOf;
+template <> struct HalfOf<uint4> {
+  using H = uint2;
+  static __device__ __forceinline__ H zero() { return make_uint2(0u, 0u); }
+};
+template <> struct HalfOf<uint2> {
+  using H = uint32_t;
+  static __device__ __forceinline__ H zero() { return 0u; }
+};
 
 // Swap decision of the compaction network for the pair at offset i of a node
 // of 2*half slots whose marks prefix is P0 at its start and Ph at its middle.
@@ -789,14 +798,16 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   constexpr bool HAS_B = LQ > 6;
   constexpr uint32_t HALF_LANES = TPM / 2;  // lanes per bucket in layout A
 
-  // 16-byte records exchange through LDS in two 8-byte halves (the tags go
-  // with the first): LDS holds 12 bytes per slot, as for 8-byte records.
-  constexpr bool HALF = lds_rec_bytes(R, Z, LAST && !SPLIT) == 8u && R == 16;
+  // Records exchange through LDS in two halves (the tags go with the
+  // first): LDS holds half a record and a tag per slot, so more workgroups
+  // share a CU.
+  constexpr bool HALF = lds_rec_bytes(R, Z, LAST && !SPLIT) < uint32_t(R);
   static_assert(!HALF || HAS_B, "two-half exchanges use layout B (Z >= 64)");
+  using H = typename HalfOf<T>::H;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t klev = a.klev, NB = 1u << klev, m = Z << klev, mp = NB * ZP;
   T* srec = reinterpret_cast<T*>(smem);
-  uint2* shalf = reinterpret_cast<uint2*>(smem);  // HALF: one 8-byte half per slot
+  H* shalf = reinterpret_cast<H*>(smem);  // HALF: one half record per slot
   uint32_t* stag = reinterpret_cast<uint32_t*>(smem + size_t(mp) * lds_rec_bytes(R, Z, LAST && !SPLIT));
   uint32_t* spfx = stag + mp;          // m/16 marks-prefix entries (16-slot granularity)
   uint32_t* sload = spfx + (m >> 4);   // NB bin loads (last pass)
@@ -921,7 +932,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
       for (uint32_t t = tid; t < mp; t += nthr) {
         BOS_TR(0, 4, t);
         if constexpr (HALF) {
-          shalf[t] = make_uint2(0u, 0u);
+          shalf[t] = HalfOf<T>::zero();
         } else {
           srec[t] = zero_rec<T>();
         }
@@ -964,10 +975,10 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         if constexpr (HALF) {
           if (round == 0) {
             if (active) BOS_TR(0, 5, pi);
-            set_lo(rv[e], active ? shalf[pi] : make_uint2(0u, 0u));
+            set_lo(rv[e], active ? shalf[pi] : HalfOf<T>::zero());
             tv[e] = active ? stag[pi] : kDummyTag;
           } else {
-            set_hi(rv[e], active ? shalf[pi] : make_uint2(0u, 0u));
+            set_hi(rv[e], active ? shalf[pi] : HalfOf<T>::zero());
           }
         } else {
           if (active) BOS_TR(0, 5, pi);
@@ -1008,7 +1019,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
         BOS_TR(0, 4, dst(e));
         BOS_TR(0, 5, dst(e));
       }
-      set_lo(rv[e], active ? shalf[dst(e)] : make_uint2(0u, 0u));
+      set_lo(rv[e], active ? shalf[dst(e)] : HalfOf<T>::zero());
       tv[e] = active ? stag[dst(e)] : kDummyTag;
     }
     sync();
@@ -1023,7 +1034,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
 #pragma unroll
     for (uint32_t e = 0; e < 16; ++e) {
       if (active) BOS_TR(0, 4, dst(e));
-      set_hi(rv[e], active ? shalf[dst(e)] : make_uint2(0u, 0u));
+      set_hi(rv[e], active ? shalf[dst(e)] : HalfOf<T>::zero());
     }
   };
   // where the previous level left this lane's slots (layout B), for HALF
@@ -1389,18 +1400,20 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel(PassArgs a, uint32_t
   route_run<R, LZ, MODE, false>(a, nitems, blockIdx.x);
 }
 
-// The passes after the first of 16-byte records whose LDS exchanges go in two
-// halves (kW3 below): compiled for three waves per SIMD (at most 168 VGPRs),
-// so that three workgroups of 2^3 Z slots share a CU, as their LDS allows.
-// The first pass, which also computes the labels, keeps the default
-// allocation (at three waves per SIMD it spills).
+// The passes after the first whose LDS exchanges go in two halves (kW3
+// below) are compiled for a register budget that lets as many workgroups
+// share a CU as their LDS allows: three waves per SIMD (at most 168 VGPRs)
+// for 16-byte records, four (at most 128) for 8-byte ones.  The first pass,
+// which also computes the labels, keeps the default allocation (it would
+// spill).
 template <int R, int LZ, int MODE>
-constexpr bool kW3 = R == 16 && lds_rec_bytes(R, 1u << LZ, (MODE & 2) && !(MODE & 4)) == 8u && LZ >= 6 &&
-                     !(MODE & 1);
+constexpr bool kW3 = lds_rec_bytes(R, 1u << LZ, (MODE & 2) && !(MODE & 4)) < uint32_t(R) && LZ >= 6 && !(MODE & 1);
+template <int R>
+constexpr int kWavesPerSimd = R == 16 ? 3 : 4;
 
 template <int R, int LZ, int MODE>
-__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void route_kernel_w3(
-    PassArgs a, uint32_t nitems) {
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<R>, 8))) void
+route_kernel_w3(PassArgs a, uint32_t nitems) {
   route_run<R, LZ, MODE, false>(a, nitems, blockIdx.x);
 }
 
@@ -1425,8 +1438,8 @@ __global__ __launch_bounds__(kMaxThreads) void route_kernel_b(const PassArgs* se
   route_b_body<R, LZ, MODE, false>(segs, blk_start, nsegs);
 }
 template <int R, int LZ, int MODE>
-__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void route_kernel_b_w3(
-    const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs) {
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<R>, 8))) void
+route_kernel_b_w3(const PassArgs* segs, const uint32_t* blk_start, uint32_t nsegs) {
   route_b_body<R, LZ, MODE, true>(segs, blk_start, nsegs);
 }
 
