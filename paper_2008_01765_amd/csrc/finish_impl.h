@@ -9,28 +9,32 @@
 // into block offsets.  This kernel then, per bin:
 //   1. sorts the bin's Z slots in record order (key, payload), dummies last,
 //      so that the permutation below does not depend on the order in which
-//      the butterfly delivered the reals;
+//      the butterfly delivered the reals, and leaves the sorted bin in LDS;
 //   2. gives the p-th real the 64-bit key r(gb*Z + p): word (g mod 4) of the
 //      Philox4x64-10 block g/4 under key (seed, 1) and counter (g/4, attempt);
-//   3. sorts the bin by (r, p), dummies last (a uniformly random order of
+//   3. orders the bin by (r, p), dummies last (a uniformly random order of
 //      the reals: random labels followed by a sort, the construction of
-//      Section 4.1).  The reals are in record order, so p increases with the
-//      record and (r, record) is the same order.  The network compares r
-//      alone; the keys depend on (seed, bin, p) only, and when two of a bin's
-//      reals (or its last real and first dummy) end up with equal keys, a
-//      flag that depends on no data sends the whole finish through a second
-//      launch with the (r, record) comparator;
-//   4. writes the reals to out[offset of the bin ..].
-// Both sorts are bitonic networks over all Z slots, so every address but the
-// final writes (which depend on the loads, revealed by the method) is a
-// function of (Z, bin) only.
+//      Section 4.1).  The network sorts one 64-bit word per slot, the top
+//      64 - log2 Z bits of r with p below them, which is the (r, p) order
+//      while no two reals share their top key bits; the keys depend on
+//      (seed, attempt, bin, p) only, and when two of a bin's reals (or its
+//      last real and first dummy) do share them, a flag that depends on no
+//      data sends the whole finish through a second launch that sorts
+//      (r, record) pairs, the (r, p) order since p follows the records;
+//   4. writes output slot j of the bin, j < load, from the LDS copy of the
+//      record of rank p(j) to out[offset of the bin + j].
+// Both sorts are bitonic networks over all Z slots and the ranks p(j) are a
+// function of the keys, so every address but the final writes (which depend
+// on the loads, revealed by the method) is a function of (Z, seed, attempt,
+// bin) only.
 //
 // Layout: lane lq of the bin's Z/16 lanes holds slots 16 lq + e (e = 0..15) in
 // registers, each record as the 64-bit word(s) that order it (key in the high
 // half for 8-byte records).  Stages on slot bits 0..3 pair registers; stages on higher bits
 // pair lanes lq ^ X through DPP (X = 1, 2), ds_swizzle (X = 4, 8, 16) or a
-// lane permute (X = 32).  No LDS memory is used for Z <= 1024; Z = 2048
-// (two waves per bin) sorts through LDS with the routing kernel's padded bin
+// lane permute (X = 32).  Up to Z = 1024 a bin's lanes are one wave's and the
+// only LDS is the bin's record copy of step 4 (the routing kernel's padded
+// bin layout); Z = 2048 (two waves per bin) sorts through LDS with that
 // layout.
 #pragma once
 #include "route_impl.h"
@@ -66,18 +70,17 @@ __device__ __forceinline__ ElemRK<T> e_xor(const ElemRK<T>& a) {
 }
 
 // Comparators of the networks below: CMP 0 = e_less of the element type
-// (record order), 1 = the random key alone, 2 = (random key, record).
+// (record order, or the packed key words of the fast launch), 2 = (random
+// key, record).
 template <int CMP, typename E>
 __device__ __forceinline__ bool lt(const E& a, const E& b) {
   if constexpr (CMP == 0) return e_less(a, b);
-  else if constexpr (CMP == 1) return a.key < b.key;
   else return (a.key < b.key) | ((a.key == b.key) & f_less(a.r, b.r));
 }
 
 // Compare-exchange of two registers (x gets the smaller when ascending) and
 // with the element of lane lq ^ X (the lower lane keeps the smaller when
-// ascending).  Elements equal under the comparator are byte-identical, or
-// (CMP 1) have equal keys, which the caller detects and re-sorts.
+// ascending).  Elements equal under the comparator are byte-identical.
 template <int CMP, typename E>
 __device__ __forceinline__ void cx_r(E& x, E& y, bool asc) {
   const bool sw = lt<CMP>(y, x) == asc;
@@ -130,10 +133,12 @@ __device__ __forceinline__ void reg_phases(E (&v)[16], uint32_t lq) {
 
 }  // namespace finish_detail
 
-// Dynamic LDS bytes of the finish kernel (only Z = 2048 sorts through LDS).
-__host__ __device__ inline uint32_t finish_lds_bytes(int rec, uint32_t lz) {
-  if (lz < 11) return 0;
+// Dynamic LDS bytes of the finish kernel: up to Z = 1024 the fast launch
+// stages each bin's records (in record order) for the final gather and the
+// exact launch uses none; Z = 2048 sorts through LDS.
+__host__ __device__ inline uint32_t finish_lds_bytes(int rec, uint32_t lz, bool exact) {
   const uint32_t z = 1u << lz, zp = z + (z >> 4), bpw = kFinishThreads / (z >> 4);
+  if (lz < 11) return exact ? 0u : bpw * zp * uint32_t(rec);
   return (bpw * zp * (uint32_t(rec) + 10u) + 15u) & ~15u;
 }
 
@@ -201,26 +206,36 @@ __device__ __forceinline__ FE1<R> e_xor(const FE1<R>& a) { return {f_xor<X>(a.r)
 template <uint32_t X, int R>
 __device__ __forceinline__ FE2<R> e_xor(const FE2<R>& a) { return {lane_xor64<X>(a.key), f_xor<X>(a.r)}; }
 
+// Key-order element of the fast launch: the top 64 - LZ bits of the key with
+// the record rank p in the low LZ bits (dummies all ones).  While no two of a
+// bin's reals share their top key bits this orders the reals as (key, p).
+struct FE3 {
+  uint64_t w;
+};
+__device__ __forceinline__ bool e_less(const FE3& a, const FE3& b) { return a.w < b.w; }
+__device__ __forceinline__ FE3 e_sel(bool c, const FE3& a, const FE3& b) { return {c ? a.w : b.w}; }
+template <uint32_t X>
+__device__ __forceinline__ FE3 e_xor(const FE3& a) { return {lane_xor64<X>(a.w)}; }
+
 // True when this lane holds two adjacent slots p, p+1 <= load (reals and the
-// first dummy) with equal keys; the pair across the lane boundary is checked
-// by the lower lane.
-template <int R, uint32_t HL>
-__device__ __forceinline__ bool key_tie(const FE2<R> (&w)[16], uint32_t lq, uint32_t load) {
+// first dummy) whose words agree in their key bits; the pair across the lane
+// boundary is checked by the lower lane.
+template <int LZ, uint32_t HL>
+__device__ __forceinline__ bool word_tie(const FE3 (&w)[16], uint32_t lq, uint32_t load) {
   bool tie = false;
 #pragma unroll
   for (uint32_t e = 0; e + 1 < 16; ++e) {
     const uint32_t p = 16u * lq + e;
-    tie |= (p < load) & (w[e].key == w[e + 1].key);
+    tie |= (p < load) & ((w[e].w >> LZ) == (w[e + 1].w >> LZ));
   }
   if constexpr (HL > 1) {
-    // first key of lane lq + 1 (within the bin)
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t src = (lane + 1u) & 63u;
-    const uint32_t lo = uint32_t(__shfl(int(uint32_t(w[0].key)), int(src), 64));
-    const uint32_t hi = uint32_t(__shfl(int(uint32_t(w[0].key >> 32)), int(src), 64));
-    const uint64_t nk = (uint64_t(hi) << 32) | lo;
+    const uint32_t lo = uint32_t(__shfl(int(uint32_t(w[0].w)), int(src), 64));
+    const uint32_t hi = uint32_t(__shfl(int(uint32_t(w[0].w >> 32)), int(src), 64));
+    const uint64_t nw = (uint64_t(hi) << 32) | lo;
     const uint32_t p = 16u * lq + 15u;
-    tie |= (lq + 1u < HL) & (p < load) & (w[15].key == nk);
+    tie |= (lq + 1u < HL) & (p < load) & ((w[15].w >> LZ) == (nw >> LZ));
   }
   return tie;
 }
@@ -233,7 +248,7 @@ __device__ __forceinline__ bool key_tie(const FE2<R> (&w)[16], uint32_t lq, uint
 // set, and then redoes every bin with the (key, record) comparator.  The
 // flag depends on the keys only, never on the data.
 template <int R, int LZ, bool EXACT>
-__global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(R == 8 ? 3 : 2))) void orp_finish_kernel(FinishArgs a) {
+__global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(R == 8 ? (EXACT ? 3 : 4) : 2))) void orp_finish_kernel(FinishArgs a) {
   using namespace finish_detail;
   using T = typename RecOf<R>::T;
   constexpr uint32_t Z = 1u << LZ, HL = Z >> 4, BPW = kFinishThreads / HL, ZP = Z + (Z >> 4);
@@ -277,37 +292,77 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
         v[e] = FE1<R>{(act && p < load) ? f_load(binned[src + e]) : f_max<R>()};
       }
       reg_phases<LZ, 1, 0>(v, lq);
-      // 2. the per-bin keys of the reals (reals hold slots 0 .. load-1)
-      FE2<R> w[16];
+      if constexpr (!EXACT) {
+        // the bin in record order to LDS (rank p at padded slot p + p/16;
+        // the bin's lanes are one wave's)
+        T* sbin = reinterpret_cast<T*>(smem) + S * ZP;
+        if (act) {
 #pragma unroll
-      for (uint32_t e4 = 0; e4 < 4; ++e4) {
-        const uint32_t p0 = 16u * lq + 4u * e4;
-        const Philox4 ph = philox4x64_10(((gb << LZ) + p0) >> 2, a.attempt, a.seed, 1);
-#pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-          const uint32_t e = 4u * e4 + q;
-          w[e] = FE2<R>{p0 + q < load ? ph.v[q] : ~0ull, v[e].r};
-        }
-      }
-      // 3. order by the keys; ties (a wave-wide, data-independent branch)
-      //    are sorted again by (key, record)
-      if constexpr (EXACT) reg_phases<LZ, 1, 2>(w, lq);
-      else reg_phases<LZ, 1, 1>(w, lq);
-      // 4. the reals to their place in the output
-      if (act) {
-#pragma unroll
-        for (uint32_t e = 0; e < 16; ++e) {
-          const uint32_t p = 16u * lq + e;
-          if (p < load && off + p < a.n) {
-            BOS_TR(0, 21, off + p);
-            out[off + p - a.out0] = f_store(w[e].r);
+          for (uint32_t e = 0; e < 16; ++e) {
+            BOS_TR(0, 4, S * ZP + 17u * lq + e);
+            sbin[17u * lq + e] = f_store(v[e].r);
           }
         }
-      }
-      if constexpr (!EXACT) {
-        if (act && key_tie<R, HL>(w, lq, load)) {
+        // 2. rank p's key r(gb*Z + p), its top bits with p below them
+        FE3 w[16];
+#pragma unroll
+        for (uint32_t e4 = 0; e4 < 4; ++e4) {
+          const uint32_t p0 = 16u * lq + 4u * e4;
+          const Philox4 ph = philox4x64_10(((gb << LZ) + p0) >> 2, a.attempt, a.seed, 1);
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t e = 4u * e4 + q;
+            w[e] = FE3{p0 + q < load ? ((ph.v[q] >> LZ) << LZ) | (p0 + q) : ~0ull};
+          }
+        }
+        // 3. order by the words (their ranks then follow the keys)
+        reg_phases<LZ, 1, 0>(w, lq);
+        lds_wave_sync();
+        // 4. output slot j of the bin takes the record of rank w[j] mod Z
+        if (act) {
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            const uint32_t j = 16u * lq + e;
+            if (j < load && off + j < a.n) {
+              const uint32_t p = uint32_t(w[e].w) & (Z - 1u);
+              BOS_TR(0, 4, S * ZP + p + (p >> 4));
+              BOS_TR(0, 21, off + j);
+              out[off + j - a.out0] = sbin[p + (p >> 4)];
+            }
+          }
+        }
+        // two reals with the same top key bits: the exact launch redoes it
+        if (act && word_tie<LZ, HL>(w, lq, load)) {
           BOS_TR(0, 24, 0);
           atomicOr(a.tie, 1ull);
+        }
+      } else {
+        // exact launch: 2. the per-bin keys of the reals (reals hold slots
+        // 0 .. load-1) with their records
+        FE2<R> w[16];
+#pragma unroll
+        for (uint32_t e4 = 0; e4 < 4; ++e4) {
+          const uint32_t p0 = 16u * lq + 4u * e4;
+          const Philox4 ph = philox4x64_10(((gb << LZ) + p0) >> 2, a.attempt, a.seed, 1);
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t e = 4u * e4 + q;
+            w[e] = FE2<R>{p0 + q < load ? ph.v[q] : ~0ull, v[e].r};
+          }
+        }
+        // 3. order by (key, record), which is (key, p) as the reals are in
+        //    record order
+        reg_phases<LZ, 1, 2>(w, lq);
+        // 4. the reals to their place in the output
+        if (act) {
+#pragma unroll
+          for (uint32_t e = 0; e < 16; ++e) {
+            const uint32_t p = 16u * lq + e;
+            if (p < load && off + p < a.n) {
+              BOS_TR(0, 21, off + p);
+              out[off + p - a.out0] = f_store(w[e].r);
+            }
+          }
         }
       }
     } else if constexpr (!EXACT) {

@@ -115,7 +115,7 @@ template <int R, int LZ, bool EXACT>
 hipError_t launch_orp_finish_e(const FinishArgs& a, uint32_t grid, hipStream_t s) {
   BOS_TRACE_BIND();
   constexpr uint32_t HL = (1u << LZ) >> 4, BPW = kFinishThreads / HL;
-  const uint32_t lds = finish_lds_bytes(R, LZ);
+  const uint32_t lds = finish_lds_bytes(R, LZ, EXACT);
   static bool attr_set = false;
   static uint32_t occ = 0;
   const void* fn = reinterpret_cast<const void*>(&orp_finish_kernel<R, LZ, EXACT>);
