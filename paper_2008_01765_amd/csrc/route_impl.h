@@ -779,7 +779,8 @@ __device__ __forceinline__ void finish_bins(const PassArgs& a, uint32_t blk, uin
 // R: record bytes; LZ: log2 Z (4..11); MODE bit 0 = first pass, bit 1 = last,
 // bit 2 = split form of the last pass (bins compacted and written to rec_out,
 // then scan + strip; the sorts only), bit 4 = the launch has exactly Z 2^klev / 16 lanes
-// (all of them hold slots, so no lane needs a guard).
+// (all of them hold slots, so no lane needs a guard), bit 5 = a first pass whose
+// groups all start on a multiple of 8 elements (no staged loads).
 // Body of one routing launch.  BATCH = false: a persistent workgroup walks
 // over items blockIdx.x, + gridDim.x, ... (last pass: tickets).  BATCH = true:
 // the workgroup runs the single item `item0` of one instance of a batch.
@@ -788,6 +789,10 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   using T = typename RecOf<R>::T;
   constexpr bool FIRST = (MODE & 1) != 0, LAST = (MODE & 2) != 0, SPLIT = (MODE & 4) != 0;
   constexpr bool FULL = (MODE & 16) != 0;  // every lane holds slots: no lane guards
+  // a first pass whose groups all start on a multiple of 8 elements: built
+  // without the staged loads (and their registers)
+  constexpr bool ALIGNED = (MODE & 32) != 0;
+  static_assert(!ALIGNED || (FIRST && !LAST), "the aligned form is a first pass that is not also the last");
   static_assert(!SPLIT || (LAST && !FIRST), "the split form is a last pass that is not also the first");
   // the split form serves the sorts: it compacts its bins, and the strip puts
   // in order the bins that straddle a tile of the comparison sort's first
@@ -828,7 +833,7 @@ __device__ __forceinline__ void route_run(const PassArgs& a, uint32_t nitems, ui
   // whole Philox blocks); otherwise inputs are staged through LDS
   // (B = 2^L: divisions by B are shifts; a 64-bit division by a run-time
   // value would be a long software sequence in every lane)
-  const bool aligned = (n & ((8ull << L) - 1ull)) == 0;
+  const bool aligned = ALIGNED || (n & ((8ull << L) - 1ull)) == 0;
 
   // ---- load one block into layout-A registers of level 0 -------------------
   // level 0 pairs LDS buckets 2ms and 2ms+1; lane lt holds slots 16*(lt mod

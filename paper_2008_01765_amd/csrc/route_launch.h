@@ -92,7 +92,10 @@ template <int R, int LZ>
 hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t grid, hipStream_t s) {
   // blocks of at least 1024 slots fill whole waves: the unguarded kernels
   const bool full = ((uint32_t(1u << LZ) << a.klev) >> 4) >= 64u;
-  switch (mode | (full ? 16 : 0)) {
+  // a first pass (not also the last) whose groups all start on a multiple of
+  // 8 elements runs the build without the staged loads
+  const bool aligned = mode == 1 && full && (a.n & ((8ull << a.levels) - 1ull)) == 0;
+  switch (mode | (full ? 16 : 0) | (aligned ? 32 : 0)) {
     case 0: return launch_route_t<R, LZ, 0>(a, nitems, grid, s);
     case 1: return launch_route_t<R, LZ, 1>(a, nitems, grid, s);
     case 2: return launch_route_t<R, LZ, 2>(a, nitems, grid, s);
@@ -103,6 +106,7 @@ hipError_t launch_route_m(const PassArgs& a, int mode, uint32_t nitems, uint32_t
     case 18: return launch_route_t<R, LZ, 18>(a, nitems, grid, s);
     case 19: return launch_route_t<R, LZ, 19>(a, nitems, grid, s);
     case 22: return launch_route_t<R, LZ, 22>(a, nitems, grid, s);
+    case 49: return launch_route_t<R, LZ, 49>(a, nitems, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
