@@ -392,10 +392,12 @@ __global__ __launch_bounds__(kMThreads<R>) void merge_tile_kernel_b(const SortSe
 // records (4029 of 4096 for 8-byte records, 2013 of 2048 for 16-byte ones;
 // aligning the second merge result adds at most ITEMS-1 slots).
 
-// A four-way tile is merged by 512 threads, each with half the records of a
-// two-way pass's thread.
+// A four-way tile is merged by 256 threads with as many records each as a
+// two-way pass's thread: fewer, longer merges per thread halve the merge-path
+// searches per record (8 records per thread over 512 threads, or 32 over 128,
+// were slower).
 template <int R>
-constexpr uint32_t kM4Items = kMItems<R> / 2;
+constexpr uint32_t kM4Items = kMItems<R>;
 template <int R>
 constexpr uint32_t kM4Threads = kMTile<R> / kM4Items<R>;
 constexpr uint32_t kSplM = 60;                  // samples per tile
