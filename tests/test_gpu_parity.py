@@ -59,6 +59,7 @@ ORP_CASES = [  # n, rec, Z, k
     (5000, 16, 128, 1),       # last pass with 16 of 64 lanes holding bins
     (9000, 8, 256, 1),        # last pass with 32 of 64 lanes holding bins
     (1 << 14, 16, 32, 3),
+    (1 << 17, 16, 1024, 2),   # per-bin finish with a whole wave per bin, 16-byte records
     (1 << 16, 8, 512, 1),
     (1 << 16, 8, 512, 2),
     (1 << 16, 8, 512, 3),
@@ -92,7 +93,7 @@ def test_orp_bit_exact(ora, n, rec, z, k, generic):
 
 @pytest.mark.parametrize("n,rec,z,k", [(1 << 16, 8, 512, 3), (1 << 17, 16, 256, 2), (100000, 8, 1024, 3),
                                        (12345, 8, 64, 3), (1 << 14, 16, 32, 3), (1024, 8, 16, 4),
-                                       (1 << 16, 8, 128, 4)])
+                                       (1 << 16, 8, 128, 4), (1 << 17, 16, 1024, 2)])
 def test_orp_exact_finish_launch(ora, n, rec, z, k):
     # The per-bin finish's second launch (the (key, record) comparator, taken
     # when two random keys of a bin tie) forced on: the same output.
