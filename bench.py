@@ -239,7 +239,26 @@ def bench_ooc(args, torch, bos, inputs):
             fn()
         torch.cuda.synchronize()
         rates[name + "_GB/s"] = round(3 * (1 << 30) / (time.perf_counter() - t0) / 1e9, 1)
-    del blk, hblk
+    # both directions at once (two streams), the ceiling of a pass that
+    # streams its slot arrays in and out together
+    blk2 = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    hblk2 = bos.pinned_empty((1 << 30,), torch.uint8)
+    s_in, s_out = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def both():
+        with torch.cuda.stream(s_in):
+            blk.copy_(hblk, non_blocking=True)
+        with torch.cuda.stream(s_out):
+            hblk2.copy_(blk2, non_blocking=True)
+
+    both()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        both()
+    torch.cuda.synchronize()
+    rates["both_directions_GB/s"] = round(3 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9, 1)
+    del blk, hblk, blk2, hblk2
     res = {"workload": "n=2^%d records of %d B in pinned host memory, Z=%d" % (args.log2n, rec, args.z),
            "device_workspace_GiB": args.ooc_dev_gib, "host_link": rates}
     bz = None

@@ -1971,8 +1971,10 @@ bos_status sort_batched_sequential(const bos_instance* inst, uint32_t count, bos
 // when the chunk covers whole groups of 2^(i+k) buckets and 2^k contiguous
 // segments otherwise, and whose output is one contiguous range of buckets
 // (the consecutive-bucket structure of Section 4.3).  Chunks alternate between
-// two streams and two staging sets, so one chunk's copies overlap another's
-// kernels.  The per-bin finish (bos_orp) or strip (bos_sort) streams the bins
+// two staging sets and run as a pipeline over three streams (input copies,
+// kernels, output copies; OocPipe), so that the next chunk's input copy runs
+// while this chunk's output copy does: the host link carries both directions
+// at once.  The per-bin finish (bos_orp) or strip (bos_sort) streams the bins
 // the same way; the sort's comparison phase is a two-pass external sort: runs
 // sorted on the device, then output segments cut by sample splitters, each
 // gathered from the runs, sorted on the device and written once.
@@ -1982,8 +1984,9 @@ constexpr uint64_t kMaxNHost = 1ull << 36;
 constexpr int kOocDevices = 64;
 
 struct OocStreams {
-  hipStream_t st[2] = {nullptr, nullptr};
+  hipStream_t st[3] = {nullptr, nullptr, nullptr};  // input copies, kernels, output copies
   hipEvent_t ev = nullptr;
+  hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_k[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
 };
 std::mutex g_ooc_mu;
 OocStreams g_ooc[kOocDevices];
@@ -2029,10 +2032,14 @@ bos_status ooc_streams(OocStreams** out) {
   OocStreams& o = g_ooc[dev];
   if (!o.st[0]) {
     // default priority (no priority variants)
-    if (hipStreamCreateWithFlags(&o.st[0], hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&o.st[1], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&o.ev, hipEventDisableTiming) != hipSuccess)
-      return BOS_ERR_HIP;
+    for (int i = 0; i < 3; ++i)
+      if (hipStreamCreateWithFlags(&o.st[i], hipStreamNonBlocking) != hipSuccess) return BOS_ERR_HIP;
+    if (hipEventCreateWithFlags(&o.ev, hipEventDisableTiming) != hipSuccess) return BOS_ERR_HIP;
+    for (int b = 0; b < 2; ++b)
+      if (hipEventCreateWithFlags(&o.ev_in[b], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&o.ev_k[b], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&o.ev_out[b], hipEventDisableTiming) != hipSuccess)
+        return BOS_ERR_HIP;
   }
   *out = &o;
   return BOS_OK;
@@ -2055,11 +2062,37 @@ hipError_t h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
 hipError_t d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
   return bytes ? hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
 }
-hipError_t sync2(OocStreams* o) {
-  hipError_t e = hipStreamSynchronize(o->st[0]);
-  if (e == hipSuccess) e = hipStreamSynchronize(o->st[1]);
+hipError_t sync3(OocStreams* o) {
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamSynchronize(o->st[i]);
   return e;
 }
+
+// One chunk of a pipelined loop over staging set b = chunk mod 2: its input
+// copies go on in() (which first waits until the set's previous output copy
+// has left), its kernels on kernels() (after the input copies), its output
+// copies on out() (after the kernels), and done() marks the set free again.
+// Every loop ends with sync3.
+struct OocPipe {
+  OocStreams* o;
+  int b = 0;
+  hipError_t start(uint64_t chunk, hipStream_t* s) {
+    b = int(chunk & 1u);
+    *s = o->st[0];
+    return chunk >= 2 ? hipStreamWaitEvent(o->st[0], o->ev_out[b], 0) : hipSuccess;
+  }
+  hipError_t kernels(hipStream_t* s) {
+    *s = o->st[1];
+    hipError_t e = hipEventRecord(o->ev_in[b], o->st[0]);
+    return e == hipSuccess ? hipStreamWaitEvent(o->st[1], o->ev_in[b], 0) : e;
+  }
+  hipError_t out(hipStream_t* s) {
+    *s = o->st[2];
+    hipError_t e = hipEventRecord(o->ev_k[b], o->st[1]);
+    return e == hipSuccess ? hipStreamWaitEvent(o->st[2], o->ev_k[b], 0) : e;
+  }
+  hipError_t done() { return hipEventRecord(o->ev_out[b], o->st[2]); }
+};
 
 // One attempt's routing passes, chunk by chunk (the last in split form: bins
 // compacted into host slot array (P - 1) & 1, loads and block counts on the
@@ -2084,9 +2117,12 @@ hipError_t ooc_route(const Plan& pl, const bos_params& q, uint32_t attempt, cons
     char* hout_rec = hws + hl.off_rec[t & 1];
     char* hout_tag = hws + hl.off_tag[t & 1];
     uint32_t c = 0;
+    OocPipe pipe{o};
     for (uint64_t it0 = 0; it0 < items; it0 += cb, ++c) {
       const int b = int(c & 1u);
-      hipStream_t s = o->st[b];
+      hipStream_t s = nullptr;
+      e = pipe.start(c, &s);
+      if (e != hipSuccess) return e;
       char* set = dws + dl.off_stage + size_t(b) * 2 * cap * (R + 4);
       char* d_in_rec = set;
       uint32_t* d_in_tag = reinterpret_cast<uint32_t*>(set + cap * R);
@@ -2146,14 +2182,18 @@ hipError_t ooc_route(const Plan& pl, const bos_params& q, uint32_t attempt, cons
       if (last) a.loads = reinterpret_cast<uint32_t*>(dws + dl.off_loads);
       const uint32_t kind = first ? BOS_K_ROUTE_FIRST : last ? BOS_K_ROUTE_LAST : BOS_K_ROUTE_MID;
       const uint64_t slot_bytes = ns_out * (uint64_t(R) + 4);
+      e = pipe.kernels(&s);
+      if (e != hipSuccess) return e;
       prof_begin(kind, t, slot_bytes * 2, s);
       e = launch_route(R, a, first, last, uint32_t(cb), num_cus(), s, last);
       prof_end(s);
+      if (e == hipSuccess) e = pipe.out(&s);
       if (e == hipSuccess) e = d2h(hout_rec + out_slot0 * R, d_out_rec, ns_out * R, s);
       if (e == hipSuccess && !last) e = d2h(hout_tag + out_slot0 * 4, d_out_tag, ns_out * 4, s);
+      if (e == hipSuccess) e = pipe.done();
       if (e != hipSuccess) return e;
     }
-    e = sync2(o);
+    e = sync3(o);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -2201,14 +2241,18 @@ hipError_t ooc_finish(const Plan& pl, const bos_params& q, uint32_t attempt, boo
   const uint64_t bslots = uint64_t(pl.Z) << klast;  // slots per routing block
   const uint64_t cblk = std::min<uint64_t>(pl.nblocks_last, cap / bslots);
   uint32_t c = 0;
+  OocPipe pipe{o};
   for (uint64_t b0 = 0; b0 < pl.nblocks_last; b0 += cblk, ++c) {
     const uint64_t b1 = std::min<uint64_t>(b0 + cblk, pl.nblocks_last);
     const int sb = int(c & 1u);
-    hipStream_t s = o->st[sb];
+    hipStream_t s = nullptr;
+    e = pipe.start(c, &s);
+    if (e != hipSuccess) return e;
     char* d_bin = dws + dl.off_stage + size_t(sb) * 2 * cap * R;
     char* d_out = d_bin + cap * R;
     const uint64_t slot0 = b0 * bslots, out0 = boff[b0], out1 = boff[b1];
     e = h2d(d_bin, binned + slot0 * R, (b1 - b0) * bslots * R, s);
+    if (e == hipSuccess) e = pipe.kernels(&s);
     if (e != hipSuccess) return e;
     if (sort) {
       prof_begin(BOS_K_STRIP, c, 2 * (out1 - out0) * R, s);
@@ -2236,10 +2280,12 @@ hipError_t ooc_finish(const Plan& pl, const bos_params& q, uint32_t attempt, boo
       e = launch_orp_finish(R, pl.lz, f, num_cus(), s);
     }
     prof_end(s);
+    if (e == hipSuccess) e = pipe.out(&s);
     if (e == hipSuccess) e = d2h(dst + out0 * R, d_out, (out1 - out0) * R, s);
+    if (e == hipSuccess) e = pipe.done();
     if (e != hipSuccess) return e;
   }
-  return sync2(o);
+  return sync3(o);
 }
 
 // Unsigned lexicographic (key, payload) order of two host records.
@@ -2297,18 +2343,23 @@ bos_status ooc_comparison_sort(const Plan& pl, char* a, char* out, char* dws, co
   if (e != hipSuccess) return BOS_ERR_HIP;
   const uint64_t m = (n + rl - 1) / rl;
   char* dst_runs = m == 1 ? out : a;  // a single run goes straight to out
+  OocPipe pipe{o};
   for (uint64_t r = 0; r < m; ++r) {
     const int sb = int(r & 1u);
-    hipStream_t s = o->st[sb];
+    hipStream_t s = nullptr;
     const uint64_t len = std::min(rl, n - r * rl);
     char* set = dws + dl.off_stage + size_t(sb) * set_bytes;
     void* result = nullptr;
-    e = h2d(set, a + r * rl * R, len * R, s);
+    e = pipe.start(r, &s);
+    if (e == hipSuccess) e = h2d(set, a + r * rl * R, len * R, s);
+    if (e == hipSuccess) e = pipe.kernels(&s);
     if (e == hipSuccess) e = sort_on_device(sb, len, s, &result);
+    if (e == hipSuccess) e = pipe.out(&s);
     if (e == hipSuccess) e = d2h(dst_runs + r * rl * R, result, len * R, s);
+    if (e == hipSuccess) e = pipe.done();
     if (e != hipSuccess) return BOS_ERR_HIP;
   }
-  if (sync2(o) != hipSuccess) return BOS_ERR_HIP;
+  if (sync3(o) != hipSuccess) return BOS_ERR_HIP;
   if (m > 1) {
     // samples every q records of every run, q the largest power of two with m q <= rl / 2
     uint64_t q = pow2_floor(rl / (2 * m));
@@ -2359,11 +2410,13 @@ bos_status ooc_comparison_sort(const Plan& pl, char* a, char* out, char* dws, co
     for (uint64_t r = 0; r < m; ++r) cut.push_back(std::min(rl, n - r * rl));
     const uint64_t nseg = cut.size() / m - 1;
     uint64_t base = 0;
+    OocPipe spipe{o};
     for (uint64_t j = 0; j < nseg; ++j) {
       const int sb = int(j & 1u);
-      hipStream_t s = o->st[sb];
+      hipStream_t s = nullptr;
       char* set = dws + dl.off_stage + size_t(sb) * set_bytes;
       uint64_t len = 0;
+      e = spipe.start(j, &s);
       for (uint64_t r = 0; r < m && e == hipSuccess; ++r) {
         const uint64_t c0 = cut[j * m + r], c1 = cut[(j + 1) * m + r];
         if (c1 < c0 || len + (c1 - c0) > rl) return BOS_ERR_INTERNAL;  // the segment bound above
@@ -2371,13 +2424,16 @@ bos_status ooc_comparison_sort(const Plan& pl, char* a, char* out, char* dws, co
         len += c1 - c0;
       }
       void* result = nullptr;
+      if (e == hipSuccess) e = spipe.kernels(&s);
       if (e == hipSuccess) e = sort_on_device(sb, len, s, &result);
+      if (e == hipSuccess) e = spipe.out(&s);
       if (e == hipSuccess) e = d2h(out + base * R, result, len * R, s);
+      if (e == hipSuccess) e = spipe.done();
       if (e != hipSuccess) return BOS_ERR_HIP;
       base += len;
     }
     if (base != n) return BOS_ERR_INTERNAL;
-    if (sync2(o) != hipSuccess) return BOS_ERR_HIP;
+    if (sync3(o) != hipSuccess) return BOS_ERR_HIP;
   }
   unsigned long long eh = 0;
   if (d2h(&eh, err, 8, o->st[0]) != hipSuccess || hipStreamSynchronize(o->st[0]) != hipSuccess) return BOS_ERR_HIP;
@@ -2411,7 +2467,7 @@ bos_status ooc_impl(const void* in, void* out, uint64_t n, bos_rec rec, const bo
   // order after the caller's stream
   hipStream_t cs = static_cast<hipStream_t>(stream);
   if (hipEventRecord(o->ev, cs) != hipSuccess || hipStreamWaitEvent(o->st[0], o->ev, 0) != hipSuccess ||
-      hipStreamWaitEvent(o->st[1], o->ev, 0) != hipSuccess)
+      hipStreamWaitEvent(o->st[1], o->ev, 0) != hipSuccess || hipStreamWaitEvent(o->st[2], o->ev, 0) != hipSuccess)
     return BOS_ERR_HIP;
   char* h = static_cast<char*>(hws);
   char* d = static_cast<char*>(dws);
