@@ -298,9 +298,12 @@ bos_status bos_bitonic_sort(const void* in, void* out, uint64_t n, bos_rec rec, 
  * bos_host_device_bytes(n, rec, p) bytes; a larger one gives larger chunks.
  * Host buffers allocated with hipHostMalloc (pinned) are copied at full DMA
  * rate and let copies overlap kernels; pageable memory works, slower.
- * The call orders itself after `stream`, runs on two internal streams of the
- * current device and returns when `out` is written (overflow retries as with
- * BOS_SYNC, whatever params->flags says).  Errors: INVALID_ARG (as bos_sort,
+ * The call orders itself after `stream`, runs on three internal streams of
+ * the current device (input copies, kernels, output copies, pipelined over
+ * two staging halves of dev_ws) and returns when `out` is written (overflow
+ * retries as with BOS_SYNC, whatever params->flags says).  The internal
+ * streams are shared by every out-of-core call on a device: such calls that
+ * overlap (two host threads) must be serialised by the caller.  Errors: INVALID_ARG (as bos_sort,
  * n > 2^36), WORKSPACE (a workspace too small), UNSUPPORTED (a plan of one
  * routing pass, or Z = 8: use the in-core calls), OVERFLOW, INSECURE_Z, HIP,
  * INTERNAL (a consistency check of the comparison phase failed). */
