@@ -18,8 +18,8 @@
  * Readings taken where the paper leaves a choice open:
  *   - B = 1 when 2n <= Z (no levels); groups are the balanced floor split
  *     [floor(jn/B), floor((j+1)n/B)).
- *   - "(i+1)-st most significant bit of the key" at level i is bit L-1-i of the
- *     L-bit label, so the final bin index equals the label.
+ *   - Level i routes by the label bit that is i+1 places from the top, that is
+ *     bit L-1-i of the L-bit label, so the final bin index equals the label.
  *   - MergeSplit appends real elements in scan order (A0's slots, then A1's),
  *     so its outputs are stable; the paper defines them as sets.
  *   - Overflow means strictly more than Z real elements in an output bucket.
