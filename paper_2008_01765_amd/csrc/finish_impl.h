@@ -240,6 +240,95 @@ __device__ __forceinline__ bool word_tie(const FE3 (&w)[16], uint32_t lq, uint32
   return tie;
 }
 
+// Record sort of a bin of 2^LZ slots (LZ = 8..10, the bin's 2^(LZ-4) lanes in
+// one wave) with every compare-exchange on two registers of one lane: three
+// layouts put one group of slot-index bits in the register index, P = bits
+// 0-3 (lane = bits 4 .. LZ-1), R = bits 4-7 (lane = bits 0-3 and 8 .. LZ-1)
+// and Q = bits LZ-4 .. LZ-1 (lane = bits 0 .. LZ-5); a phase whose stages
+// reach bits above 3 moves the bin through its LDS slots (padded s + s/16)
+// into those layouts and back, in place of lane exchanges.  Addresses depend
+// on (lane, register) only.
+template <int LZ, int G>
+__device__ __forceinline__ uint32_t bslot(uint32_t l, uint32_t e) {
+  if constexpr (G == 0) return (l << 4) | e;
+  else if constexpr (G == 1) return ((l >> 4) << 8) | (e << 4) | (l & 15u);
+  else return (e << (LZ - 4)) | l;
+}
+template <int LZ, int KK, int G, int JB, typename E>
+__device__ __forceinline__ void lay_stages(E (&v)[16], uint32_t l) {
+  if constexpr (JB >= 0) {
+    constexpr uint32_t hb = 1u << JB;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      if (e & hb) continue;
+      const bool asc = KK == LZ || ((bslot<LZ, G>(l, e) >> KK) & 1u) == 0u;
+      cx_r<0>(v[e], v[e | hb], asc);
+    }
+    lay_stages<LZ, KK, G, JB - 1>(v, l);
+  }
+}
+// Padded LDS slot of register e in layout G, bslot + bslot/16, written as a
+// lane base plus e times a constant (immediate offsets, no per-register
+// address registers): P 17 l + e, R 272 (l/16) + l mod 16 + 17 e, Q l + l/16
+// + e (2^(LZ-4) + 2^(LZ-8)).
+template <int LZ, int G>
+__device__ __forceinline__ uint32_t pad_base(uint32_t l) {
+  if constexpr (G == 0) return 17u * l;
+  else if constexpr (G == 1) return 272u * (l >> 4) + (l & 15u);
+  else return l + (l >> 4);
+}
+template <int LZ, int G>
+constexpr uint32_t pad_step() {
+  return G == 0 ? 1u : G == 1 ? 17u : (1u << (LZ - 4)) + (1u << (LZ - 8));
+}
+// (the bin's LDS slots hold the ordering words themselves while the network
+// runs: no conversion to the record layout between layouts)
+template <int LZ, int G, int R>
+__device__ __forceinline__ void lay_st(const FE1<R> (&v)[16], FRec<R>* sb, uint32_t l, uint32_t trb) {
+  constexpr uint32_t st = pad_step<LZ, G>();
+  const uint32_t pb = pad_base<LZ, G>(l);
+  FRec<R>* b = sb + pb;
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) {
+    BOS_TR(0, 4, trb + pb + e * st);
+    b[e * st] = v[e].r;
+  }
+}
+template <int LZ, int G, int R>
+__device__ __forceinline__ void lay_ld(FE1<R> (&v)[16], const FRec<R>* sb, uint32_t l, uint32_t trb) {
+  constexpr uint32_t st = pad_step<LZ, G>();
+  const uint32_t pb = pad_base<LZ, G>(l);
+  const FRec<R>* b = sb + pb;
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) {
+    BOS_TR(0, 4, trb + pb + e * st);
+    v[e] = FE1<R>{b[e * st]};
+  }
+}
+// Phases KK .. LZ; v holds layout P on entry and exit.
+template <int LZ, int KK, int R>
+__device__ __forceinline__ void lay_phases(FE1<R> (&v)[16], FRec<R>* sb, uint32_t l, uint32_t trb) {
+  if constexpr (KK <= LZ) {
+    if constexpr (KK >= 5) {
+      lay_st<LZ, 0>(v, sb, l, trb);
+      lds_wave_sync();
+      if constexpr (KK >= 9) {
+        lay_ld<LZ, 2>(v, sb, l, trb);
+        lay_stages<LZ, KK, 2, KK - 1 - (LZ - 4)>(v, l);  // slot bits KK-1 .. LZ-4
+        lay_st<LZ, 2>(v, sb, l, trb);
+        lds_wave_sync();
+      }
+      lay_ld<LZ, 1>(v, sb, l, trb);
+      lay_stages<LZ, KK, 1, (KK >= 9 ? LZ - 9 : KK - 5)>(v, l);  // slot bits min(KK-1, LZ-5) .. 4
+      lay_st<LZ, 1>(v, sb, l, trb);
+      lds_wave_sync();
+      lay_ld<LZ, 0>(v, sb, l, trb);
+    }
+    lay_stages<LZ, KK, 0, (KK >= 4 ? 3 : KK - 1)>(v, l);  // slot bits min(KK-1, 3) .. 0
+    lay_phases<LZ, KK + 1>(v, sb, l, trb);
+  }
+}
+
 }  // namespace finish_detail
 
 // EXACT = false: the key sort compares the random keys alone and raises
@@ -285,13 +374,32 @@ __global__ __launch_bounds__(kFinishThreads) __attribute__((amdgpu_waves_per_eu(
     if constexpr (LZ <= 10) {
       // 1. record order, dummies (maximal record) last
       FE1<R> v[16];
+      if constexpr (!EXACT && LZ >= 8) {
+        // the bin's reals read in layout Q (the bin's lanes take consecutive
+        // slots), moved to layout P through the bin's LDS slots, then the
+        // layout-switching network
+        FRec<R>* sb = reinterpret_cast<FRec<R>*>(smem) + S * ZP;
+        static_assert(sizeof(FRec<R>) == sizeof(T), "a slot holds a record or its ordering words");
+        const uint64_t b0 = (gb << LZ) - a.bin_slot0;
 #pragma unroll
-      for (uint32_t e = 0; e < 16; ++e) {
-        const uint32_t p = 16u * lq + e;
-        if (act && p < load) BOS_TR(0, 20, src + e);
-        v[e] = FE1<R>{(act && p < load) ? f_load(binned[src + e]) : f_max<R>()};
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t p = bslot<LZ, 2>(lq, e);
+          if (act && p < load) BOS_TR(0, 20, b0 + p);
+          v[e] = FE1<R>{(act && p < load) ? f_load(binned[b0 + p]) : f_max<R>()};
+        }
+        lay_st<LZ, 2>(v, sb, lq, S * ZP);
+        lds_wave_sync();
+        lay_ld<LZ, 0>(v, sb, lq, S * ZP);
+        lay_phases<LZ, 1>(v, sb, lq, S * ZP);
+      } else {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e) {
+          const uint32_t p = 16u * lq + e;
+          if (act && p < load) BOS_TR(0, 20, src + e);
+          v[e] = FE1<R>{(act && p < load) ? f_load(binned[src + e]) : f_max<R>()};
+        }
+        reg_phases<LZ, 1, 0>(v, lq);
       }
-      reg_phases<LZ, 1, 0>(v, lq);
       if constexpr (!EXACT) {
         // the bin in record order to LDS (rank p at padded slot p + p/16;
         // the bin's lanes are one wave's)

@@ -84,9 +84,93 @@ __device__ __forceinline__ uint64_t merge_path(const T* A, uint64_t la, const T*
 template <uint32_t TLOG>
 constexpr uint32_t tile_threads() { return (1u << TLOG) / 16u; }
 
-// Sort one tile of 2^TLOG records of buf in place with the register bitonic
-// network of the per-bin finish (record order; slots past n sort last as the
-// maximal record).
+// Tiles of 4096 records: every compare-exchange of the bitonic network pairs
+// two registers of one lane.  Three layouts of the tile over 256 lanes x 16
+// registers put one 4-bit group of the slot index in the register index:
+// P = bits 0-3 (lane = bits 4-11), R = bits 4-7 (lane = bits 0-3 and 8-11),
+// Q = bits 8-11 (lane = bits 0-7).  A phase whose stages reach a higher group
+// moves the tile through LDS (padded slot s + s/16) into that group's layout
+// and back, so no stage exchanges records between lanes (a lane exchange costs
+// a move per record word on top of the compare-exchange).  Every LDS address
+// is a function of (lane, register) only.
+template <int G>
+__device__ __forceinline__ uint32_t tslot(uint32_t l, uint32_t e) {
+  if constexpr (G == 0) return (l << 4) | e;
+  else if constexpr (G == 1) return ((l >> 4) << 8) | (e << 4) | (l & 15u);
+  else return (e << 8) | l;
+}
+
+// Stages of phase KK (merges of 2^KK slots) on register bits JB .. 0 of
+// layout G (slot bits 4G + JB .. 4G); a pair sorts ascending when bit KK of
+// its slots is 0, and every pair does in the last phase.
+template <int KK, int G, int JB, typename E>
+__device__ __forceinline__ void tile_reg_stages(E (&v)[16], uint32_t l) {
+  if constexpr (JB >= 0) {
+    constexpr uint32_t hb = 1u << JB;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      if (e & hb) continue;
+      const bool asc = KK == 12 || ((tslot<G>(l, e) >> KK) & 1u) == 0u;
+      cx_reg(v[e], v[e | hb], asc);
+    }
+    tile_reg_stages<KK, G, JB - 1>(v, l);
+  }
+}
+
+// Padded LDS slot tslot + tslot/16 of register e, as a lane base plus e times
+// a constant: P 17 l + e, R 272 (l/16) + l mod 16 + 17 e, Q l + l/16 + 272 e.
+template <int G>
+__device__ __forceinline__ uint32_t tpad_base(uint32_t l) {
+  if constexpr (G == 0) return 17u * l;
+  else if constexpr (G == 1) return 272u * (l >> 4) + (l & 15u);
+  else return l + (l >> 4);
+}
+template <int G>
+constexpr uint32_t tpad_step() { return G == 0 ? 1u : G == 1 ? 17u : 272u; }
+
+template <int G, typename E, typename T>
+__device__ __forceinline__ void tile_to_lds(const E (&v)[16], const LdsR<T>& lds, uint32_t l) {
+  const uint32_t b = tpad_base<G>(l);
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) lds.st(b + e * tpad_step<G>(), v[e]);
+}
+template <int G, typename E, typename T>
+__device__ __forceinline__ void tile_from_lds(E (&v)[16], const LdsR<T>& lds, uint32_t l) {
+  const uint32_t b = tpad_base<G>(l);
+#pragma unroll
+  for (uint32_t e = 0; e < 16; ++e) v[e] = lds.ld(b + e * tpad_step<G>());
+}
+
+// Phases KK .. 12 of the bitonic sort of a 4096-record tile; v holds layout P
+// on entry and exit.  A lane writes back exactly the slots it read in the same
+// layout, so only a change of layout needs a barrier.
+template <int KK, typename E, typename T>
+__device__ __forceinline__ void tile_phase(E (&v)[16], const LdsR<T>& lds, uint32_t l) {
+  if constexpr (KK <= 12) {
+    if constexpr (KK >= 5) {
+      tile_to_lds<0>(v, lds, l);
+      __syncthreads();
+      if constexpr (KK >= 9) {
+        tile_from_lds<2>(v, lds, l);
+        tile_reg_stages<KK, 2, KK - 9>(v, l);  // slot bits KK-1 .. 8
+        tile_to_lds<2>(v, lds, l);
+        __syncthreads();
+      }
+      tile_from_lds<1>(v, lds, l);
+      tile_reg_stages<KK, 1, (KK >= 9 ? 3 : KK - 5)>(v, l);  // slot bits min(KK-1, 7) .. 4
+      tile_to_lds<1>(v, lds, l);
+      __syncthreads();
+      tile_from_lds<0>(v, lds, l);
+    }
+    tile_reg_stages<KK, 0, (KK >= 4 ? 3 : KK - 1)>(v, l);  // slot bits min(KK-1, 3) .. 0
+    tile_phase<KK + 1>(v, lds, l);
+  }
+}
+
+// Sort one tile of 2^TLOG records of buf in place (record order; slots past n
+// sort last as the maximal record): 4096-record tiles with the three-layout
+// network above, smaller ones with the register network of the per-bin
+// finish.
 template <int R, uint32_t TLOG>
 __device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t tile, void* smp) {
   using T = typename RecOf<R>::T;
@@ -94,15 +178,47 @@ __device__ __forceinline__ void tile_sort_one(void* buf, uint64_t n, uint64_t ti
   T* srec = reinterpret_cast<T*>(smem);
   T* B = static_cast<T*>(buf);
   const uint32_t lq = threadIdx.x;
-  const uint64_t base = (tile << TLOG) + 16u * lq;
   ElemR<T> v[16];
+  LdsR<T> lds{srec};
+  lds.tw = 1;
+  if constexpr (TLOG == 12) {
+    // Loads and stores in layout Q (register e of lane l is slot 256 e + l:
+    // a wave reads and writes 64 consecutive records per instruction), turned
+    // into layout P through LDS before the network and back after it.
+    const uint64_t t0 = tile << 12;
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint64_t gi = t0 + (e << 8) + lq;
+      if (gi < n) BOS_TR(1, 40, gi);
+      v[e] = ElemR<T>{gi < n ? B[gi] : max_rec<T>()};
+    }
+    tile_to_lds<2>(v, lds, lq);
+    __syncthreads();
+    tile_from_lds<0>(v, lds, lq);
+    tile_phase<1>(v, lds, lq);
+    tile_to_lds<0>(v, lds, lq);
+    __syncthreads();
+    tile_from_lds<2>(v, lds, lq);
+#pragma unroll
+    for (uint32_t e = 0; e < 16; ++e) {
+      const uint64_t gi = t0 + (e << 8) + lq;
+      if (gi < n) {
+        BOS_TR(1, 40, gi);
+        B[gi] = v[e].r;
+        if (smp && (gi & ((1ull << kSmpLog<R>) - 1)) == 0) {
+          BOS_TR(1, 41, gi >> kSmpLog<R>);
+          static_cast<T*>(smp)[gi >> kSmpLog<R>] = v[e].r;
+        }
+      }
+    }
+    return;
+  }
+  const uint64_t base = (tile << TLOG) + 16u * lq;
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e) {
     if (base + e < n) BOS_TR(1, 40, base + e);
     v[e] = ElemR<T>{base + e < n ? B[base + e] : max_rec<T>()};
   }
-  LdsR<T> lds{srec};
-  lds.tw = 1;
   bin_bitonic<TLOG>(v, lds, 0u, lq, true);
 #pragma unroll
   for (uint32_t e = 0; e < 16; ++e)
