@@ -1097,46 +1097,62 @@ __device__ __forceinline__ void bitonic_tile_one(const void* src_, void* dst_, u
   T* D = static_cast<T*>(dst_);
   const uint32_t tid = threadIdx.x, sub = tid / 256u, lq = tid % 256u;
   const uint64_t tbase = tile << TLOG;
-  const uint32_t p0 = sub * kSub + 16u * lq;
-  const LdsR<T> lds{s};
+  const uint32_t q0 = sub * kSub;  // the sub-tile's first slot
+  LdsR<T> lsub{s + sub * kSubPad};
   ElemR<T> v[16];
-  if constexpr (MERGE) {  // merge passes read whole tiles of the N slots
+  // loads and stores in layout Q of the sub-tile (register e of lane l is its
+  // slot 256 e + l: a wave reads and writes 64 consecutive records per
+  // instruction); the networks are those of the comparison sort's tile sort
+  // (register pairs only, layouts switched through the sub-tile's LDS region)
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{S[tbase + p0 + e]};
-  } else {
-    const uint64_t in_lane = n_src > tbase + p0 ? n_src - (tbase + p0) : 0;
-    const uint32_t cnt = in_lane < 16 ? uint32_t(in_lane) : 16u;
-#pragma unroll
-    for (uint32_t e = 0; e < 16; ++e) v[e] = ElemR<T>{e < cnt ? S[tbase + p0 + e] : max_rec<T>()};
+  for (uint32_t e = 0; e < 16; ++e) {
+    const uint64_t g = tbase + q0 + (e << 8) + lq;
+    v[e] = ElemR<T>{MERGE || g < n_src ? S[g] : max_rec<T>()};
   }
   if constexpr (!MERGE) {
-    bin_bitonic<12>(v, lds, sub * kSubPad, lq, true);
+    tile_to_lds<2>(v, lsub, lq);
+    __syncthreads();
+    tile_from_lds<0>(v, lsub, lq);
+    tile_phase<1>(v, lsub, lq);
     if constexpr (TLOG >= 13) {
       subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 1u, true);
-      bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+      tile_phase<12>(v, lsub, lq);
     }
     if constexpr (TLOG == 14) {
       subtile_cross<T, kSubPad>(v, s, sub, lq, 3u - sub, true);
       subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 1u, false);
-      bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+      tile_phase<12>(v, lsub, lq);
     }
+    __syncthreads();  // every lane's last reads of layout P are done
+    tile_to_lds<0>(v, lsub, lq);
+    __syncthreads();
+    tile_from_lds<2>(v, lsub, lq);
   } else {
+    // the cross-sub-tile strides pair the same (lane, register) of two
+    // sub-tiles, in any layout; then phase 12 from layout Q: slot bits 11-8
+    // in Q, 7-4 in R, 3-0 in P, and back to Q
     if constexpr (TLOG == 14) subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 2u, false);
     if constexpr (TLOG >= 13) subtile_cross<T, kSubPad>(v, s, sub, lq, sub ^ 1u, false);
-    bin_bitonic_merge<12>(v, lds, sub * kSubPad, lq, true);
+    tile_reg_stages<12, 2, 3>(v, lq);
+    tile_to_lds<2>(v, lsub, lq);
+    __syncthreads();
+    tile_from_lds<1>(v, lsub, lq);
+    tile_reg_stages<12, 1, 3>(v, lq);
+    tile_to_lds<1>(v, lsub, lq);
+    __syncthreads();
+    tile_from_lds<0>(v, lsub, lq);
+    tile_reg_stages<12, 0, 3>(v, lq);
+    __syncthreads();  // every lane's reads of layout R are done
+    tile_to_lds<0>(v, lsub, lq);
+    __syncthreads();
+    tile_from_lds<2>(v, lsub, lq);
   }
   const bool desc = (tbase & k2) != 0;  // descending: slot p goes to ts - 1 - p
-  const uint64_t o = desc ? tbase + ts - 16u - p0 : tbase + p0;
-  const uint64_t out_lane = n_dst > o ? n_dst - o : 0;
-  const uint32_t cnt = out_lane < 16 ? uint32_t(out_lane) : 16u;
-  if (!desc) {
 #pragma unroll
-    for (uint32_t e = 0; e < 16; ++e)
-      if (e < cnt) D[o + e] = v[e].r;
-  } else {
-#pragma unroll
-    for (uint32_t e = 0; e < 16; ++e)
-      if (e < cnt) D[o + e] = v[15u - e].r;
+  for (uint32_t e = 0; e < 16; ++e) {
+    const uint32_t p = q0 + (e << 8) + lq;
+    const uint64_t o = tbase + (desc ? ts - 1u - p : p);
+    if (o < n_dst) D[o] = v[e].r;
   }
 }
 
