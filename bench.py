@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--data-seed", type=int, default=42)
     ap.add_argument("--bitonic-steps", type=int, default=2, help="0 skips the bitonic baseline")
-    ap.add_argument("--cpu-log2n", type=int, default=24, help="oracle sample size; 0 skips it")
+    ap.add_argument("--cpu-log2n", type=int, default=25, help="oracle sample size; 0 skips it")
     ap.add_argument("--mode", default="sort", choices=("sort", "orp", "copy"),
                     help="copy: a plain device copy of the input (counter calibration)")
     ap.add_argument("--batched-count", type=int, default=4096,
