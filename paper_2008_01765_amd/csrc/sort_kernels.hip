@@ -854,14 +854,17 @@ __device__ __forceinline__ void merge_items_lds(const T* s, uint32_t xa, uint32_
   }
   uint32_t ia = l, ib = dd - l;
   T va = at(xa + (ia < na ? ia : 0)), vb = at(xb + (ib < nb ? ib : 0));
+  // every step without branches: the conditions combine as bits and both
+  // candidate slots are formed before one of them is read
 #pragma unroll
   for (uint32_t k = 0; k < ITEMS; ++k) {
-    const bool take_a = ia < na && (ib >= nb || !rec_less(vb, va));
+    const bool take_a = (ia < na) & ((ib >= nb) | !rec_less(vb, va));
     out[k] = sel(take_a, va, vb);
-    ia += take_a ? 1u : 0u;
-    ib += take_a ? 0u : 1u;
+    ia += uint32_t(take_a);
+    ib += uint32_t(!take_a);
     if (k + 1 < ITEMS) {
-      const T nv = at(take_a ? xa + (ia < na ? ia : 0) : xb + (ib < nb ? ib : 0));
+      const uint32_t qa = xa + (ia < na ? ia : 0u), qb = xb + (ib < nb ? ib : 0u);
+      const T nv = at(take_a ? qa : qb);
       va = sel(take_a, nv, va);
       vb = sel(take_a, vb, nv);
     }
